@@ -1,0 +1,59 @@
+"""The seeded generators produce the workload shapes they promise (sizes,
+widths, depth, activity), deterministically."""
+import numpy as np
+
+from oracle import oracle as O
+from paper_2403_04714_amd import netgen as g
+
+
+def comb_depth(nl):
+    d = np.zeros(nl.n_nodes, np.int64)
+    for n in range(nl.n_nodes):                    # builders emit operands first
+        if nl.op[n] >= g.OPS["MEMRD"]:
+            d[n] = 1 + max(d[a] for a in nl.arg[n] if a != g.NONE)
+    return d
+
+
+def test_tiny_shape():
+    nl = g.gen_tiny(0)
+    assert nl.n_regs == 64 and nl.n_inputs == 8
+    assert nl.n_comb_ops() == 1000
+    assert 1 <= nl.reg_width.min() and nl.reg_width.max() <= 32
+    assert comb_depth(nl).max() <= 16
+    ar = (nl.arg != g.NONE).sum(axis=1)[nl.op >= g.OPS["AND"]]
+    assert set(np.unique(ar)) <= {1, 2, 3}
+
+
+def test_deterministic():
+    a, b = g.gen_tiny(5), g.gen_tiny(5)
+    for f in ("op", "width", "arg", "imm", "reg_init", "reg_next"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))
+
+
+def test_core_shape_and_activity():
+    nl = g.gen_core(1)
+    s = nl.summary()
+    assert s["regs"] == 20000 and s["regs_1b"] == 14000
+    assert 180_000 <= s["comb_ops"] <= 220_000
+    assert s["mems"] == 2 and s["wports"] == 2
+    assert 30 <= comb_depth(nl).max() <= 48
+    # activity: most registers toggle within the first cycles
+    sim = O.Sim(nl, seed=g.STIM_SEED_BASE)
+    r0 = sim.regs().copy()
+    changed = np.zeros(nl.n_regs, bool)
+    for _ in range(20):
+        sim.step(1)
+        r = sim.regs()
+        changed |= r != r0
+        r0 = r.copy()
+    assert changed.mean() > 0.3, changed.mean()
+
+
+def test_soc_replicates_core():
+    core = g.gen_core(1, g.CoreParams(n_regs_1=350, n_regs_32=75, n_regs_64=75,
+                                      target_ops=5000, mem_depth=64, reg_locality=32))
+    soc = g.gen_soc(2, 2, core, mesh_seed=2)
+    assert soc.n_regs == 4 * core.n_regs + 4 * 4 * 3
+    assert soc.n_mems == 4 * core.n_mems and soc.n_inputs == 4 * core.n_inputs
+    sim = O.Sim(soc, seed=1)      # valid: acyclic, indices in range
+    sim.step(20)
