@@ -1,0 +1,234 @@
+/*
+ * fibersim.h -- C-ABI of libfibersim, per-cycle bulk-synchronous simulation
+ * of a fiber-partitioned RTL netlist on one MI355X (gfx950).
+ *
+ * The method is Parendi's (Emami, Bourgeat, Larus, ASPLOS 2025):
+ *   - Sec. 3.2: the design is a data-dependence graph in which every register
+ *     is split into a read-only current value and a write-only next value;
+ *     a fiber is the set of nodes that produces one register's next value;
+ *     processes are sets of fibers, shared nodes are duplicated, and one
+ *     simulated cycle is "compute, barrier, exchange, barrier";
+ *   - Sec. 5.1: fibers are found by a reverse crawl from every sink and merged
+ *     into processes by a four-stage partitioner (large-array pre-merge,
+ *     multi-chip cut, conservative bottom-up merge, forced merge);
+ *   - Sec. 5.3: compilation fails on combinational loops and on designs that
+ *     exceed the target's capacity; the test driver runs on the device.
+ *
+ * Conventions for every call:
+ *   - return value 0 (FSIM_OK) or a negative FSIM_E_* status; nothing throws
+ *     across the ABI and nothing aborts.  fsim_last_error() describes the last
+ *     failure of the calling thread.
+ *   - Host pointers are borrowed for the duration of the call and copied.
+ *     Device pointers (fsim_sim_create's workspace, fsim_enable_digest's
+ *     buffer) are borrowed for the lifetime of the object; the caller keeps
+ *     them alive (e.g. as torch tensors) and frees them afterwards.
+ *   - Handles are opaque; the caller destroys what it creates.  A design is
+ *     reference counted: sims and servers keep it alive after
+ *     fsim_design_free().
+ *   - Values cross the ABI as one uint64_t per register / output / memory
+ *     word, masked to the declared width.
+ *   - A device error poisons the sim: later calls on it return FSIM_E_STATE.
+ *   - One sim must not be used by two host threads at once; a server is
+ *     thread-safe.
+ */
+#ifndef FIBERSIM_H
+#define FIBERSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ----------------------------------------------------------------- status */
+#define FSIM_OK              0
+#define FSIM_E_ARG          -1   /* bad argument, call-order or size error    */
+#define FSIM_E_NETLIST      -2   /* bad opcode arity, width 0, index range    */
+#define FSIM_E_COMB_LOOP    -3   /* combinational cycle (Sec. 5.3)            */
+#define FSIM_E_UNSUPPORTED  -4   /* width > 64, unknown opcode                */
+#define FSIM_E_CAPACITY     -5   /* LDS / HBM budget exceeded (Sec. 5.3)      */
+#define FSIM_E_DEVICE       -6   /* HIP runtime or kernel error               */
+#define FSIM_E_STATE        -7   /* poisoned sim, or object in the wrong state*/
+#define FSIM_E_BUSY         -8   /* server queue full                         */
+
+/* Text of the calling thread's last failure; valid until its next call. */
+const char* fsim_last_error(void);
+
+/* --------------------------------------------------------------- netlist
+ * Node opcodes (a file format: the numbering is fixed).  Operands are the
+ * values of other nodes, zero-extended to 64 bits; every result is masked to
+ * the node width w (1..64).  Shift amounts >= 64 give 0.  EQ/LT are unsigned
+ * and give 0 or 1.  MUX(sel, a, b) = sel != 0 ? a : b.  Leaves read the
+ * current register value (REG, imm = register), an input port (INPUT,
+ * imm = port), a constant (CONST, imm = value); MEMRD (imm = memory,
+ * arg0 = address) reads the memory as it was at the start of the cycle, at
+ * address mod depth.  */
+enum {
+  FSIM_OP_CONST = 0, FSIM_OP_INPUT = 1, FSIM_OP_REG = 2, FSIM_OP_MEMRD = 3,
+  FSIM_OP_AND = 4, FSIM_OP_OR = 5, FSIM_OP_XOR = 6, FSIM_OP_NOT = 7,
+  FSIM_OP_ADD = 8, FSIM_OP_SUB = 9, FSIM_OP_MUX = 10, FSIM_OP_SHL = 11,
+  FSIM_OP_SHR = 12, FSIM_OP_EQ = 13, FSIM_OP_LT = 14, FSIM_OP_MUL = 15
+};
+#define FSIM_NONE 0xFFFFFFFFu
+
+/* A flattened word-level netlist (the data-dependence graph of Sec. 3.2),
+ * structure of arrays, all host memory, borrowed for the call.
+ *   arg:       [n_nodes][3] node indices, FSIM_NONE where unused.
+ *   reg_next:  node whose value becomes the register's next value.
+ *   mem_init:  all memories back to back (sum of depths words), or NULL = 0.
+ *   write ports (wp_*): node indices of enable, address and data; ports are
+ *   applied at the end of the cycle in index order (the highest port wins). */
+typedef struct fsim_netlist {
+  uint32_t n_nodes;
+  const uint8_t* op;
+  const uint8_t* width;
+  const uint32_t* arg;
+  const uint64_t* imm;
+  uint32_t n_regs;
+  const uint8_t* reg_width;
+  const uint64_t* reg_init;
+  const uint32_t* reg_next;
+  uint32_t n_inputs;
+  const uint8_t* in_width;
+  uint32_t n_outputs;
+  const uint32_t* out_node;
+  uint32_t n_mems;
+  const uint32_t* mem_depth;
+  const uint8_t* mem_width;
+  const uint64_t* mem_init;
+  uint32_t n_wports;
+  const uint32_t* wp_mem;
+  const uint32_t* wp_en;
+  const uint32_t* wp_addr;
+  const uint32_t* wp_data;
+} fsim_netlist;
+
+/* Sinks are numbered registers 0..R-1, then write ports, then outputs.
+ * sink_to_process[s] names the process (Sec. 3.2 "process", Sec. 5.1) that
+ * produces sink s.  Every sink whose cone reads memory m must share a process
+ * with m's write ports (the memory commit stays inside one process). */
+typedef struct fsim_partition {
+  uint32_t n_sinks;
+  const uint32_t* sink_to_process;
+} fsim_partition;
+
+/* Packing policy when no partition is given. */
+#define FSIM_PACK_SLB      0   /* Sec. 5.1 stages 1, 3, 4: bottom-up merge   */
+#define FSIM_PACK_FIBERS   1   /* one fiber per process (memory groups kept) */
+#define FSIM_PACK_SINGLE   2   /* one process holding every fiber            */
+
+typedef struct fsim_compile_opts {
+  uint32_t pack;              /* FSIM_PACK_*                                 */
+  uint32_t target_processes;  /* SLB target process count; 0 = device CUs    */
+  uint32_t max_process_nodes; /* capacity of one process (Sec. 5.1 memory
+                                 limit); 0 = derived from the LDS size       */
+} fsim_compile_opts;
+
+typedef struct fsim_design_info {
+  uint32_t n_nodes, n_live_ops, n_regs, n_sinks, n_processes, max_depth;
+  uint64_t sum_fiber_ops;     /* sum over sinks of combinational cone size  */
+  uint64_t sum_process_ops;   /* sum over processes of union cone size      */
+  double dup_fiber;           /* D_f = sum_fiber_ops / n_live_ops           */
+  double dup_process;         /* D_p = sum_process_ops / n_live_ops         */
+  uint64_t max_fiber_cost;    /* straggler bound of Sec. 4.3                */
+  uint64_t max_process_cost;  /* t_comp proxy: costliest process            */
+  uint64_t program_bytes;     /* encoded plain-form program                 */
+  uint32_t max_process_levels;
+  uint32_t max_process_nodes;
+  double compile_seconds;
+} fsim_design_info;
+
+typedef struct fsim_ctx fsim_ctx;
+typedef struct fsim_design fsim_design;
+typedef struct fsim_sim fsim_sim;
+
+/* Context on one HIP device.  hip_stream is a borrowed hipStream_t (e.g.
+ * torch.cuda.current_stream().cuda_stream); NULL = the null stream. */
+int fsim_ctx_create(int hip_device, void* hip_stream, fsim_ctx** out);
+void fsim_ctx_destroy(fsim_ctx* ctx);
+/* Device facts used by the autotuner: CUs, LDS bytes per workgroup,
+ * co-resident workgroups of the plain kernel at 256 threads. */
+int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_bytes,
+                    uint32_t* max_coresident_wgs);
+
+/* Validate (Sec. 5.3: comb loops rejected), extract fibers by reverse crawl
+ * (Sec. 5.1), pack them into processes (Sec. 5.1, or the given partition),
+ * levelize and encode, and upload the program.  partition and opts may be
+ * NULL. */
+int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl,
+                     const fsim_partition* partition,
+                     const fsim_compile_opts* opts, fsim_design** out);
+int fsim_design_info_get(const fsim_design* d, fsim_design_info* out);
+/* The process of every sink (n_sinks entries) and each process's node list
+ * (CSR: proc_off[n_processes + 1], proc_nodes[proc_off[n_processes]]), as
+ * compiled.  Any pointer may be NULL to skip it. */
+int fsim_design_partition(const fsim_design* d, uint32_t* sink_to_process,
+                          uint32_t* proc_off, uint32_t* proc_nodes);
+void fsim_design_free(fsim_design* d);
+
+/* ------------------------------------------------------------ simulation
+ * A sim holds n_instances independent copies of the design state.  One
+ * instance runs the plain form (lanes of a workgroup evaluate one process's
+ * level in parallel); more than one runs the batched form (one lane per
+ * instance, Sec. 6.4 "many short tests" / prior art on batch stimulus). */
+
+#define FSIM_LAUNCH_AUTO        0
+#define FSIM_LAUNCH_PERSISTENT  1  /* one cooperative launch, grid barrier per cycle */
+#define FSIM_LAUNCH_PER_CYCLE   2  /* one launch per cycle (kernel boundary = barrier) */
+#define FSIM_LAUNCH_GRAPH       3  /* per-cycle launches captured in a hipGraph */
+
+typedef struct fsim_sim_opts {
+  uint32_t launch;          /* FSIM_LAUNCH_*                                */
+  uint32_t wg_threads;      /* plain form: threads per workgroup, 0 = auto  */
+  uint32_t grid;            /* workgroups of the persistent kernel, 0 = auto*/
+  uint32_t graph_cycles;    /* cycles per captured graph (GRAPH mode)       */
+} fsim_sim_opts;
+
+/* Device bytes a sim needs for n_instances (state x2, memories, outputs,
+ * stimulus keys, scratch); what fsim_sim_create's workspace must hold. */
+int fsim_sim_footprint(const fsim_design* d, uint32_t n_instances, size_t* device_bytes);
+
+/* workspace: caller-owned device memory of at least fsim_sim_footprint()
+ * bytes, 256-byte aligned (e.g. a torch uint8 tensor), or NULL to let the
+ * library allocate.  opts may be NULL. */
+int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* workspace,
+                    size_t workspace_bytes, const fsim_sim_opts* opts, fsim_sim** out);
+void fsim_sim_destroy(fsim_sim* s);
+
+/* Device-side stimulus (Sec. 5.3: the test driver runs on the device):
+ * instance i, port p, cycle t gets mask(w_p, H(H(H(seed_base + i) ^ p) ^ t)),
+ * H = SplitMix64's output function.  This is the default mode. */
+int fsim_set_stimulus_seed(fsim_sim* s, uint64_t seed_base);
+/* Explicit inputs for cycles [first_cycle, first_cycle + n_cycles):
+ * vals[n_cycles][n_inputs][n_instances]; stepping outside that window
+ * fails with FSIM_E_ARG. */
+int fsim_set_inputs(fsim_sim* s, uint64_t first_cycle, uint32_t n_cycles,
+                    const uint64_t* vals);
+
+/* Advance n_cycles, asynchronously on the context's stream. */
+int fsim_step(fsim_sim* s, uint64_t n_cycles);
+int fsim_sync(fsim_sim* s);
+uint64_t fsim_cycle(const fsim_sim* s);
+
+/* State access (each synchronises).  out/in hold n_regs, n_outputs or the
+ * memory's depth values; outputs are those of the last simulated cycle. */
+int fsim_read_regs(fsim_sim* s, uint32_t inst, uint64_t* out);
+int fsim_write_regs(fsim_sim* s, uint32_t inst, const uint64_t* in);
+int fsim_read_outputs(fsim_sim* s, uint32_t inst, uint64_t* out);
+int fsim_read_mem(fsim_sim* s, uint32_t inst, uint32_t mem, uint64_t* out);
+int fsim_write_mem(fsim_sim* s, uint32_t inst, uint32_t mem, const uint64_t* in);
+/* Set the cycle counter (restoring a checkpoint: regs + mems + cycle). */
+int fsim_set_cycle(fsim_sim* s, uint64_t cycle);
+
+/* Verification digests: after every simulated cycle the device adds, per
+ * instance, D = sum_r H(r ^ H(R[r])) mod 2^64 into
+ * dev_out[(cycle - first) * n_instances + inst], where first is the cycle
+ * at which digests were enabled.  dev_out is caller device memory of
+ * max_cycles * n_instances uint64, zeroed by this call; NULL disables. */
+int fsim_enable_digest(fsim_sim* s, uint64_t* dev_out, uint64_t max_cycles);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FIBERSIM_H */

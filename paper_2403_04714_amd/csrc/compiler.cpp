@@ -1,0 +1,616 @@
+// compiler.cpp -- host-side preparation of a design (once per design).
+//
+//   copy_and_validate   operator/width/index checks; Kahn topological order;
+//                       combinational loops rejected (Parendi Sec. 5.3);
+//                       ASAP levels.
+//   partition_design    fibers = reverse crawl from every sink (Sec. 5.1);
+//                       stage 1: co-locate every fiber that touches a memory
+//                       with that memory's write ports (adapted from the
+//                       large-array pre-merge of Sec. 5.1); stages 3-4: the
+//                       bottom-up submodular load-balancing merge of Sec. 5.1
+//                       with the cost tau(P) = sum of the costs of the union
+//                       of the cones (Sec. 4.3).
+//   encode_plain        per process: constant prologue, leaf-load level,
+//                       operator levels (sorted by opcode so that wavefronts
+//                       run one operator at a time), store level, write-port
+//                       commit.
+//   encode_batched      per process: one sequential stream in depth-first
+//                       order with liveness-based slot reuse per class.
+#include "compiler.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <set>
+#include <unordered_set>
+
+namespace fsim {
+
+static inline int arity(uint8_t op) {
+  switch (op) {
+    case FSIM_OP_CONST: case FSIM_OP_INPUT: case FSIM_OP_REG: return 0;
+    case FSIM_OP_MEMRD: case FSIM_OP_NOT: return 1;
+    case FSIM_OP_MUX: return 3;
+    default: return 2;
+  }
+}
+
+static std::string fmt(const char* f, unsigned long long a = 0, unsigned long long b = 0) {
+  char buf[256];
+  snprintf(buf, sizeof buf, f, a, b);
+  return buf;
+}
+
+Status copy_and_validate(const fsim_netlist* nl, Design& d) {
+  if (!nl) return Status::err(FSIM_E_ARG, "netlist is NULL");
+  auto need = [&](const void* p, uint64_t n, const char* what) -> Status {
+    if (n && !p) return Status::err(FSIM_E_ARG, std::string(what) + " is NULL");
+    return {};
+  };
+  Status s;
+  if (!(s = need(nl->op, nl->n_nodes, "op")).ok()) return s;
+  if (!(s = need(nl->width, nl->n_nodes, "width")).ok()) return s;
+  if (!(s = need(nl->arg, nl->n_nodes, "arg")).ok()) return s;
+  if (!(s = need(nl->imm, nl->n_nodes, "imm")).ok()) return s;
+  if (!(s = need(nl->reg_width, nl->n_regs, "reg_width")).ok()) return s;
+  if (!(s = need(nl->reg_init, nl->n_regs, "reg_init")).ok()) return s;
+  if (!(s = need(nl->reg_next, nl->n_regs, "reg_next")).ok()) return s;
+  if (!(s = need(nl->in_width, nl->n_inputs, "in_width")).ok()) return s;
+  if (!(s = need(nl->out_node, nl->n_outputs, "out_node")).ok()) return s;
+  if (!(s = need(nl->mem_depth, nl->n_mems, "mem_depth")).ok()) return s;
+  if (!(s = need(nl->mem_width, nl->n_mems, "mem_width")).ok()) return s;
+  for (auto* p : {nl->wp_mem, nl->wp_en, nl->wp_addr, nl->wp_data})
+    if (!(s = need(p, nl->n_wports, "write port array")).ok()) return s;
+  if (nl->n_nodes >= 0x7FFFFFFFu) return Status::err(FSIM_E_CAPACITY, "too many nodes");
+
+  d.N = nl->n_nodes; d.R = nl->n_regs; d.I = nl->n_inputs; d.O = nl->n_outputs;
+  d.M = nl->n_mems; d.W = nl->n_wports;
+  d.op.assign(nl->op, nl->op + d.N);
+  d.width.assign(nl->width, nl->width + d.N);
+  d.arg.assign(nl->arg, nl->arg + 3ull * d.N);
+  d.imm.assign(nl->imm, nl->imm + d.N);
+  d.reg_width.assign(nl->reg_width, nl->reg_width + d.R);
+  d.reg_init.assign(nl->reg_init, nl->reg_init + d.R);
+  d.reg_next.assign(nl->reg_next, nl->reg_next + d.R);
+  d.in_width.assign(nl->in_width, nl->in_width + d.I);
+  d.out_node.assign(nl->out_node, nl->out_node + d.O);
+  d.mem_depth.assign(nl->mem_depth, nl->mem_depth + d.M);
+  d.mem_width.assign(nl->mem_width, nl->mem_width + d.M);
+  d.wp_mem.assign(nl->wp_mem, nl->wp_mem + d.W);
+  d.wp_en.assign(nl->wp_en, nl->wp_en + d.W);
+  d.wp_addr.assign(nl->wp_addr, nl->wp_addr + d.W);
+  d.wp_data.assign(nl->wp_data, nl->wp_data + d.W);
+
+  for (uint32_t n = 0; n < d.N; ++n) {
+    uint8_t op = d.op[n], w = d.width[n];
+    if (op > FSIM_OP_MUL) return Status::err(FSIM_E_UNSUPPORTED, fmt("node %llu: unknown opcode %llu", n, op));
+    if (w == 0) return Status::err(FSIM_E_NETLIST, fmt("node %llu: width 0", n));
+    if (w > 64) return Status::err(FSIM_E_UNSUPPORTED, fmt("node %llu: width %llu > 64", n, w));
+    for (int k = 0; k < arity(op); ++k)
+      if (d.arg[3ull * n + k] >= d.N)
+        return Status::err(FSIM_E_NETLIST, fmt("node %llu: operand %llu out of range", n, k));
+    if (op == FSIM_OP_INPUT && d.imm[n] >= d.I) return Status::err(FSIM_E_NETLIST, fmt("node %llu: bad input port", n));
+    if (op == FSIM_OP_REG && d.imm[n] >= d.R) return Status::err(FSIM_E_NETLIST, fmt("node %llu: bad register", n));
+    if (op == FSIM_OP_MEMRD && d.imm[n] >= d.M) return Status::err(FSIM_E_NETLIST, fmt("node %llu: bad memory", n));
+  }
+  for (uint32_t r = 0; r < d.R; ++r) {
+    if (d.reg_width[r] == 0) return Status::err(FSIM_E_NETLIST, fmt("register %llu: width 0", r));
+    if (d.reg_width[r] > 64) return Status::err(FSIM_E_UNSUPPORTED, fmt("register %llu: width > 64", r));
+    if (d.reg_next[r] >= d.N) return Status::err(FSIM_E_NETLIST, fmt("register %llu: next node out of range", r));
+  }
+  for (uint32_t p = 0; p < d.I; ++p)
+    if (d.in_width[p] == 0 || d.in_width[p] > 64)
+      return Status::err(d.in_width[p] ? FSIM_E_UNSUPPORTED : FSIM_E_NETLIST, fmt("input %llu: bad width", p));
+  for (uint32_t o = 0; o < d.O; ++o)
+    if (d.out_node[o] >= d.N) return Status::err(FSIM_E_NETLIST, fmt("output %llu: node out of range", o));
+  d.mem_off.assign(d.M + 1, 0);
+  for (uint32_t m = 0; m < d.M; ++m) {
+    if (d.mem_depth[m] == 0) return Status::err(FSIM_E_NETLIST, fmt("memory %llu: depth 0", m));
+    if (d.mem_width[m] == 0 || d.mem_width[m] > 64)
+      return Status::err(d.mem_width[m] ? FSIM_E_UNSUPPORTED : FSIM_E_NETLIST, fmt("memory %llu: bad width", m));
+    d.mem_off[m + 1] = d.mem_off[m] + d.mem_depth[m];
+  }
+  d.mem_init.assign(d.mem_off[d.M], 0);
+  if (nl->mem_init)
+    for (uint32_t m = 0; m < d.M; ++m) {
+      uint64_t msk = ~0ull >> (64 - d.mem_width[m]);
+      for (uint64_t a = d.mem_off[m]; a < d.mem_off[m + 1]; ++a) d.mem_init[a] = nl->mem_init[a] & msk;
+    }
+  for (uint32_t k = 0; k < d.W; ++k)
+    if (d.wp_mem[k] >= d.M || d.wp_en[k] >= d.N || d.wp_addr[k] >= d.N || d.wp_data[k] >= d.N)
+      return Status::err(FSIM_E_NETLIST, fmt("write port %llu: index out of range", k));
+  for (uint32_t r = 0; r < d.R; ++r) d.reg_init[r] &= ~0ull >> (64 - d.reg_width[r]);
+
+  // Kahn's algorithm; ASAP level = 1 + max operand level, leaves at 0.
+  std::vector<uint32_t> indeg(d.N, 0), ucount(d.N + 1, 0);
+  for (uint32_t n = 0; n < d.N; ++n)
+    for (int k = 0; k < arity(d.op[n]); ++k) { ucount[d.arg[3ull * n + k] + 1]++; indeg[n]++; }
+  for (uint32_t n = 0; n < d.N; ++n) ucount[n + 1] += ucount[n];
+  std::vector<uint32_t> users(ucount[d.N]), fill(ucount.begin(), ucount.end() - 1);
+  for (uint32_t n = 0; n < d.N; ++n)
+    for (int k = 0; k < arity(d.op[n]); ++k) users[fill[d.arg[3ull * n + k]]++] = n;
+  d.level.assign(d.N, 0);
+  std::vector<uint32_t> q;
+  q.reserve(d.N);
+  for (uint32_t n = 0; n < d.N; ++n) if (!indeg[n]) q.push_back(n);
+  for (size_t h = 0; h < q.size(); ++h) {
+    uint32_t x = q[h];
+    for (uint32_t e = ucount[x]; e < ucount[x + 1]; ++e) {
+      uint32_t y = users[e];
+      d.level[y] = std::max(d.level[y], d.level[x] + 1);
+      if (--indeg[y] == 0) q.push_back(y);
+    }
+  }
+  if (q.size() != d.N) return Status::err(FSIM_E_COMB_LOOP, "combinational loop in the netlist");
+  d.cost.assign(d.N, 0);
+  for (uint32_t n = 0; n < d.N; ++n) {
+    uint8_t op = d.op[n];
+    if (op == FSIM_OP_CONST) d.cost[n] = 0;
+    else if (op == FSIM_OP_REG || op == FSIM_OP_INPUT) d.cost[n] = 1;
+    else d.cost[n] = d.width[n] > 32 ? 2 : 1;
+  }
+  return {};
+}
+
+// ------------------------------------------------------------- partition
+
+namespace {
+
+struct UF {
+  std::vector<uint32_t> p;
+  explicit UF(size_t n) : p(n) { std::iota(p.begin(), p.end(), 0u); }
+  uint32_t find(uint32_t x) {
+    while (p[x] != x) { p[x] = p[p[x]]; x = p[x]; }
+    return x;
+  }
+  void unite(uint32_t a, uint32_t b) {
+    a = find(a); b = find(b);
+    if (a != b) p[std::max(a, b)] = std::min(a, b);
+  }
+};
+
+uint32_t sink_roots(const Design& d, uint32_t s, uint32_t roots[3]) {
+  if (s < d.R) { roots[0] = d.reg_next[s]; return 1; }
+  if (s < d.R + d.W) {
+    uint32_t k = s - d.R;
+    roots[0] = d.wp_en[k]; roots[1] = d.wp_addr[k]; roots[2] = d.wp_data[k];
+    return 3;
+  }
+  roots[0] = d.out_node[s - d.R - d.W];
+  return 1;
+}
+
+uint64_t set_cost(const Design& d, const std::vector<uint32_t>& v) {
+  uint64_t c = 0;
+  for (uint32_t n : v) c += d.cost[n];
+  return c;
+}
+
+// cost and size of the union of two sorted node sets
+void union_stats(const Design& d, const std::vector<uint32_t>& a, const std::vector<uint32_t>& b,
+                 uint64_t& cost, uint64_t& size) {
+  size_t i = 0, j = 0;
+  cost = 0; size = 0;
+  while (i < a.size() || j < b.size()) {
+    uint32_t x;
+    if (j == b.size() || (i < a.size() && a[i] < b[j])) x = a[i++];
+    else if (i == a.size() || b[j] < a[i]) x = b[j++];
+    else { x = a[i]; ++i; ++j; }
+    cost += d.cost[x]; ++size;
+  }
+}
+
+std::vector<uint32_t> set_union(const std::vector<uint32_t>& a, const std::vector<uint32_t>& b) {
+  std::vector<uint32_t> out;
+  out.reserve(a.size() + b.size());
+  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(out));
+  return out;
+}
+
+
+// Bottom-up merge of Sec. 5.1 (stages 3 and 4) under a cost bound B: take the
+// cheapest process; merge it into the process it communicates with whose
+// union is cheapest, if that stays within B and within the node capacity;
+// otherwise into the costliest process that still fits under B (best fit);
+// otherwise skip it.  Stops when every process was considered or the target
+// count is reached.
+struct SlbResult {
+  uint32_t n_alive = 0;
+  std::vector<uint32_t> proc_of_sink;
+};
+
+SlbResult slb_merge(const Design& d, const std::vector<std::vector<uint32_t>>& nodes0,
+                    const std::vector<uint64_t>& cost0, const std::vector<std::vector<uint32_t>>& sinks0,
+                    const std::vector<std::vector<uint32_t>>& readers, uint64_t B, uint32_t target,
+                    uint64_t max_nodes) {
+  const uint32_t P0 = (uint32_t)nodes0.size();
+  std::vector<std::vector<uint32_t>> nodes(nodes0), sinks(sinks0);
+  std::vector<uint64_t> cost(cost0);
+  std::vector<uint32_t> owner_init(d.R, UINT32_MAX);
+  for (uint32_t p = 0; p < P0; ++p)
+    for (uint32_t s : sinks0[p]) if (s < d.R) owner_init[s] = p;
+  UF puf(P0);
+  std::vector<uint8_t> alive(P0, 1), done(P0, 0);
+  std::multiset<std::pair<uint64_t, uint32_t>> by_cost;
+  for (uint32_t p = 0; p < P0; ++p) by_cost.emplace(cost[p], p);
+  uint32_t n_alive = P0;
+  const size_t K = P0 > 200000 ? 4 : 8;
+  std::vector<uint32_t> cand, mark(P0, UINT32_MAX);
+  uint32_t iter = 0;
+  // processes not yet considered, cheapest first
+  std::set<std::pair<uint64_t, uint32_t>> todo(by_cost.begin(), by_cost.end());
+  auto merge = [&](uint32_t p, uint32_t q) {
+    by_cost.erase(by_cost.find({cost[p], p}));
+    by_cost.erase(by_cost.find({cost[q], q}));
+    todo.erase({cost[q], q});
+    bool p_todo = todo.erase({cost[p], p}) > 0;
+    nodes[p] = set_union(nodes[p], nodes[q]);
+    std::vector<uint32_t>().swap(nodes[q]);
+    sinks[p].insert(sinks[p].end(), sinks[q].begin(), sinks[q].end());
+    std::vector<uint32_t>().swap(sinks[q]);
+    cost[p] = set_cost(d, nodes[p]);
+    alive[q] = 0;
+    puf.p[q] = p;
+    puf.p[p] = p;
+    by_cost.emplace(cost[p], p);
+    if (p_todo) todo.emplace(cost[p], p);
+    n_alive--;
+  };
+  while (n_alive > target && !todo.empty()) {
+    auto [c, p] = *todo.begin();
+    todo.erase(todo.begin());
+    ++iter;
+    cand.clear();
+    for (uint32_t x : nodes[p]) {
+      if (cand.size() >= K) break;
+      if (d.op[x] != FSIM_OP_REG) continue;
+      uint32_t o = owner_init[(uint32_t)d.imm[x]];
+      if (o == UINT32_MAX) continue;
+      uint32_t q = puf.find(o);
+      if (q != p && alive[q] && mark[q] != iter) { mark[q] = iter; cand.push_back(q); }
+    }
+    for (uint32_t s : sinks[p]) {
+      if (cand.size() >= K || s >= d.R) break;
+      const auto& rd = readers[s];
+      for (size_t i = 0; i < rd.size() && i < 32 && cand.size() < K; ++i) {
+        uint32_t q = puf.find(rd[i]);
+        if (q != p && alive[q] && mark[q] != iter) { mark[q] = iter; cand.push_back(q); }
+      }
+    }
+    uint32_t best = UINT32_MAX;
+    uint64_t best_cost = UINT64_MAX;
+    for (uint32_t q : cand) {
+      uint64_t uc, us;
+      union_stats(d, nodes[p], nodes[q], uc, us);
+      if (us > max_nodes || uc > B) continue;
+      if (uc < best_cost) { best_cost = uc; best = q; }
+    }
+    if (best == UINT32_MAX && cost[p] <= B) {
+      // best fit: the costliest process q with cost(q) <= B - cost(p)
+      auto it = by_cost.upper_bound({B - cost[p], UINT32_MAX});
+      int tries = 0;
+      while (it != by_cost.begin() && tries < 4) {
+        --it;
+        uint32_t q = it->second;
+        if (q == p) continue;
+        ++tries;
+        uint64_t uc, us;
+        union_stats(d, nodes[p], nodes[q], uc, us);
+        if (us <= max_nodes && uc <= B) { best = q; break; }
+      }
+    }
+    if (best != UINT32_MAX) {
+      merge(best, p);           // p joins best; best stays where it was in the order
+      if (alive[best] && !done[best]) {
+        // the grown process may still take more work: consider it again
+        todo.emplace(cost[best], best);
+      }
+    } else {
+      done[p] = 1;
+    }
+  }
+  SlbResult r;
+  r.n_alive = 0;
+  r.proc_of_sink.assign(d.n_sinks(), 0);
+  for (uint32_t p = 0; p < P0; ++p)
+    if (alive[p]) { for (uint32_t s : sinks[p]) r.proc_of_sink[s] = r.n_alive; r.n_alive++; }
+  return r;
+}
+
+}  // namespace
+
+Status partition_design(Design& d, const fsim_partition* part, const fsim_compile_opts& opts,
+                        uint32_t default_target, uint32_t default_max_nodes) {
+  const uint32_t S = d.n_sinks();
+  // ---- fibers: reverse crawl from every sink (Sec. 5.1)
+  std::vector<uint64_t> cone_off(S + 1, 0);
+  std::vector<uint32_t> cone;             // sorted per sink
+  std::vector<uint32_t> stamp(d.N, UINT32_MAX), stack;
+  std::vector<uint8_t> live(d.N, 0);
+  std::vector<std::vector<uint32_t>> mem_readers(d.M);
+  d.sum_fiber_ops = 0; d.max_fiber_cost = 0; d.max_depth = 0;
+  for (uint32_t s = 0; s < S; ++s) {
+    uint32_t roots[3], nr = sink_roots(d, s, roots);
+    size_t start = cone.size();
+    for (uint32_t k = 0; k < nr; ++k)
+      if (stamp[roots[k]] != s) { stamp[roots[k]] = s; stack.push_back(roots[k]); }
+    while (!stack.empty()) {
+      uint32_t x = stack.back(); stack.pop_back();
+      cone.push_back(x);
+      for (int k = 0; k < arity(d.op[x]); ++k) {
+        uint32_t y = d.arg[3ull * x + k];
+        if (stamp[y] != s) { stamp[y] = s; stack.push_back(y); }
+      }
+    }
+    std::sort(cone.begin() + start, cone.end());
+    uint64_t c = 0, ops = 0;
+    for (size_t i = start; i < cone.size(); ++i) {
+      uint32_t x = cone[i];
+      c += d.cost[x];
+      live[x] = 1;
+      if (d.op[x] >= FSIM_OP_MEMRD) {
+        ops++;
+        d.max_depth = std::max(d.max_depth, d.level[x]);
+      }
+      if (d.op[x] == FSIM_OP_MEMRD) {
+        auto& v = mem_readers[d.imm[x]];
+        if (v.empty() || v.back() != s) v.push_back(s);
+      }
+    }
+    d.sum_fiber_ops += ops;
+    d.max_fiber_cost = std::max(d.max_fiber_cost, c);
+    cone_off[s + 1] = cone.size();
+  }
+  d.n_live_ops = 0;
+  for (uint32_t n = 0; n < d.N; ++n) if (live[n] && d.op[n] >= FSIM_OP_MEMRD) d.n_live_ops++;
+
+  // ---- stage 1: every sink that reads memory m shares a process with m's
+  // write ports, so the end-of-cycle commit never races a read elsewhere
+  UF uf(S);
+  std::vector<int64_t> mem_anchor(d.M, -1);
+  for (uint32_t k = 0; k < d.W; ++k) {
+    uint32_t m = d.wp_mem[k];
+    if (mem_anchor[m] < 0) mem_anchor[m] = d.R + k; else uf.unite((uint32_t)mem_anchor[m], d.R + k);
+  }
+  for (uint32_t m = 0; m < d.M; ++m) {
+    if (mem_anchor[m] < 0) continue;      // never written: read-only, no constraint
+    for (uint32_t s : mem_readers[m]) uf.unite((uint32_t)mem_anchor[m], s);
+  }
+
+  d.sink_proc.assign(S, 0);
+  if (part) {
+    if (part->n_sinks != S || (S && !part->sink_to_process))
+      return Status::err(FSIM_E_ARG, "partition: n_sinks does not match the netlist");
+    // compact the caller's ids, in first-appearance order
+    std::vector<uint32_t> remap;
+    std::vector<uint32_t> ids(part->sink_to_process, part->sink_to_process + S);
+    uint32_t mx = 0;
+    for (uint32_t x : ids) mx = std::max(mx, x);
+    if (S && mx > 16u * S) return Status::err(FSIM_E_ARG, "partition: process id out of range");
+    remap.assign(S ? mx + 1 : 1, UINT32_MAX);
+    uint32_t P = 0;
+    for (uint32_t s = 0; s < S; ++s) {
+      if (remap[ids[s]] == UINT32_MAX) remap[ids[s]] = P++;
+      d.sink_proc[s] = remap[ids[s]];
+    }
+    for (uint32_t s = 0; s < S; ++s)
+      if (d.sink_proc[uf.find(s)] != d.sink_proc[s])
+        return Status::err(FSIM_E_ARG,
+                           fmt("partition: sink %llu reads or writes a memory whose other ports are in another process", s));
+    d.P = std::max(P, 1u);
+  } else if (opts.pack == FSIM_PACK_SINGLE) {
+    d.P = 1;
+  } else {
+    // initial processes: the stage-1 groups (one fiber each otherwise)
+    std::vector<uint32_t> root_id(S, UINT32_MAX);
+    uint32_t P0 = 0;
+    for (uint32_t s = 0; s < S; ++s) {
+      uint32_t r = uf.find(s);
+      if (root_id[r] == UINT32_MAX) root_id[r] = P0++;
+      d.sink_proc[s] = root_id[r];
+    }
+    d.P = std::max(P0, 1u);
+    uint32_t target = opts.target_processes ? opts.target_processes : default_target;
+    uint64_t max_nodes = opts.max_process_nodes ? opts.max_process_nodes : default_max_nodes;
+    if (opts.pack == FSIM_PACK_SLB && P0 > target) {
+      std::vector<std::vector<uint32_t>> nodes0(P0), sinks0(P0);
+      for (uint32_t s = 0; s < S; ++s) sinks0[d.sink_proc[s]].push_back(s);
+      std::vector<uint64_t> cost0(P0);
+      uint64_t straggler = 0, total = 0;
+      for (uint32_t p = 0; p < P0; ++p) {
+        std::vector<uint32_t> acc;
+        for (uint32_t s : sinks0[p]) {
+          std::vector<uint32_t> c(cone.begin() + cone_off[s], cone.begin() + cone_off[s + 1]);
+          acc = acc.empty() ? std::move(c) : set_union(acc, c);
+        }
+        nodes0[p] = std::move(acc);
+        cost0[p] = set_cost(d, nodes0[p]);
+        straggler = std::max(straggler, cost0[p]);
+        total += cost0[p];
+      }
+      std::vector<std::vector<uint32_t>> readers(d.R);
+      for (uint32_t p = 0; p < P0; ++p)
+        for (uint32_t x : nodes0[p])
+          if (d.op[x] == FSIM_OP_REG) readers[d.imm[x]].push_back(p);
+      SlbResult best;
+      // stage 3: conservative merge, the straggler bound stays put
+      SlbResult r3 = slb_merge(d, nodes0, cost0, sinks0, readers, straggler, target, max_nodes);
+      if (r3.n_alive <= target) {
+        best = std::move(r3);
+      } else {
+        // stage 4: the straggler may grow; the smallest bound under which the
+        // same merge reaches the target is found by bisection
+        uint64_t lo = std::max<uint64_t>(straggler, (total + target - 1) / target), hi = total;
+        SlbResult r = slb_merge(d, nodes0, cost0, sinks0, readers, hi, target, max_nodes);
+        if (r.n_alive > target)
+          return Status::err(FSIM_E_CAPACITY,
+              fmt("cannot pack the design into %llu processes of at most %llu nodes", target, max_nodes));
+        best = std::move(r);
+        for (int it = 0; it < 18 && lo < hi; ++it) {
+          uint64_t mid = lo + (hi - lo) / 2;
+          SlbResult t = slb_merge(d, nodes0, cost0, sinks0, readers, mid, target, max_nodes);
+          if (t.n_alive <= target) { hi = mid; best = std::move(t); }
+          else lo = mid + 1;
+          if (hi - lo <= std::max<uint64_t>(1, hi / 100)) break;
+        }
+      }
+      for (uint32_t s = 0; s < S; ++s) d.sink_proc[s] = best.proc_of_sink[s];
+      d.P = std::max(best.n_alive, 1u);
+    }
+  }
+
+  // ---- process node lists: union of member cones, ordered by level
+  d.psink_off.assign(d.P + 1, 0);
+  for (uint32_t s = 0; s < S; ++s) d.psink_off[d.sink_proc[s] + 1]++;
+  for (uint32_t p = 0; p < d.P; ++p) d.psink_off[p + 1] += d.psink_off[p];
+  d.psinks.assign(S, 0);
+  {
+    std::vector<uint32_t> f(d.psink_off.begin(), d.psink_off.end() - 1);
+    for (uint32_t s = 0; s < S; ++s) d.psinks[f[d.sink_proc[s]]++] = s;
+  }
+  d.proc_off.assign(d.P + 1, 0);
+  d.proc_nodes.clear();
+  std::fill(stamp.begin(), stamp.end(), UINT32_MAX);
+  d.sum_process_ops = 0; d.max_process_cost = 0; d.max_process_levels = 0; d.max_process_nodes = 0;
+  for (uint32_t p = 0; p < d.P; ++p) {
+    size_t start = d.proc_nodes.size();
+    for (uint32_t i = d.psink_off[p]; i < d.psink_off[p + 1]; ++i) {
+      uint32_t s = d.psinks[i];
+      for (uint64_t j = cone_off[s]; j < cone_off[s + 1]; ++j) {
+        uint32_t x = cone[j];
+        if (stamp[x] != p) { stamp[x] = p; d.proc_nodes.push_back(x); }
+      }
+    }
+    std::sort(d.proc_nodes.begin() + start, d.proc_nodes.end(), [&](uint32_t a, uint32_t b) {
+      if (d.level[a] != d.level[b]) return d.level[a] < d.level[b];
+      return a < b;
+    });
+    uint64_t c = 0, ops = 0;
+    uint32_t maxl = 0;
+    for (size_t i = start; i < d.proc_nodes.size(); ++i) {
+      uint32_t x = d.proc_nodes[i];
+      c += d.cost[x];
+      if (d.op[x] >= FSIM_OP_MEMRD) { ops++; maxl = std::max(maxl, d.level[x]); }
+    }
+    d.sum_process_ops += ops;
+    d.max_process_cost = std::max(d.max_process_cost, c);
+    d.max_process_levels = std::max(d.max_process_levels, maxl);
+    d.max_process_nodes = std::max<uint32_t>(d.max_process_nodes, (uint32_t)(d.proc_nodes.size() - start));
+    d.proc_off[p + 1] = (uint32_t)d.proc_nodes.size();
+  }
+  return {};
+}
+
+// --------------------------------------------------------- plain encoding
+
+static Instr make(uint8_t op, uint8_t w, uint16_t dst, uint16_t a, uint16_t b, uint16_t c, uint32_t aux) {
+  Instr in;
+  in.op = op; in.w = w; in.cls = 0; in.flags = 0;
+  in.dst = dst; in.a = a; in.b = b; in.c = c; in.aux = aux;
+  return in;
+}
+
+Status encode_plain(Design& d, uint32_t max_slots) {
+  d.plain_procs.assign(d.P, PlainProc{});
+  d.plain_levels.clear();
+  d.plain_instr.clear();
+  d.consts.clear();
+  d.plain_max_slots = 0;
+  d.plain_max_instr = 0;
+  std::vector<uint32_t> slot(d.N, UINT32_MAX);
+  for (uint32_t p = 0; p < d.P; ++p) {
+    const uint32_t lo = d.proc_off[p], hi = d.proc_off[p + 1];
+    const uint32_t n = hi - lo;
+    if (n > max_slots || n > 0xFFFE)
+      return Status::err(FSIM_E_CAPACITY,
+                         fmt("process %llu needs %llu value slots; use more processes", p, n));
+    for (uint32_t i = lo; i < hi; ++i) slot[d.proc_nodes[i]] = i - lo;
+    PlainProc& pp = d.plain_procs[p];
+    pp.n_slots = n;
+    const uint32_t base = (uint32_t)d.plain_instr.size();
+    // constant prologue
+    pp.const_off = base;
+    for (uint32_t i = lo; i < hi; ++i) {
+      uint32_t x = d.proc_nodes[i];
+      if (d.op[x] != FSIM_OP_CONST) continue;
+      uint64_t v = d.imm[x] & (~0ull >> (64 - d.width[x]));
+      d.plain_instr.push_back(make(I_LDCONST, d.width[x], (uint16_t)slot[x], 0xFFFF, 0xFFFF, 0xFFFF,
+                                   (uint32_t)d.consts.size()));
+      d.consts.push_back(v);
+    }
+    pp.n_consts = (uint32_t)d.plain_instr.size() - pp.const_off;
+    // levels: 0 = register and input loads; then one level per operator
+    // level present in the process (empty levels are dropped), sorted by
+    // opcode and width so wavefronts are uniform; then the store level
+    pp.lvl_off = (uint32_t)d.plain_levels.size();
+    std::vector<uint32_t> lvl_nodes;
+    uint32_t i = lo;
+    uint32_t n_lvls = 0;
+    while (i < hi) {
+      uint32_t L = d.level[d.proc_nodes[i]];
+      lvl_nodes.clear();
+      while (i < hi && d.level[d.proc_nodes[i]] == L) {
+        uint32_t x = d.proc_nodes[i++];
+        if (d.op[x] != FSIM_OP_CONST) lvl_nodes.push_back(x);
+      }
+      if (lvl_nodes.empty()) continue;
+      std::stable_sort(lvl_nodes.begin(), lvl_nodes.end(), [&](uint32_t a, uint32_t b) {
+        if (d.op[a] != d.op[b]) return d.op[a] < d.op[b];
+        return (d.width[a] > 32) < (d.width[b] > 32);
+      });
+      d.plain_levels.push_back((uint32_t)d.plain_instr.size());
+      n_lvls++;
+      for (uint32_t x : lvl_nodes) {
+        uint8_t op = d.op[x];
+        const uint32_t* a = &d.arg[3ull * x];
+        auto s = [&](int k) -> uint16_t { return k < arity(op) ? (uint16_t)slot[a[k]] : 0xFFFF; };
+        if (op == FSIM_OP_REG)
+          d.plain_instr.push_back(make(I_LDREG, d.width[x], (uint16_t)slot[x], 0xFFFF, 0xFFFF, 0xFFFF, (uint32_t)d.imm[x]));
+        else if (op == FSIM_OP_INPUT)
+          d.plain_instr.push_back(make(I_LDIN, d.width[x], (uint16_t)slot[x], 0xFFFF, 0xFFFF, 0xFFFF, (uint32_t)d.imm[x]));
+        else if (op == FSIM_OP_MEMRD)
+          d.plain_instr.push_back(make(I_MEMRD, d.width[x], (uint16_t)slot[x], s(0), 0xFFFF, 0xFFFF, (uint32_t)d.imm[x]));
+        else
+          d.plain_instr.push_back(make(op, d.width[x], (uint16_t)slot[x], s(0), s(1), s(2), 0));
+      }
+    }
+    // store level
+    d.plain_levels.push_back((uint32_t)d.plain_instr.size());
+    n_lvls++;
+    for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
+      uint32_t s = d.psinks[k];
+      if (s < d.R)
+        d.plain_instr.push_back(make(I_STREG, d.reg_width[s], 0xFFFF, (uint16_t)slot[d.reg_next[s]], 0xFFFF, 0xFFFF, s));
+      else if (s >= d.R + d.W) {
+        uint32_t o = s - d.R - d.W;
+        d.plain_instr.push_back(make(I_STOUT, d.width[d.out_node[o]], 0xFFFF, (uint16_t)slot[d.out_node[o]], 0xFFFF, 0xFFFF, o));
+      }
+    }
+    d.plain_levels.push_back((uint32_t)d.plain_instr.size());
+    pp.n_lvls = n_lvls;
+    // write-port commit, in port order
+    pp.wp_off = (uint32_t)d.plain_instr.size();
+    for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
+      uint32_t s = d.psinks[k];
+      if (s >= d.R && s < d.R + d.W) {
+        uint32_t q = s - d.R;
+        d.plain_instr.push_back(make(I_WPORT, d.mem_width[d.wp_mem[q]], 0xFFFF, (uint16_t)slot[d.wp_en[q]],
+                                     (uint16_t)slot[d.wp_addr[q]], (uint16_t)slot[d.wp_data[q]], d.wp_mem[q]));
+      }
+    }
+    pp.n_wp = (uint32_t)d.plain_instr.size() - pp.wp_off;
+    d.plain_max_slots = std::max(d.plain_max_slots, n);
+    d.plain_max_instr = std::max(d.plain_max_instr, (uint32_t)d.plain_instr.size() - base);
+    for (uint32_t j = lo; j < hi; ++j) slot[d.proc_nodes[j]] = UINT32_MAX;
+  }
+  return {};
+}
+
+Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
+  (void)d; (void)max_slots_per_class;
+  return Status::err(FSIM_E_UNSUPPORTED, "batched form not built yet");
+}
+
+}  // namespace fsim

@@ -1,0 +1,67 @@
+// isa.h -- the device instruction format shared by the host encoder and the
+// HIP kernels of libfibersim.  One instruction is 16 bytes.
+//
+// A process (a set of fibers, Parendi Sec. 3.2) is encoded as a straight-line,
+// call-free stream (Sec. 5.2 "aggressive inline": the device program has no
+// calls).  Combinational operators keep the netlist's opcode numbers; the
+// stream adds leaf loads, sink stores and the memory write-port commit.
+#pragma once
+#include <cstdint>
+
+namespace fsim {
+
+enum : uint8_t {
+  I_MEMRD = 3,
+  I_AND = 4, I_OR = 5, I_XOR = 6, I_NOT = 7, I_ADD = 8, I_SUB = 9, I_MUX = 10,
+  I_SHL = 11, I_SHR = 12, I_EQ = 13, I_LT = 14, I_MUL = 15,
+  I_LDREG = 16,    // dst <- current value of register aux
+  I_LDIN = 17,     // dst <- input port aux of this cycle
+  I_LDCONST = 18,  // dst <- consts[aux]
+  I_STREG = 19,    // next value of register aux <- a (masked to w)
+  I_STOUT = 20,    // output aux <- a
+  I_WPORT = 21,    // if a != 0: mem[aux][b mod depth] <- c (port order)
+  I_NUM = 22
+};
+
+// Slot classes of the batched form: 1-bit values are 64-lane ballot masks,
+// narrow values one u32 per lane, wide values one u64 per lane.
+enum : uint8_t { C_B = 0, C_W = 1, C_D = 2 };
+inline uint8_t class_of_width(uint32_t w) { return w == 1 ? C_B : (w <= 32 ? C_W : C_D); }
+
+struct Instr {
+  uint8_t op;     // I_*
+  uint8_t w;      // result width 1..64 (STREG: register width; WPORT: memory width)
+  uint8_t cls;    // batched: class of dst | a << 2 | b << 4 | c << 6
+  uint8_t flags;
+  uint16_t dst, a, b, c;   // slot indices
+  uint32_t aux;            // register / port / output / memory / constant index
+};
+static_assert(sizeof(Instr) == 16, "Instr must be 16 bytes");
+
+// Plain form: per process, a constant prologue (run once per launch), then
+// levels 0..n_lvls-1 (leaf loads, operator levels, the store level), each a
+// contiguous instruction range; then the write-port commit, run in order by
+// one thread after every read of the cycle.
+struct PlainProc {
+  uint32_t lvl_off;    // index into the level table: n_lvls + 1 entries
+  uint32_t n_lvls;
+  uint32_t const_off;  // prologue instructions
+  uint32_t n_consts;
+  uint32_t wp_off;     // commit instructions
+  uint32_t n_wp;
+  uint32_t n_slots;    // u64 LDS slots used
+  uint32_t pad;
+};
+static_assert(sizeof(PlainProc) == 32, "PlainProc must be 32 bytes");
+
+// Batched form: per process, one sequential stream evaluated by a wave for
+// 64 instances at a time; slots are per class.
+struct BatchProc {
+  uint32_t instr_off;
+  uint32_t n_instr;
+  uint32_t slots[3];   // live slots needed per class
+  uint32_t pad[3];
+};
+static_assert(sizeof(BatchProc) == 32, "BatchProc must be 32 bytes");
+
+}  // namespace fsim

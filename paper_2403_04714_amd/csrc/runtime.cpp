@@ -1,0 +1,603 @@
+// runtime.cpp -- the C-ABI of libfibersim (include/fibersim.h): contexts,
+// design loading, sims, stepping, state access and verification digests.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fibersim.h"
+#include "compiler.h"
+#include "kernels.h"
+
+using fsim::Design;
+using fsim::Status;
+
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+int fail(const Status& s) { return fail(s.code, s.msg); }
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(FSIM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// A device buffer the library owns.
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  hipError_t alloc(size_t bytes) {
+    if (p) { (void)hipFree(p); p = nullptr; }
+    n = bytes;
+    return hipMalloc(&p, bytes ? bytes : 256);
+  }
+};
+}  // namespace
+
+struct fsim_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint32_t n_cus = 0, lds_bytes = 0;
+  std::mutex mu;
+};
+
+struct fsim_design {
+  std::atomic<int> refs{1};
+  fsim_ctx* ctx = nullptr;          // null: compiled on the host only
+  Design d;
+  fsim_design_info info{};
+  // plain-form program on the device
+  DevBuf instr, levels, procs, consts, mem_off, mem_depth, in_width;
+  uint32_t slot_words = 0, max_proc_instr = 0;
+};
+
+struct fsim_sim {
+  fsim_design* d = nullptr;
+  uint32_t n_inst = 1;
+  uint32_t G = 1, threads = 256, launch = FSIM_LAUNCH_PERSISTENT, graph_cycles = 64;
+  size_t lds_bytes = 0;
+  bool stage_instr = false;
+  bool poisoned = false;
+  uint64_t cycle = 0, seed = 0;
+  uint32_t epoch = 0;
+  // device memory: workspace (owned or borrowed) and its carve-up
+  DevBuf own_ws;
+  char* ws = nullptr;
+  uint64_t *state = nullptr, *outputs = nullptr, *mem = nullptr, *keys = nullptr, *cyc_dev = nullptr;
+  uint32_t *flags = nullptr, *error = nullptr;
+  // explicit inputs
+  DevBuf in_vals;
+  uint64_t in_first = 0, in_count = 0;
+  bool explicit_inputs = false;
+  // digests
+  uint64_t* dig_out = nullptr;
+  uint64_t dig_first = 0, dig_max = 0;
+  DevBuf dig_part;
+  // graph mode
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  ~fsim_sim() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+extern "C" const char* fsim_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ context
+extern "C" int fsim_ctx_create(int hip_device, void* hip_stream, fsim_ctx** out) {
+  if (!out) return fail(FSIM_E_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n) return fail(FSIM_E_ARG, "no such HIP device");
+  HIP_TRY(hipSetDevice(hip_device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+  auto* c = new fsim_ctx;
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  c->n_cus = (uint32_t)prop.multiProcessorCount;
+  c->lds_bytes = (uint32_t)prop.sharedMemPerBlock;
+  *out = c;
+  return FSIM_OK;
+}
+
+extern "C" void fsim_ctx_destroy(fsim_ctx* ctx) { delete ctx; }
+
+extern "C" int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_bytes,
+                               uint32_t* max_coresident_wgs) {
+  if (!ctx) return fail(FSIM_E_ARG, "ctx is NULL");
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (n_cus) *n_cus = ctx->n_cus;
+  if (lds_bytes) *lds_bytes = ctx->lds_bytes;
+  if (max_coresident_wgs) {
+    int b = 0;
+    HIP_TRY(fsim::plain_occupancy(&b, 256, 0));
+    *max_coresident_wgs = (uint32_t)b * ctx->n_cus;
+  }
+  return FSIM_OK;
+}
+
+// ------------------------------------------------------------------- design
+static constexpr uint32_t kDefaultLds = 160 * 1024;
+static constexpr uint32_t kStaticLds = 1024;     // abort flag, reduction scratch
+
+template <class T>
+static int upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+  HIP_TRY(b.alloc(v.size() * sizeof(T)));
+  if (!v.empty()) HIP_TRY(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsim_partition* part,
+                                const fsim_compile_opts* opts, fsim_design** out) {
+  if (!out) return fail(FSIM_E_ARG, "out is NULL");
+  *out = nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  auto dz = std::make_unique<fsim_design>();
+  fsim_compile_opts o{};
+  if (opts) o = *opts;
+  if (o.pack > FSIM_PACK_SINGLE) return fail(FSIM_E_ARG, "unknown packing policy");
+  Design& d = dz->d;
+  Status s = fsim::copy_and_validate(nl, d);
+  if (!s.ok()) return fail(s);
+  const uint32_t lds = ctx ? ctx->lds_bytes : kDefaultLds;
+  const uint32_t max_slots = (lds - kStaticLds) / 8;
+  const uint32_t default_target = ctx ? ctx->n_cus : 256;
+  const uint32_t default_nodes = std::min<uint32_t>(max_slots / 2, 0xFFFE);
+  s = fsim::partition_design(d, part, o, default_target, default_nodes);
+  if (!s.ok()) return fail(s);
+  s = fsim::encode_plain(d, std::min<uint32_t>(max_slots, 0xFFFE));
+  if (!s.ok()) return fail(s);
+  // per-process instruction span (levels + commit), for LDS staging
+  uint32_t mx = 0;
+  for (const auto& pp : d.plain_procs) {
+    uint32_t n = d.plain_levels[pp.lvl_off + pp.n_lvls] - d.plain_levels[pp.lvl_off] + pp.n_wp;
+    mx = std::max(mx, n);
+  }
+  dz->max_proc_instr = mx;
+  dz->slot_words = (d.plain_max_slots + 1) & ~1u;
+  d.compile_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fsim_design_info& I = dz->info;
+  I.n_nodes = d.N;
+  I.n_live_ops = (uint32_t)d.n_live_ops;
+  I.n_regs = d.R;
+  I.n_sinks = d.n_sinks();
+  I.n_processes = d.P;
+  I.max_depth = d.max_depth;
+  I.sum_fiber_ops = d.sum_fiber_ops;
+  I.sum_process_ops = d.sum_process_ops;
+  I.dup_fiber = d.n_live_ops ? (double)d.sum_fiber_ops / (double)d.n_live_ops : 1.0;
+  I.dup_process = d.n_live_ops ? (double)d.sum_process_ops / (double)d.n_live_ops : 1.0;
+  I.max_fiber_cost = d.max_fiber_cost;
+  I.max_process_cost = d.max_process_cost;
+  I.program_bytes = d.plain_instr.size() * sizeof(fsim::Instr) + d.plain_levels.size() * 4 +
+                    d.plain_procs.size() * sizeof(fsim::PlainProc) + d.consts.size() * 8;
+  I.max_process_levels = d.max_process_levels;
+  I.max_process_nodes = d.max_process_nodes;
+  I.compile_seconds = d.compile_seconds;
+  if (ctx) {
+    dz->ctx = ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    int rc;
+    if ((rc = upload(dz->instr, d.plain_instr, st))) return rc;
+    if ((rc = upload(dz->levels, d.plain_levels, st))) return rc;
+    if ((rc = upload(dz->procs, d.plain_procs, st))) return rc;
+    if ((rc = upload(dz->consts, d.consts, st))) return rc;
+    std::vector<uint64_t> moff(d.mem_off.begin(), d.mem_off.end() - (d.M ? 1 : 0));
+    if (d.M == 0) moff.clear();
+    if ((rc = upload(dz->mem_off, moff, st))) return rc;
+    if ((rc = upload(dz->mem_depth, d.mem_depth, st))) return rc;
+    if ((rc = upload(dz->in_width, d.in_width, st))) return rc;
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  *out = dz.release();
+  return FSIM_OK;
+}
+
+extern "C" int fsim_design_info_get(const fsim_design* d, fsim_design_info* out) {
+  if (!d || !out) return fail(FSIM_E_ARG, "NULL argument");
+  *out = d->info;
+  return FSIM_OK;
+}
+
+extern "C" int fsim_design_partition(const fsim_design* dd, uint32_t* sink_to_process,
+                                     uint32_t* proc_off, uint32_t* proc_nodes) {
+  if (!dd) return fail(FSIM_E_ARG, "design is NULL");
+  const Design& d = dd->d;
+  if (sink_to_process) std::copy(d.sink_proc.begin(), d.sink_proc.end(), sink_to_process);
+  if (proc_off) std::copy(d.proc_off.begin(), d.proc_off.end(), proc_off);
+  if (proc_nodes) std::copy(d.proc_nodes.begin(), d.proc_nodes.end(), proc_nodes);
+  return FSIM_OK;
+}
+
+static void design_release(fsim_design* d) {
+  if (d && --d->refs == 0) delete d;
+}
+
+extern "C" void fsim_design_free(fsim_design* d) { design_release(d); }
+
+// ---------------------------------------------------------------------- sim
+namespace {
+struct Layout {
+  size_t state, outputs, mem, keys, flags, error, cyc, total;
+};
+
+Layout layout(const Design& d, uint32_t n_inst, uint32_t G) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  L.state = take(2ull * d.R * 8 * n_inst);
+  L.outputs = take((size_t)d.O * 8 * n_inst);
+  L.mem = take(d.mem_off[d.M] * 8 * n_inst);
+  L.keys = take((size_t)d.I * 8 * n_inst);
+  L.flags = take((size_t)std::max(G, 1u) * 4);
+  L.error = take(16);
+  L.cyc = take(8);
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+extern "C" int fsim_sim_footprint(const fsim_design* d, uint32_t n_instances, size_t* bytes) {
+  if (!d || !bytes) return fail(FSIM_E_ARG, "NULL argument");
+  if (n_instances == 0) return fail(FSIM_E_ARG, "n_instances must be >= 1");
+  *bytes = layout(d->d, n_instances, d->d.P).total;
+  return FSIM_OK;
+}
+
+static int sim_reset_state(fsim_sim* s) {
+  const Design& d = s->d->d;
+  hipStream_t st = s->d->ctx->stream;
+  HIP_TRY(hipMemcpyAsync(s->state, d.reg_init.data(), (size_t)d.R * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(s->state + d.R, 0, (size_t)d.R * 8, st));
+  if (d.mem_off[d.M])
+    HIP_TRY(hipMemcpyAsync(s->mem, d.mem_init.data(), d.mem_off[d.M] * 8, hipMemcpyHostToDevice, st));
+  if (d.O) HIP_TRY(hipMemsetAsync(s->outputs, 0, (size_t)d.O * 8, st));
+  HIP_TRY(hipMemsetAsync(s->flags, 0, (size_t)s->G * 4, st));
+  HIP_TRY(hipMemsetAsync(s->error, 0, 16, st));
+  HIP_TRY(hipMemsetAsync(s->cyc_dev, 0, 8, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_set_stimulus_seed(fsim_sim* s, uint64_t seed_base) {
+  if (!s) return fail(FSIM_E_ARG, "sim is NULL");
+  if (s->poisoned) return fail(FSIM_E_STATE, "sim is poisoned by an earlier device error");
+  s->seed = seed_base;
+  s->explicit_inputs = false;
+  HIP_TRY(fsim::launch_stim_keys(s->keys, seed_base, s->n_inst, s->d->d.I, s->d->ctx->stream));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* workspace, size_t ws_bytes,
+                               const fsim_sim_opts* opts, fsim_sim** out) {
+  if (!d || !out) return fail(FSIM_E_ARG, "NULL argument");
+  *out = nullptr;
+  if (!d->ctx) return fail(FSIM_E_STATE, "design was compiled without a device context");
+  if (n_instances != 1) return fail(FSIM_E_UNSUPPORTED, "batched form: n_instances > 1 not built yet");
+  fsim_sim_opts o{};
+  if (opts) o = *opts;
+  auto s = std::make_unique<fsim_sim>();
+  s->d = d;
+  s->n_inst = n_instances;
+  s->G = d->d.P;
+  s->threads = o.wg_threads ? o.wg_threads : 256;
+  if (s->threads < 64 || s->threads > 1024 || s->threads % 64)
+    return fail(FSIM_E_ARG, "wg_threads must be a multiple of 64 in [64, 1024]");
+  if (o.grid && o.grid != s->G)
+    return fail(FSIM_E_ARG, "plain form: grid must equal the design's process count");
+  s->launch = o.launch ? o.launch : FSIM_LAUNCH_PERSISTENT;
+  if (s->launch > FSIM_LAUNCH_GRAPH) return fail(FSIM_E_ARG, "unknown launch mode");
+  s->graph_cycles = o.graph_cycles ? o.graph_cycles : 64;
+  if (s->graph_cycles % 2) s->graph_cycles++;      // keeps the state parity of the base cycle even
+  HIP_TRY(hipSetDevice(d->ctx->device));
+  // LDS: slots, plus the process's instructions when they fit
+  const size_t lds_limit = d->ctx->lds_bytes - kStaticLds;
+  size_t lds = (size_t)d->slot_words * 8;
+  if (lds + (size_t)d->max_proc_instr * sizeof(fsim::Instr) <= lds_limit) {
+    s->stage_instr = true;
+    lds += (size_t)d->max_proc_instr * sizeof(fsim::Instr);
+  }
+  if (lds > lds_limit) return fail(FSIM_E_CAPACITY, "process does not fit in LDS");
+  s->lds_bytes = lds;
+  if (s->launch == FSIM_LAUNCH_PERSISTENT) {
+    int b = 0;
+    HIP_TRY(fsim::plain_occupancy(&b, s->threads, lds));
+    if ((uint64_t)b * d->ctx->n_cus < s->G)
+      return fail(FSIM_E_CAPACITY, "persistent launch: " + std::to_string(s->G) +
+                                       " workgroups are not co-resident; use fewer processes");
+  }
+  Layout L = layout(d->d, n_instances, s->G);
+  if (workspace) {
+    if (ws_bytes < L.total) return fail(FSIM_E_ARG, "workspace smaller than fsim_sim_footprint()");
+    if ((uintptr_t)workspace % 256) return fail(FSIM_E_ARG, "workspace must be 256-byte aligned");
+    s->ws = (char*)workspace;
+  } else {
+    HIP_TRY(s->own_ws.alloc(L.total));
+    s->ws = (char*)s->own_ws.p;
+  }
+  s->state = (uint64_t*)(s->ws + L.state);
+  s->outputs = (uint64_t*)(s->ws + L.outputs);
+  s->mem = (uint64_t*)(s->ws + L.mem);
+  s->keys = (uint64_t*)(s->ws + L.keys);
+  s->flags = (uint32_t*)(s->ws + L.flags);
+  s->error = (uint32_t*)(s->ws + L.error);
+  s->cyc_dev = (uint64_t*)(s->ws + L.cyc);
+  int rc = sim_reset_state(s.get());
+  if (rc) return rc;
+  if ((rc = fsim_set_stimulus_seed(s.get(), 0))) return rc;
+  d->refs++;
+  *out = s.release();
+  return FSIM_OK;
+}
+
+extern "C" void fsim_sim_destroy(fsim_sim* s) {
+  if (!s) return;
+  if (s->d && s->d->ctx) {
+    (void)hipSetDevice(s->d->ctx->device);
+    (void)hipStreamSynchronize(s->d->ctx->stream);
+  }
+  fsim_design* d = s->d;
+  delete s;
+  design_release(d);
+}
+
+extern "C" int fsim_set_inputs(fsim_sim* s, uint64_t first_cycle, uint32_t n_cycles, const uint64_t* vals) {
+  if (!s || (!vals && n_cycles)) return fail(FSIM_E_ARG, "NULL argument");
+  if (s->poisoned) return fail(FSIM_E_STATE, "sim is poisoned by an earlier device error");
+  const Design& d = s->d->d;
+  size_t bytes = (size_t)n_cycles * d.I * s->n_inst * 8;
+  HIP_TRY(hipStreamSynchronize(s->d->ctx->stream));
+  HIP_TRY(s->in_vals.alloc(bytes));
+  if (bytes) HIP_TRY(hipMemcpy(s->in_vals.p, vals, bytes, hipMemcpyHostToDevice));
+  s->in_first = first_cycle;
+  s->in_count = n_cycles;
+  s->explicit_inputs = true;
+  return FSIM_OK;
+}
+
+static fsim::PlainArgs plain_args(fsim_sim* s) {
+  const fsim_design* dd = s->d;
+  fsim::PlainArgs a{};
+  a.instr = (const fsim::Instr*)dd->instr.p;
+  a.levels = (const uint32_t*)dd->levels.p;
+  a.procs = (const fsim::PlainProc*)dd->procs.p;
+  a.consts = (const uint64_t*)dd->consts.p;
+  a.state = s->state;
+  a.outputs = s->outputs;
+  a.mem = s->mem;
+  a.mem_off = (const uint64_t*)dd->mem_off.p;
+  a.mem_depth = (const uint32_t*)dd->mem_depth.p;
+  a.in_width = (const uint8_t*)dd->in_width.p;
+  a.in_keys = s->keys;
+  a.in_vals = s->explicit_inputs ? (const uint64_t*)s->in_vals.p : nullptr;
+  a.in_first = s->in_first;
+  a.in_count = s->in_count;
+  a.digest_part = s->dig_out ? (uint64_t*)s->dig_part.p : nullptr;
+  a.digest_first = s->dig_first;
+  a.digest_max = s->dig_max;
+  a.flags = s->flags;
+  a.error = s->error;
+  a.R = dd->d.R;
+  a.I = dd->d.I;
+  a.stage_instr = s->stage_instr ? 1 : 0;
+  a.slot_words = dd->slot_words;
+  a.cycle_ptr = nullptr;
+  return a;
+}
+
+static int build_graph(fsim_sim* s) {
+  hipStream_t st = s->d->ctx->stream;
+  hipStream_t cap;
+  HIP_TRY(hipStreamCreate(&cap));
+  fsim::PlainArgs a = plain_args(s);
+  a.cycle_ptr = s->cyc_dev;
+  a.n_cycles = 1;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  for (uint32_t k = 0; e == hipSuccess && k < s->graph_cycles; ++k) {
+    a.cycle0 = k;
+    e = fsim::launch_plain(a, s->G, s->threads, s->lds_bytes, false, cap);
+  }
+  if (e == hipSuccess) e = fsim::launch_add_u64(s->cyc_dev, s->graph_cycles, cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  (void)st;
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(FSIM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  s->graph = g;
+  HIP_TRY(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_step(fsim_sim* s, uint64_t n_cycles) {
+  if (!s) return fail(FSIM_E_ARG, "sim is NULL");
+  if (s->poisoned) return fail(FSIM_E_STATE, "sim is poisoned by an earlier device error");
+  if (n_cycles == 0) return FSIM_OK;
+  if (s->explicit_inputs &&
+      (s->cycle < s->in_first || s->cycle + n_cycles > s->in_first + s->in_count))
+    return fail(FSIM_E_ARG, "explicit inputs do not cover the requested cycles");
+  fsim_design* dd = s->d;
+  hipStream_t st = dd->ctx->stream;
+  HIP_TRY(hipSetDevice(dd->ctx->device));
+  const uint64_t c_begin = s->cycle;
+  uint64_t left = n_cycles;
+  fsim::PlainArgs a = plain_args(s);
+  if (s->launch == FSIM_LAUNCH_PERSISTENT) {
+    while (left) {
+      uint32_t n = (uint32_t)std::min<uint64_t>(left, 1u << 20);
+      a.cycle0 = s->cycle;
+      a.n_cycles = n;
+      a.epoch0 = s->epoch;
+      hipError_t e = fsim::launch_plain(a, s->G, s->threads, s->lds_bytes, true, st);
+      if (e != hipSuccess) { s->poisoned = true; return fail(FSIM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e)); }
+      s->epoch += n;
+      s->cycle += n;
+      left -= n;
+    }
+  } else {
+    // graph mode needs the device-side cycle counter in step with the host's
+    bool graph = s->launch == FSIM_LAUNCH_GRAPH && !s->explicit_inputs;
+    if (graph && !s->gexec) {
+      int rc = build_graph(s);
+      if (rc) return rc;
+    }
+    while (left) {
+      if (graph && left >= s->graph_cycles && (s->cycle % 2) == 0) {
+        // device counter holds the base cycle of the next graph
+        uint64_t c = s->cycle;
+        HIP_TRY(hipMemcpyAsync(s->cyc_dev, &c, 8, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        while (left >= s->graph_cycles) {
+          HIP_TRY(hipGraphLaunch(s->gexec, st));
+          s->cycle += s->graph_cycles;
+          left -= s->graph_cycles;
+        }
+        continue;
+      }
+      a.cycle0 = s->cycle;
+      a.n_cycles = 1;
+      hipError_t e = fsim::launch_plain(a, s->G, s->threads, s->lds_bytes, false, st);
+      if (e != hipSuccess) { s->poisoned = true; return fail(FSIM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e)); }
+      s->cycle += 1;
+      left -= 1;
+    }
+  }
+  if (s->dig_out) {
+    uint64_t lo = std::max(c_begin, s->dig_first), hi = std::min(s->cycle, s->dig_first + s->dig_max);
+    if (hi > lo) {
+      uint64_t k0 = lo - s->dig_first;
+      HIP_TRY(fsim::launch_digest_reduce((const uint64_t*)s->dig_part.p + k0 * s->G, s->G, hi - lo,
+                                         s->dig_out + k0, st));
+    }
+  }
+  return FSIM_OK;
+}
+
+extern "C" int fsim_sync(fsim_sim* s) {
+  if (!s) return fail(FSIM_E_ARG, "sim is NULL");
+  if (s->poisoned) return fail(FSIM_E_STATE, "sim is poisoned by an earlier device error");
+  HIP_TRY(hipSetDevice(s->d->ctx->device));
+  hipError_t e = hipStreamSynchronize(s->d->ctx->stream);
+  if (e != hipSuccess) { s->poisoned = true; return fail(FSIM_E_DEVICE, hipGetErrorString(e)); }
+  uint32_t err[2] = {0, 0};
+  e = hipMemcpy(err, s->error, 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) { s->poisoned = true; return fail(FSIM_E_DEVICE, hipGetErrorString(e)); }
+  if (err[0]) { s->poisoned = true; return fail(FSIM_E_DEVICE, "grid barrier timed out"); }
+  if (err[1]) { s->poisoned = true; return fail(FSIM_E_ARG, "explicit inputs missing for a simulated cycle"); }
+  return FSIM_OK;
+}
+
+extern "C" uint64_t fsim_cycle(const fsim_sim* s) { return s ? s->cycle : 0; }
+
+static int check_inst(fsim_sim* s, uint32_t inst) {
+  if (!s) return fail(FSIM_E_ARG, "sim is NULL");
+  if (inst >= s->n_inst) return fail(FSIM_E_ARG, "instance out of range");
+  return fsim_sync(s);
+}
+
+extern "C" int fsim_read_regs(fsim_sim* s, uint32_t inst, uint64_t* out) {
+  int rc = check_inst(s, inst);
+  if (rc) return rc;
+  if (!out && s->d->d.R) return fail(FSIM_E_ARG, "out is NULL");
+  const uint32_t R = s->d->d.R;
+  HIP_TRY(hipMemcpy(out, s->state + (s->cycle & 1) * R, (size_t)R * 8, hipMemcpyDeviceToHost));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_write_regs(fsim_sim* s, uint32_t inst, const uint64_t* in) {
+  int rc = check_inst(s, inst);
+  if (rc) return rc;
+  const Design& d = s->d->d;
+  if (!in && d.R) return fail(FSIM_E_ARG, "in is NULL");
+  std::vector<uint64_t> v(in, in + d.R);
+  for (uint32_t r = 0; r < d.R; ++r) v[r] &= ~0ull >> (64 - d.reg_width[r]);
+  HIP_TRY(hipMemcpy(s->state + (s->cycle & 1) * d.R, v.data(), (size_t)d.R * 8, hipMemcpyHostToDevice));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_read_outputs(fsim_sim* s, uint32_t inst, uint64_t* out) {
+  int rc = check_inst(s, inst);
+  if (rc) return rc;
+  const uint32_t O = s->d->d.O;
+  if (!out && O) return fail(FSIM_E_ARG, "out is NULL");
+  if (O) HIP_TRY(hipMemcpy(out, s->outputs, (size_t)O * 8, hipMemcpyDeviceToHost));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_read_mem(fsim_sim* s, uint32_t inst, uint32_t m, uint64_t* out) {
+  int rc = check_inst(s, inst);
+  if (rc) return rc;
+  const Design& d = s->d->d;
+  if (m >= d.M) return fail(FSIM_E_ARG, "memory out of range");
+  if (!out) return fail(FSIM_E_ARG, "out is NULL");
+  HIP_TRY(hipMemcpy(out, s->mem + d.mem_off[m], (size_t)d.mem_depth[m] * 8, hipMemcpyDeviceToHost));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_write_mem(fsim_sim* s, uint32_t inst, uint32_t m, const uint64_t* in) {
+  int rc = check_inst(s, inst);
+  if (rc) return rc;
+  const Design& d = s->d->d;
+  if (m >= d.M) return fail(FSIM_E_ARG, "memory out of range");
+  if (!in) return fail(FSIM_E_ARG, "in is NULL");
+  std::vector<uint64_t> v(in, in + d.mem_depth[m]);
+  for (auto& x : v) x &= ~0ull >> (64 - d.mem_width[m]);
+  HIP_TRY(hipMemcpy(s->mem + d.mem_off[m], v.data(), v.size() * 8, hipMemcpyHostToDevice));
+  return FSIM_OK;
+}
+
+extern "C" int fsim_set_cycle(fsim_sim* s, uint64_t cycle) {
+  int rc = check_inst(s, 0);
+  if (rc) return rc;
+  const uint32_t R = s->d->d.R;
+  if ((cycle & 1) != (s->cycle & 1) && R)
+    HIP_TRY(hipMemcpy(s->state + (cycle & 1) * R, s->state + (s->cycle & 1) * R, (size_t)R * 8 * s->n_inst,
+                      hipMemcpyDeviceToDevice));
+  s->cycle = cycle;
+  return FSIM_OK;
+}
+
+extern "C" int fsim_enable_digest(fsim_sim* s, uint64_t* dev_out, uint64_t max_cycles) {
+  if (!s) return fail(FSIM_E_ARG, "sim is NULL");
+  if (s->poisoned) return fail(FSIM_E_STATE, "sim is poisoned by an earlier device error");
+  hipStream_t st = s->d->ctx->stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  if (!dev_out || max_cycles == 0) {
+    s->dig_out = nullptr;
+    s->dig_max = 0;
+    return FSIM_OK;
+  }
+  HIP_TRY(s->dig_part.alloc((size_t)max_cycles * s->G * 8 * s->n_inst));
+  HIP_TRY(hipMemsetAsync(s->dig_part.p, 0, (size_t)max_cycles * s->G * 8 * s->n_inst, st));
+  HIP_TRY(hipMemsetAsync(dev_out, 0, (size_t)max_cycles * 8 * s->n_inst, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  s->dig_out = dev_out;
+  s->dig_first = s->cycle;
+  s->dig_max = max_cycles;
+  if (s->gexec) {               // the captured graph has digests baked out
+    (void)hipGraphExecDestroy(s->gexec);
+    (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+  }
+  return FSIM_OK;
+}

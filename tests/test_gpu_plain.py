@@ -1,0 +1,170 @@
+"""Parity of the plain form (one instance, level-parallel workgroups) on the
+GPU against the oracle: per-cycle digests and full state, bit-exact, across
+packings (single process, one fiber per process, SLB merge), launch modes
+(persistent with grid barrier, one launch per cycle, hipGraph) and the
+circuits with known behaviour."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2403_04714_amd import netgen as g
+
+pytestmark = pytest.mark.gpu
+
+SEED = g.STIM_SEED_BASE
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2403_04714_amd import fibersim
+    return fibersim
+
+
+@pytest.fixture(scope="module")
+def ctx(F):
+    return F.Context(0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run_both(F, ctx, nl, cycles, pack, target=0, launch=None, threads=0, seed=SEED, chunks=(None,)):
+    launch = F.LAUNCH_PERSISTENT if launch is None else launch
+    say(f"case {nl.name}: pack={pack} target={target} launch={launch} threads={threads} cycles={cycles}")
+    d = F.Design(ctx, nl, pack=pack, target_processes=target)
+    s = F.Sim(d, 1, launch=launch, wg_threads=threads, seed=seed)
+    s.enable_digest(cycles)
+    done = 0
+    for c in chunks:
+        n = cycles - done if c is None else c
+        s.step(n)
+        done += n
+    assert done == cycles
+    dg = s.digests()[:, 0]
+    ref = O.Sim(nl, seed=seed)
+    rd = ref.step(cycles, digests=True)
+    bad = np.nonzero(dg != rd)[0]
+    assert bad.size == 0, f"first digest mismatch at cycle {bad[0]} of {cycles}"
+    assert np.array_equal(s.regs(), ref.regs())
+    assert np.array_equal(s.outputs(), ref.outputs())
+    for m in range(nl.n_mems):
+        assert np.array_equal(s.mem(m), ref.mem(m)), f"memory {m}"
+    return d, s
+
+
+def test_tiny_single_process_10k_cycles(F, ctx):
+    run_both(F, ctx, g.gen_tiny(0), 10_000, F.PACK_SINGLE)
+
+
+@pytest.mark.parametrize("pack,target", [(1, 0), (0, 8), (0, 33)])
+def test_tiny_packings(F, ctx, pack, target):
+    run_both(F, ctx, g.gen_tiny(1), 2000, pack, target)
+
+
+@pytest.mark.parametrize("launch", [2, 3])
+def test_tiny_launch_modes(F, ctx, launch):
+    run_both(F, ctx, g.gen_tiny(2), 1000, 0, 16, launch=launch, chunks=(3, 130, 500, None))
+
+
+@pytest.mark.parametrize("threads", [64, 128, 1024])
+def test_tiny_workgroup_sizes(F, ctx, threads):
+    run_both(F, ctx, g.gen_tiny(3), 1000, 0, 5, threads=threads)
+
+
+def test_persistent_chunks_and_odd_steps(F, ctx):
+    run_both(F, ctx, g.gen_tiny(4), 777, 0, 12, chunks=(1, 2, 3, 100, None))
+
+
+def small_core(seed=5):
+    p = g.CoreParams(n_regs_1=1400, n_regs_32=300, n_regs_64=300, target_ops=20000,
+                     mem_depth=256, reg_locality=96)
+    return g.gen_core(seed, p)
+
+
+@pytest.mark.parametrize("target", [4, 24, 200])
+def test_small_core_with_memories(F, ctx, target):
+    run_both(F, ctx, small_core(), 400, 0, target)
+
+
+def test_core_full_size_2000_cycles(F, ctx):
+    """The single-core workload at full size (~200k operators, depth 40, two
+    4096 x 64 memories), one fiber per register merged to 256 processes;
+    2,000 cycles compared per cycle (the oracle needs ~6 ms per cycle)."""
+    run_both(F, ctx, g.workload("core"), 2000, 0, 256)
+
+
+def _pairs_inputs(n=4):
+    pairs = list(itertools.product(range(2**n), repeat=2))
+    return pairs, np.array(pairs, np.uint64)
+
+
+@pytest.mark.parametrize("builder,check", [
+    (g.ripple_adder, lambda a, b, r: int(r[0]) == a + b),
+    (g.array_multiplier, lambda a, b, r: int(r[0]) == a * b),
+    (g.comparators, lambda a, b, r: int(r[0]) == int(a == b) and int(r[1]) == int(a < b)),
+])
+def test_bruteforce_circuits_explicit_inputs(F, ctx, builder, check):
+    nl = builder(4)
+    say(f"case {nl.name}: explicit inputs, all 256 pairs")
+    pairs, vals = _pairs_inputs()
+    for pack in (F.PACK_SINGLE, F.PACK_FIBERS):
+        d = F.Design(ctx, nl, pack=pack)
+        s = F.Sim(d, 1)
+        s.set_inputs(0, vals)
+        for (a, b) in pairs:
+            s.step(1)
+            assert check(a, b, s.regs()), (nl.name, a, b)
+
+
+def test_closed_forms(F, ctx):
+    say("case counters/lfsr/xorshift")
+    for w in (1, 8, 64):
+        d = F.Design(ctx, g.counter(w))
+        s = F.Sim(d, 1)
+        s.step(1000)
+        assert int(s.regs()[0]) == 1000 % 2**w
+    d = F.Design(ctx, g.lfsr(12, [12, 11, 10, 4]), pack=F.PACK_FIBERS)
+    s = F.Sim(d, 1)
+    r0 = s.regs().copy()
+    s.step(2**12 - 1)
+    assert np.array_equal(s.regs(), r0)
+    d = F.Design(ctx, g.xorshift32())
+    s = F.Sim(d, 1)
+    s.step(1)
+    assert int(s.regs()[0]) == 723471715
+
+
+def test_explicit_input_window_error(F, ctx):
+    nl = g.ripple_adder(4)
+    d = F.Design(ctx, nl)
+    s = F.Sim(d, 1)
+    s.set_inputs(0, np.zeros((10, 2), np.uint64))
+    s.step(10)
+    with pytest.raises(F.FsimError) as e:
+        s.step(1)
+    assert e.value.code == F.E_ARG
+    s.step(0)
+
+
+def test_checkpoint_resume(F, ctx):
+    """Run N, checkpoint (registers, memories, cycle), restore into a fresh sim,
+    run M: equal to an uninterrupted N + M run."""
+    nl = small_core(9)
+    say("case checkpoint/resume on small core")
+    d = F.Design(ctx, nl, target_processes=16)
+    a = F.Sim(d, 1, seed=SEED)
+    a.step(150)
+    regs, mems, cyc = a.regs().copy(), [a.mem(m).copy() for m in range(nl.n_mems)], a.cycle
+    a.step(251)
+    b = F.Sim(d, 1, seed=SEED)
+    b.write_regs(regs)
+    for m, v in enumerate(mems):
+        b.write_mem(m, v)
+    b.set_cycle(cyc)
+    b.step(251)
+    assert np.array_equal(a.regs(), b.regs())
+    for m in range(nl.n_mems):
+        assert np.array_equal(a.mem(m), b.mem(m))
