@@ -228,6 +228,20 @@ int fsim_set_cycle(fsim_sim* s, uint64_t cycle);
  * max_cycles * n_instances uint64, zeroed by this call; NULL disables. */
 int fsim_enable_digest(fsim_sim* s, uint64_t* dev_out, uint64_t max_cycles);
 
+/* Phase timestamps, for the per-cycle time breakdown of Parendi Sec. 4
+ * (Eq. sim_rate: t_sync + t_comm + t_comp).  For every simulated cycle from
+ * the current one and every workgroup, the device writes the 100 MHz
+ * realtime counter to dev_out[(k * workgroups + wg) * stride + j]: j = 0 at
+ * the cycle start, j = L + 1 after level L of the process, j = stride - 2
+ * after the memory commit, j = stride - 1 after the grid barrier.  dev_out
+ * is caller device memory of max_cycles * workgroups * stride uint64; the
+ * stride is returned.  NULL disables. */
+int fsim_enable_trace(fsim_sim* s, uint64_t* dev_out, uint64_t max_cycles, uint32_t* stride);
+/* Launch shape chosen for the sim: workgroups, threads per workgroup,
+ * launch mode, and whether the process instructions are staged in LDS. */
+int fsim_sim_layout(const fsim_sim* s, uint32_t* workgroups, uint32_t* threads,
+                    uint32_t* launch, uint32_t* staged);
+
 #ifdef __cplusplus
 }
 #endif

@@ -541,21 +541,29 @@ Status encode_plain(Design& d, uint32_t max_slots) {
       d.consts.push_back(v);
     }
     pp.n_consts = (uint32_t)d.plain_instr.size() - pp.const_off;
-    // levels: 0 = register and input loads; then one level per operator
-    // level present in the process (empty levels are dropped), sorted by
-    // opcode and width so wavefronts are uniform; then the store level
+    // levels: 0 = register and input loads (always present, possibly empty);
+    // then one level per operator level present in the process (empty levels
+    // are dropped), sorted by opcode and width so wavefronts are uniform;
+    // then the store level.  Unused operand slots repeat operand a so that
+    // the kernel can read all three without tests.
     pp.lvl_off = (uint32_t)d.plain_levels.size();
     std::vector<uint32_t> lvl_nodes;
     uint32_t i = lo;
     uint32_t n_lvls = 0;
+    d.plain_levels.push_back((uint32_t)d.plain_instr.size());
+    n_lvls++;
+    while (i < hi && d.level[d.proc_nodes[i]] == 0) {
+      uint32_t x = d.proc_nodes[i++];
+      if (d.op[x] == FSIM_OP_REG)
+        d.plain_instr.push_back(make(I_LDREG, d.width[x], (uint16_t)slot[x], 0, 0, 0, (uint32_t)d.imm[x]));
+      else if (d.op[x] == FSIM_OP_INPUT)   // the width folds in the port's own width
+        d.plain_instr.push_back(make(I_LDIN, std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]),
+                                     (uint16_t)slot[x], 0, 0, 0, (uint32_t)d.imm[x]));
+    }
     while (i < hi) {
       uint32_t L = d.level[d.proc_nodes[i]];
       lvl_nodes.clear();
-      while (i < hi && d.level[d.proc_nodes[i]] == L) {
-        uint32_t x = d.proc_nodes[i++];
-        if (d.op[x] != FSIM_OP_CONST) lvl_nodes.push_back(x);
-      }
-      if (lvl_nodes.empty()) continue;
+      while (i < hi && d.level[d.proc_nodes[i]] == L) lvl_nodes.push_back(d.proc_nodes[i++]);
       std::stable_sort(lvl_nodes.begin(), lvl_nodes.end(), [&](uint32_t a, uint32_t b) {
         if (d.op[a] != d.op[b]) return d.op[a] < d.op[b];
         return (d.width[a] > 32) < (d.width[b] > 32);
@@ -565,15 +573,12 @@ Status encode_plain(Design& d, uint32_t max_slots) {
       for (uint32_t x : lvl_nodes) {
         uint8_t op = d.op[x];
         const uint32_t* a = &d.arg[3ull * x];
-        auto s = [&](int k) -> uint16_t { return k < arity(op) ? (uint16_t)slot[a[k]] : 0xFFFF; };
-        if (op == FSIM_OP_REG)
-          d.plain_instr.push_back(make(I_LDREG, d.width[x], (uint16_t)slot[x], 0xFFFF, 0xFFFF, 0xFFFF, (uint32_t)d.imm[x]));
-        else if (op == FSIM_OP_INPUT)
-          d.plain_instr.push_back(make(I_LDIN, d.width[x], (uint16_t)slot[x], 0xFFFF, 0xFFFF, 0xFFFF, (uint32_t)d.imm[x]));
-        else if (op == FSIM_OP_MEMRD)
-          d.plain_instr.push_back(make(I_MEMRD, d.width[x], (uint16_t)slot[x], s(0), 0xFFFF, 0xFFFF, (uint32_t)d.imm[x]));
+        uint16_t sa = (uint16_t)slot[a[0]];
+        auto s = [&](int k) -> uint16_t { return k < arity(op) ? (uint16_t)slot[a[k]] : sa; };
+        if (op == FSIM_OP_MEMRD)
+          d.plain_instr.push_back(make(I_MEMRD, d.width[x], (uint16_t)slot[x], sa, sa, sa, (uint32_t)d.imm[x]));
         else
-          d.plain_instr.push_back(make(op, d.width[x], (uint16_t)slot[x], s(0), s(1), s(2), 0));
+          d.plain_instr.push_back(make(op, d.width[x], (uint16_t)slot[x], sa, s(1), s(2), 0));
       }
     }
     // store level

@@ -25,11 +25,15 @@ struct PlainArgs {
   uint64_t in_first, in_count;
   uint64_t* digest_part;      // [max_cycles][G] or null
   uint64_t digest_first, digest_max;
+  uint64_t* trace;            // phase timestamps [max][G][trace_stride], or null
+  uint64_t trace_first, trace_max;
+  uint32_t trace_stride;      // levels + 3
   uint32_t* flags;            // [G] barrier epochs
   uint32_t* error;            // [0] barrier timeout, [1] input window
   uint32_t R, I;
   uint32_t stage_instr;       // instructions staged in LDS
   uint32_t slot_words;        // u64 words of LDS reserved for slots
+  uint32_t instr_words;       // 16-byte instruction slots staged in LDS
   uint64_t cycle0;            // absolute cycle at the first cycle of this launch
   uint32_t n_cycles;
   uint32_t epoch0;            // barrier epoch before this launch
@@ -38,7 +42,7 @@ struct PlainArgs {
 
 hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t lds_bytes,
                         bool persistent, hipStream_t s);
-hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes);
+hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged);
 hipError_t launch_digest_reduce(const uint64_t* part, uint32_t G, uint64_t n, uint64_t* out,
                                 hipStream_t s);
 hipError_t launch_stim_keys(uint64_t* keys, uint64_t seed_base, uint32_t n_inst, uint32_t I,

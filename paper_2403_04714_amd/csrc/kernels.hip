@@ -96,7 +96,23 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* flags, uint32_t* error, u
   return *lds_abort == 0;
 }
 
-template <bool PERSISTENT>
+struct Dec {
+  uint32_t op, w, dst, a, b, c, aux;
+};
+
+// The 16-byte instruction is read with one 128-bit load and decoded from
+// registers: x = op | w << 8 | cls << 16 | flags << 24, y = dst | a << 16,
+// z = b | c << 16, w = aux.
+__device__ __forceinline__ Dec decode(uint4 r) {
+  Dec d;
+  d.op = r.x & 0xFF; d.w = (r.x >> 8) & 0xFF;
+  d.dst = r.y & 0xFFFF; d.a = r.y >> 16;
+  d.b = r.z & 0xFFFF; d.c = r.z >> 16;
+  d.aux = r.w;
+  return d;
+}
+
+template <bool PERSISTENT, bool STAGED>
 __device__ void plain_body(const PlainArgs& A) {
   extern __shared__ uint64_t lds[];
   __shared__ int abort_flag;
@@ -104,71 +120,125 @@ __device__ void plain_body(const PlainArgs& A) {
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
   const PlainProc pp = A.procs[blockIdx.x];
   uint64_t* slot = lds;
-  const uint32_t n_instr_all = A.levels[pp.lvl_off + pp.n_lvls] - A.levels[pp.lvl_off] + pp.n_wp;
   const uint32_t ibase = A.levels[pp.lvl_off];           // first level instruction
-  const Instr* I = A.instr + ibase;
-  Instr* Is = reinterpret_cast<Instr*>(lds + A.slot_words);
-  if (A.stage_instr) {
-    // stage the level and commit instructions (contiguous) in LDS
-    for (uint32_t i = tid; i < n_instr_all; i += nthr) Is[i] = I[i];
-    I = Is;
-  }
+  const uint32_t n_instr_all = A.levels[pp.lvl_off + pp.n_lvls] - ibase + pp.n_wp;
+  const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + ibase;
+  uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
+  // level table (relative to ibase) after the staged instructions
+  uint32_t* lvs = reinterpret_cast<uint32_t*>(Is + (STAGED ? A.instr_words : 0));
+  if (STAGED)
+    for (uint32_t i = tid; i < n_instr_all; i += nthr) Is[i] = Ig[i];
+  for (uint32_t L = tid; L <= pp.n_lvls; L += nthr) lvs[L] = A.levels[pp.lvl_off + L] - ibase;
   for (uint32_t i = tid; i < pp.n_consts; i += nthr) {
     const Instr in = A.instr[pp.const_off + i];
     slot[in.dst] = A.consts[in.aux];
   }
   if (tid == 0) abort_flag = 0;
   __syncthreads();
-  const uint32_t* lv = A.levels + pp.lvl_off;
+  auto fetch = [&](uint32_t i) -> uint4 { return STAGED ? Is[i] : Ig[i]; };
+  const uint32_t n_lvls = pp.n_lvls;
+  // the level table lives in the lanes of two registers and is read with
+  // v_readlane (no LDS round trip on the level-to-level critical path);
+  // deeper processes fall back to the LDS copy
+  const uint32_t lane = tid & 63;
+  const uint32_t lv_lo = lane <= n_lvls ? lvs[lane] : 0;
+  const uint32_t lv_hi = lane + 64 <= n_lvls ? lvs[lane + 64] : 0;
+  auto lvl = [&](uint32_t L) -> uint32_t {
+    if (L < 64) return (uint32_t)__builtin_amdgcn_readlane((int)lv_lo, (int)L);
+    if (L < 128) return (uint32_t)__builtin_amdgcn_readlane((int)lv_hi, (int)(L - 64));
+    return lvs[L];
+  };
+  // one wave: LDS operations of a wave complete in order, so a level needs no
+  // s_barrier, only a compiler barrier
+  const bool one_wave = nthr <= 64;
   const uint64_t cyc0 = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
+  // phase timestamps: [cycle][workgroup][trace_stride] of the 100 MHz
+  // realtime counter: cycle start, end of every level, commit, barrier
+  uint64_t* trace_row = nullptr;
   for (uint32_t t = 0; t < A.n_cycles; ++t) {
     const uint64_t cyc = cyc0 + t;
     const uint64_t* cur = A.state + (cyc & 1) * A.R;
     uint64_t* nxt = A.state + ((cyc + 1) & 1) * A.R;
     uint64_t dacc = 0;
-    for (uint32_t L = 0; L < pp.n_lvls; ++L) {
-      const uint32_t lo = lv[L] - ibase, hi = lv[L + 1] - ibase;
-      for (uint32_t i = lo + tid; i < hi; i += nthr) {
-        const Instr in = I[i];
-        const uint32_t op = in.op, w = in.w;
-        if (op <= I_MUL && op >= I_AND) {
-          uint64_t a = slot[in.a];
-          uint64_t b = in.b != 0xFFFF ? slot[in.b] : 0;
-          uint64_t c = in.c != 0xFFFF ? slot[in.c] : 0;
-          slot[in.dst] = alu(op, w, a, b, c);
-        } else if (op == I_LDREG) {
-          slot[in.dst] = cur[in.aux] & wmask(w);
-        } else if (op == I_LDIN) {
-          uint64_t x;
-          if (A.in_vals) {
-            if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); x = 0; }
-            else x = A.in_vals[(cyc - A.in_first) * A.I + in.aux];
+    if (A.trace && tid == 0) {
+      const uint64_t k = cyc - A.trace_first;
+      trace_row = k < A.trace_max ? A.trace + (k * gridDim.x + blockIdx.x) * A.trace_stride : nullptr;
+      if (trace_row) trace_row[0] = __builtin_amdgcn_s_memrealtime();
+    }
+    uint32_t lo = lvl(0), hi = lvl(1);
+    uint4 raw = (lo + tid < hi) ? fetch(lo + tid) : make_uint4(0, 0, 0, 0);
+    for (uint32_t L = 0; L < n_lvls; ++L) {
+      // next level's bounds and this thread's first instruction there, issued
+      // before this level's operand reads so that their wait covers it
+      const uint32_t nhi = L + 1 < n_lvls ? lvl(L + 2) : hi;
+      const bool have_next = L + 1 < n_lvls && hi + tid < nhi;
+      uint4 raw_next = have_next ? fetch(hi + tid) : raw;
+      if (L == 0) {
+        // leaf level: current register values and this cycle's inputs
+        for (uint32_t i = lo + tid; i < hi; i += nthr) {
+          if (i != lo + tid) raw = fetch(i);
+          const Dec in = decode(raw);
+          uint64_t v;
+          if (in.op == I_LDREG) {
+            v = cur[in.aux];
+          } else if (A.in_vals) {
+            if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v = 0; }
+            else v = A.in_vals[(cyc - A.in_first) * A.I + in.aux];
           } else {
-            x = hmix(A.in_keys[in.aux] ^ cyc);
+            v = hmix(A.in_keys[in.aux] ^ cyc);
           }
-          slot[in.dst] = x & wmask(A.in_width[in.aux]) & wmask(w);
-        } else if (op == I_MEMRD) {
-          const uint32_t m = in.aux;
-          const uint64_t addr = slot[in.a] % A.mem_depth[m];
-          slot[in.dst] = A.mem[A.mem_off[m] + addr] & wmask(w);
-        } else if (op == I_STREG) {
-          const uint64_t v = slot[in.a] & wmask(w);
-          nxt[in.aux] = v;
-          if (A.digest_part) dacc += hmix((uint64_t)in.aux ^ hmix(v));
-        } else if (op == I_STOUT) {
-          A.outputs[in.aux] = slot[in.a];
+          slot[in.dst] = v & wmask(in.w);   // LDIN widths fold in the port width
+        }
+      } else if (L + 1 < n_lvls) {
+        // operator level: every operand slot is valid (unused ones repeat a),
+        // so the three LDS reads issue together and one wait covers them
+        for (uint32_t i = lo + tid; i < hi; i += nthr) {
+          if (i != lo + tid) raw = fetch(i);
+          const Dec in = decode(raw);
+          uint64_t a = slot[in.a], b = slot[in.b], c = slot[in.c];
+          // keep the three reads (and their single wait) ahead of the
+          // per-opcode branches: without this the compiler sinks each read
+          // into the cases that use it and every case then waits on its own
+          asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
+          if (in.op == I_MEMRD) {
+            const uint64_t depth = A.mem_depth[in.aux];
+            const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
+            slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
+          } else {
+            slot[in.dst] = alu(in.op, in.w, a, b, c);
+          }
+        }
+      } else {
+        // store level: next register values and outputs
+        for (uint32_t i = lo + tid; i < hi; i += nthr) {
+          if (i != lo + tid) raw = fetch(i);
+          const Dec in = decode(raw);
+          const uint64_t v = slot[in.a] & wmask(in.w);
+          if (in.op == I_STREG) {
+            nxt[in.aux] = v;
+            if (A.digest_part) dacc += hmix((uint64_t)in.aux ^ hmix(v));
+          } else {
+            A.outputs[in.aux] = v;
+          }
         }
       }
-      __syncthreads();
+      raw = raw_next;
+      lo = hi;
+      hi = nhi;
+      if (one_wave) asm volatile("" ::: "memory");
+      else __syncthreads();
+      if (trace_row && L + 2 < A.trace_stride) trace_row[L + 1] = __builtin_amdgcn_s_memrealtime();
     }
     // memory commit after every read of this cycle, in port order
     if (tid == 0) {
-      const uint32_t wlo = lv[pp.n_lvls] - ibase;
+      const uint32_t wlo = lvs[n_lvls];
       for (uint32_t k = 0; k < pp.n_wp; ++k) {
-        const Instr in = I[wlo + k];
+        const Dec in = decode(fetch(wlo + k));
         if (slot[in.a] != 0) {
           const uint32_t m = in.aux;
-          A.mem[A.mem_off[m] + slot[in.b] % A.mem_depth[m]] = slot[in.c] & wmask(in.w);
+          const uint64_t depth = A.mem_depth[m], av = slot[in.b];
+          const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
+          A.mem[A.mem_off[m] + addr] = slot[in.c] & wmask(in.w);
         }
       }
     }
@@ -184,6 +254,7 @@ __device__ void plain_body(const PlainArgs& A) {
         if (k < A.digest_max) A.digest_part[k * gridDim.x + blockIdx.x] = s;
       }
     }
+    if (trace_row) trace_row[A.trace_stride - 2] = __builtin_amdgcn_s_memrealtime();
     if (PERSISTENT) {
       if (gridDim.x > 1) {
         if (!grid_barrier(A.flags, A.error, gridDim.x, A.epoch0 + t + 1, &abort_flag)) return;
@@ -191,11 +262,14 @@ __device__ void plain_body(const PlainArgs& A) {
         __syncthreads();
       }
     }
+    if (trace_row) trace_row[A.trace_stride - 1] = __builtin_amdgcn_s_memrealtime();
   }
 }
 
-__global__ void __launch_bounds__(1024) plain_persistent(PlainArgs A) { plain_body<true>(A); }
-__global__ void __launch_bounds__(1024) plain_cycle(PlainArgs A) { plain_body<false>(A); }
+__global__ void __launch_bounds__(1024) plain_persistent(PlainArgs A) { plain_body<true, true>(A); }
+__global__ void __launch_bounds__(1024) plain_cycle(PlainArgs A) { plain_body<false, true>(A); }
+__global__ void __launch_bounds__(1024) plain_persistent_g(PlainArgs A) { plain_body<true, false>(A); }
+__global__ void __launch_bounds__(1024) plain_cycle_g(PlainArgs A) { plain_body<false, false>(A); }
 
 // digest[k] = sum over workgroups of the partials of cycle k
 __global__ void digest_reduce(const uint64_t* part, uint32_t G, uint64_t n, uint64_t* out) {
@@ -227,16 +301,17 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t
                         bool persistent, hipStream_t s) {
   if (persistent) {
     void* args[] = {const_cast<PlainArgs*>(&a)};
-    return hipLaunchCooperativeKernel((const void*)plain_persistent, dim3(G), dim3(threads), args,
-                                      (unsigned)lds_bytes, s);
+    return hipLaunchCooperativeKernel(a.stage_instr ? (const void*)plain_persistent : (const void*)plain_persistent_g,
+                                      dim3(G), dim3(threads), args, (unsigned)lds_bytes, s);
   }
-  hipLaunchKernelGGL(plain_cycle, dim3(G), dim3(threads), lds_bytes, s, a);
+  if (a.stage_instr) hipLaunchKernelGGL(plain_cycle, dim3(G), dim3(threads), lds_bytes, s, a);
+  else hipLaunchKernelGGL(plain_cycle_g, dim3(G), dim3(threads), lds_bytes, s, a);
   return hipGetLastError();
 }
 
-hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, plain_persistent, (int)threads,
-                                                      lds_bytes);
+hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, staged ? plain_persistent : plain_persistent_g,
+                                                      (int)threads, lds_bytes);
 }
 
 hipError_t launch_digest_reduce(const uint64_t* part, uint32_t G, uint64_t n, uint64_t* out,

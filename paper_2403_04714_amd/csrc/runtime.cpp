@@ -63,7 +63,7 @@ struct fsim_design {
   fsim_design_info info{};
   // plain-form program on the device
   DevBuf instr, levels, procs, consts, mem_off, mem_depth, in_width;
-  uint32_t slot_words = 0, max_proc_instr = 0;
+  uint32_t slot_words = 0, max_proc_instr = 0, max_lvls = 0;
 };
 
 struct fsim_sim {
@@ -88,6 +88,9 @@ struct fsim_sim {
   uint64_t* dig_out = nullptr;
   uint64_t dig_first = 0, dig_max = 0;
   DevBuf dig_part;
+  // phase timestamps
+  uint64_t* trace = nullptr;
+  uint64_t trace_first = 0, trace_max = 0;
   // graph mode
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -128,7 +131,7 @@ extern "C" int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_byt
   if (lds_bytes) *lds_bytes = ctx->lds_bytes;
   if (max_coresident_wgs) {
     int b = 0;
-    HIP_TRY(fsim::plain_occupancy(&b, 256, 0));
+    HIP_TRY(fsim::plain_occupancy(&b, 256, 0, true));
     *max_coresident_wgs = (uint32_t)b * ctx->n_cus;
   }
   return FSIM_OK;
@@ -166,12 +169,14 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   s = fsim::encode_plain(d, std::min<uint32_t>(max_slots, 0xFFFE));
   if (!s.ok()) return fail(s);
   // per-process instruction span (levels + commit), for LDS staging
-  uint32_t mx = 0;
+  uint32_t mx = 0, ml = 0;
   for (const auto& pp : d.plain_procs) {
     uint32_t n = d.plain_levels[pp.lvl_off + pp.n_lvls] - d.plain_levels[pp.lvl_off] + pp.n_wp;
     mx = std::max(mx, n);
+    ml = std::max(ml, pp.n_lvls);
   }
   dz->max_proc_instr = mx;
+  dz->max_lvls = ml;
   dz->slot_words = (d.plain_max_slots + 1) & ~1u;
   d.compile_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fsim_design_info& I = dz->info;
@@ -311,7 +316,9 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
   HIP_TRY(hipSetDevice(d->ctx->device));
   // LDS: slots, plus the process's instructions when they fit
   const size_t lds_limit = d->ctx->lds_bytes - kStaticLds;
-  size_t lds = (size_t)d->slot_words * 8;
+  // slots, then (when they fit) the process's instructions, then the level table
+  const size_t lvl_bytes = ((size_t)d->max_lvls + 1) * 4;
+  size_t lds = (size_t)d->slot_words * 8 + lvl_bytes;
   if (lds + (size_t)d->max_proc_instr * sizeof(fsim::Instr) <= lds_limit) {
     s->stage_instr = true;
     lds += (size_t)d->max_proc_instr * sizeof(fsim::Instr);
@@ -320,7 +327,7 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
   s->lds_bytes = lds;
   if (s->launch == FSIM_LAUNCH_PERSISTENT) {
     int b = 0;
-    HIP_TRY(fsim::plain_occupancy(&b, s->threads, lds));
+    HIP_TRY(fsim::plain_occupancy(&b, s->threads, lds, s->stage_instr));
     if ((uint64_t)b * d->ctx->n_cus < s->G)
       return fail(FSIM_E_CAPACITY, "persistent launch: " + std::to_string(s->G) +
                                        " workgroups are not co-resident; use fewer processes");
@@ -394,12 +401,17 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   a.digest_part = s->dig_out ? (uint64_t*)s->dig_part.p : nullptr;
   a.digest_first = s->dig_first;
   a.digest_max = s->dig_max;
+  a.trace = s->trace;
+  a.trace_first = s->trace_first;
+  a.trace_max = s->trace_max;
+  a.trace_stride = dd->max_lvls + 3;
   a.flags = s->flags;
   a.error = s->error;
   a.R = dd->d.R;
   a.I = dd->d.I;
   a.stage_instr = s->stage_instr ? 1 : 0;
   a.slot_words = dd->slot_words;
+  a.instr_words = dd->max_proc_instr;
   a.cycle_ptr = nullptr;
   return a;
 }
@@ -599,5 +611,32 @@ extern "C" int fsim_enable_digest(fsim_sim* s, uint64_t* dev_out, uint64_t max_c
     s->gexec = nullptr;
     s->graph = nullptr;
   }
+  return FSIM_OK;
+}
+
+extern "C" int fsim_enable_trace(fsim_sim* s, uint64_t* dev_out, uint64_t max_cycles, uint32_t* stride) {
+  if (!s) return fail(FSIM_E_ARG, "sim is NULL");
+  if (s->poisoned) return fail(FSIM_E_STATE, "sim is poisoned by an earlier device error");
+  HIP_TRY(hipStreamSynchronize(s->d->ctx->stream));
+  if (stride) *stride = s->d->max_lvls + 3;
+  s->trace = max_cycles ? dev_out : nullptr;
+  s->trace_first = s->cycle;
+  s->trace_max = dev_out ? max_cycles : 0;
+  if (s->gexec) {
+    (void)hipGraphExecDestroy(s->gexec);
+    (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+  }
+  return FSIM_OK;
+}
+
+extern "C" int fsim_sim_layout(const fsim_sim* s, uint32_t* workgroups, uint32_t* threads,
+                               uint32_t* launch, uint32_t* staged) {
+  if (!s) return fail(FSIM_E_ARG, "sim is NULL");
+  if (workgroups) *workgroups = s->G;
+  if (threads) *threads = s->threads;
+  if (launch) *launch = s->launch;
+  if (staged) *staged = s->stage_instr ? 1 : 0;
   return FSIM_OK;
 }

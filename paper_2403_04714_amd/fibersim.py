@@ -98,6 +98,8 @@ SIGNATURES = {
     "fsim_write_mem": (_I, [_P, _U32, _U32, _P]),
     "fsim_set_cycle": (_I, [_P, _U64]),
     "fsim_enable_digest": (_I, [_P, _P, _U64]),
+    "fsim_enable_trace": (_I, [_P, _P, _U64, _P]),
+    "fsim_sim_layout": (_I, [_P, _P, _P, _P, _P]),
 }
 
 _lib = None
@@ -307,6 +309,28 @@ class Sim:
                                    device=f"cuda:{self.design.ctx.device}")
         _check(lib().fsim_enable_digest(self._h, C.c_void_p(self._digest.data_ptr()), max_cycles),
                "fsim_enable_digest")
+
+    def layout(self) -> dict:
+        g_, t_, l_, s_ = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(lib().fsim_sim_layout(self._h, C.byref(g_), C.byref(t_), C.byref(l_), C.byref(s_)),
+               "fsim_sim_layout")
+        return dict(workgroups=g_.value, threads=t_.value, launch=l_.value, staged=bool(s_.value))
+
+    def enable_trace(self, max_cycles: int):
+        """Phase timestamps (100 MHz counter) per cycle, workgroup and level."""
+        import torch
+        lay = self.layout()
+        stride = C.c_uint32()
+        _check(lib().fsim_enable_trace(self._h, None, 0, C.byref(stride)), "fsim_enable_trace")
+        self._trace_shape = (max_cycles, lay["workgroups"], stride.value)
+        self._trace = torch.zeros(max_cycles * lay["workgroups"] * stride.value, dtype=torch.int64,
+                                  device=f"cuda:{self.design.ctx.device}")
+        _check(lib().fsim_enable_trace(self._h, C.c_void_p(self._trace.data_ptr()), max_cycles, None),
+               "fsim_enable_trace")
+
+    def trace(self) -> np.ndarray:
+        self.sync()
+        return self._trace.cpu().numpy().view(np.uint64).reshape(self._trace_shape)
 
     def digests(self) -> np.ndarray:
         self.sync()

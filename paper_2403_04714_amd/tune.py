@@ -1,0 +1,112 @@
+"""Autotuner: picks the launch configuration of a design by timing short runs.
+
+The simulation rate is not monotone in the number of processes (Parendi
+Sec. 6.3: the "staircase" of equal-size stragglers, and Sec. 4: t_sync and
+t_comm grow with parallelism while t_comp falls), so the configuration is
+measured rather than derived.  Knobs: packing target (processes = workgroups
+of the plain kernel), threads per workgroup, launch mode (persistent kernel
+with grid barrier, or per-cycle launches captured in a hipGraph).  Results are
+cached per (design hash, instances, device name) in a JSON file.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+import numpy as np
+
+from . import fibersim as F
+
+CACHE = os.environ.get("FSIM_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                         "tune_cache.json"))
+
+
+def design_hash(nl) -> str:
+    h = hashlib.sha1()
+    for f in ("op", "width", "arg", "imm", "reg_width", "reg_init", "reg_next", "in_width",
+              "out_node", "mem_depth", "mem_width", "wp_mem", "wp_en", "wp_addr", "wp_data"):
+        h.update(np.ascontiguousarray(getattr(nl, f)).tobytes())
+    return h.hexdigest()[:16]
+
+
+def _device_name():
+    import torch
+    return torch.cuda.get_device_name(0)
+
+
+def _load_cache():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(c):
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def time_plain(ctx, design, launch, threads, cycles, seed=0x5EED0000, reps=2):
+    """Seconds per simulated cycle (best of reps), torch events on ctx's stream."""
+    import torch
+    s = F.Sim(design, 1, launch=launch, wg_threads=threads, seed=seed)
+    s.step(min(200, cycles))
+    s.sync()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.torch_stream)
+        s.step(cycles)
+        e1.record(ctx.torch_stream)
+        e1.synchronize()
+        s.sync()
+        best = min(best, e0.elapsed_time(e1) / 1e3 / cycles)
+    del s
+    return best
+
+
+def tune_plain(ctx, nl, targets=(16, 32, 64, 128, 256), threads=(256, 512, 1024),
+               launches=(F.LAUNCH_PERSISTENT, F.LAUNCH_GRAPH), cycles=2000, use_cache=True,
+               verbose=False):
+    """Returns (best, trials): best = dict(target, threads, launch, s_per_cycle)."""
+    key = f"plain/{design_hash(nl)}/{_device_name()}"
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return cache[key], []
+    trials = []
+    best = None
+    for t in targets:
+        try:
+            d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=t)
+        except F.FsimError as e:
+            if verbose:
+                print(f"tune: target {t}: {e}", flush=True)
+            continue
+        for th in threads:
+            for la in launches:
+                try:
+                    spc = time_plain(ctx, d, la, th, cycles)
+                except F.FsimError as e:
+                    if verbose:
+                        print(f"tune: target {t} threads {th} launch {la}: {e}", flush=True)
+                    continue
+                rec = dict(target=t, processes=d.info()["n_processes"], threads=th, launch=la,
+                           s_per_cycle=spc)
+                trials.append(rec)
+                if verbose:
+                    print(f"tune: {rec}  ({1/spc/1e3:.1f} kHz)", flush=True)
+                if best is None or spc < best["s_per_cycle"]:
+                    best = rec
+        del d
+    if best is None:
+        raise RuntimeError("autotuner found no runnable configuration")
+    if use_cache:
+        cache = _load_cache()
+        cache[key] = best
+        _save_cache(cache)
+    return best, trials
