@@ -178,15 +178,24 @@ void fsim_design_free(fsim_design* d);
 #define FSIM_LAUNCH_PER_CYCLE   2  /* one launch per cycle (kernel boundary = barrier) */
 #define FSIM_LAUNCH_GRAPH       3  /* per-cycle launches captured in a hipGraph */
 
+#define FSIM_FORM_AUTO     0   /* plain for one instance, batched for more   */
+#define FSIM_FORM_BATCHED  1   /* one lane per instance, even for one        */
+#define FSIM_FORM_PLAIN    2   /* level-parallel workgroups (one instance)   */
+
 typedef struct fsim_sim_opts {
-  uint32_t launch;          /* FSIM_LAUNCH_*                                */
-  uint32_t wg_threads;      /* plain form: threads per workgroup, 0 = auto  */
+  uint32_t launch;          /* FSIM_LAUNCH_*; the batched form always ends a
+                               cycle at a kernel boundary (PER_CYCLE/GRAPH)  */
+  uint32_t wg_threads;      /* plain: threads per workgroup (64..1024);
+                               batched: 64 x tiles of 64 instances per
+                               workgroup (64..256); 0 = auto                 */
   uint32_t grid;            /* workgroups of the persistent kernel, 0 = auto*/
   uint32_t graph_cycles;    /* cycles per captured graph (GRAPH mode)       */
+  uint32_t form;            /* FSIM_FORM_*                                  */
 } fsim_sim_opts;
 
 /* Device bytes a sim needs for n_instances (state x2, memories, outputs,
- * stimulus keys, scratch); what fsim_sim_create's workspace must hold. */
+ * stimulus keys, scratch); what fsim_sim_create's workspace must hold.  For
+ * one instance it covers both forms. */
 int fsim_sim_footprint(const fsim_design* d, uint32_t n_instances, size_t* device_bytes);
 
 /* workspace: caller-owned device memory of at least fsim_sim_footprint()

@@ -516,10 +516,13 @@ Status encode_plain(Design& d, uint32_t max_slots) {
   d.plain_procs.assign(d.P, PlainProc{});
   d.plain_levels.clear();
   d.plain_instr.clear();
+  d.plain_chunks.clear();
   d.consts.clear();
   d.plain_max_slots = 0;
   d.plain_max_instr = 0;
+  d.plain_max_chunks = 0;
   std::vector<uint32_t> slot(d.N, UINT32_MAX);
+  std::vector<uint32_t> lvl_nodes;
   for (uint32_t p = 0; p < d.P; ++p) {
     const uint32_t lo = d.proc_off[p], hi = d.proc_off[p + 1];
     const uint32_t n = hi - lo;
@@ -529,93 +532,297 @@ Status encode_plain(Design& d, uint32_t max_slots) {
     for (uint32_t i = lo; i < hi; ++i) slot[d.proc_nodes[i]] = i - lo;
     PlainProc& pp = d.plain_procs[p];
     pp.n_slots = n;
-    const uint32_t base = (uint32_t)d.plain_instr.size();
     // constant prologue
-    pp.const_off = base;
+    pp.const_off = (uint32_t)d.plain_instr.size();
     for (uint32_t i = lo; i < hi; ++i) {
       uint32_t x = d.proc_nodes[i];
       if (d.op[x] != FSIM_OP_CONST) continue;
       uint64_t v = d.imm[x] & (~0ull >> (64 - d.width[x]));
-      d.plain_instr.push_back(make(I_LDCONST, d.width[x], (uint16_t)slot[x], 0xFFFF, 0xFFFF, 0xFFFF,
+      d.plain_instr.push_back(make(I_LDCONST, d.width[x], (uint16_t)slot[x], 0, 0, 0,
                                    (uint32_t)d.consts.size()));
       d.consts.push_back(v);
     }
     pp.n_consts = (uint32_t)d.plain_instr.size() - pp.const_off;
-    // levels: 0 = register and input loads (always present, possibly empty);
-    // then one level per operator level present in the process (empty levels
-    // are dropped), sorted by opcode and width so wavefronts are uniform;
-    // then the store level.  Unused operand slots repeat operand a so that
-    // the kernel can read all three without tests.
+    pp.instr_off = (uint32_t)d.plain_instr.size();
+    pp.chunk_off = (uint32_t)d.plain_chunks.size();
     pp.lvl_off = (uint32_t)d.plain_levels.size();
-    std::vector<uint32_t> lvl_nodes;
-    uint32_t i = lo;
+    // emits one level from a list of instructions sorted by opcode
+    auto emit_level = [&](const std::vector<Instr>& ins) {
+      d.plain_levels.push_back((uint32_t)d.plain_chunks.size() - pp.chunk_off);
+      size_t k = 0;
+      while (k < ins.size()) {
+        size_t e = k;
+        while (e < ins.size() && e - k < 64 && ins[e].op == ins[k].op) ++e;
+        uint32_t start = (uint32_t)d.plain_instr.size() - pp.instr_off;
+        for (size_t j = k; j < e; ++j) d.plain_instr.push_back(ins[j]);
+        d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), ins[k].op));
+        k = e;
+      }
+    };
+    std::vector<Instr> ins;
     uint32_t n_lvls = 0;
-    d.plain_levels.push_back((uint32_t)d.plain_instr.size());
-    n_lvls++;
+    // level 0: register and input loads (always present, possibly empty)
+    uint32_t i = lo;
     while (i < hi && d.level[d.proc_nodes[i]] == 0) {
       uint32_t x = d.proc_nodes[i++];
       if (d.op[x] == FSIM_OP_REG)
-        d.plain_instr.push_back(make(I_LDREG, d.width[x], (uint16_t)slot[x], 0, 0, 0, (uint32_t)d.imm[x]));
+        ins.push_back(make(I_LDREG, d.width[x], (uint16_t)slot[x], 0, 0, 0, (uint32_t)d.imm[x]));
       else if (d.op[x] == FSIM_OP_INPUT)   // the width folds in the port's own width
-        d.plain_instr.push_back(make(I_LDIN, std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]),
-                                     (uint16_t)slot[x], 0, 0, 0, (uint32_t)d.imm[x]));
+        ins.push_back(make(I_LDIN, std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]),
+                           (uint16_t)slot[x], 0, 0, 0, (uint32_t)d.imm[x]));
     }
+    std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
+    emit_level(ins);
+    n_lvls++;
+    // operator levels (empty levels dropped); unused operand slots repeat a
     while (i < hi) {
       uint32_t L = d.level[d.proc_nodes[i]];
       lvl_nodes.clear();
       while (i < hi && d.level[d.proc_nodes[i]] == L) lvl_nodes.push_back(d.proc_nodes[i++]);
-      std::stable_sort(lvl_nodes.begin(), lvl_nodes.end(), [&](uint32_t a, uint32_t b) {
-        if (d.op[a] != d.op[b]) return d.op[a] < d.op[b];
-        return (d.width[a] > 32) < (d.width[b] > 32);
-      });
-      d.plain_levels.push_back((uint32_t)d.plain_instr.size());
-      n_lvls++;
+      ins.clear();
       for (uint32_t x : lvl_nodes) {
         uint8_t op = d.op[x];
         const uint32_t* a = &d.arg[3ull * x];
         uint16_t sa = (uint16_t)slot[a[0]];
         auto s = [&](int k) -> uint16_t { return k < arity(op) ? (uint16_t)slot[a[k]] : sa; };
         if (op == FSIM_OP_MEMRD)
-          d.plain_instr.push_back(make(I_MEMRD, d.width[x], (uint16_t)slot[x], sa, sa, sa, (uint32_t)d.imm[x]));
+          ins.push_back(make(I_MEMRD, d.width[x], (uint16_t)slot[x], sa, sa, sa, (uint32_t)d.imm[x]));
         else
-          d.plain_instr.push_back(make(op, d.width[x], (uint16_t)slot[x], sa, s(1), s(2), 0));
+          ins.push_back(make(op, d.width[x], (uint16_t)slot[x], sa, s(1), s(2), 0));
       }
+      std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
+      emit_level(ins);
+      n_lvls++;
     }
     // store level
-    d.plain_levels.push_back((uint32_t)d.plain_instr.size());
-    n_lvls++;
+    ins.clear();
     for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
       uint32_t s = d.psinks[k];
       if (s < d.R)
-        d.plain_instr.push_back(make(I_STREG, d.reg_width[s], 0xFFFF, (uint16_t)slot[d.reg_next[s]], 0xFFFF, 0xFFFF, s));
+        ins.push_back(make(I_STREG, d.reg_width[s], 0, (uint16_t)slot[d.reg_next[s]], 0, 0, s));
       else if (s >= d.R + d.W) {
         uint32_t o = s - d.R - d.W;
-        d.plain_instr.push_back(make(I_STOUT, d.width[d.out_node[o]], 0xFFFF, (uint16_t)slot[d.out_node[o]], 0xFFFF, 0xFFFF, o));
+        ins.push_back(make(I_STOUT, d.width[d.out_node[o]], 0, (uint16_t)slot[d.out_node[o]], 0, 0, o));
       }
     }
-    d.plain_levels.push_back((uint32_t)d.plain_instr.size());
+    std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
+    emit_level(ins);
+    n_lvls++;
+    d.plain_levels.push_back((uint32_t)d.plain_chunks.size() - pp.chunk_off);
     pp.n_lvls = n_lvls;
+    pp.n_chunks = (uint32_t)d.plain_chunks.size() - pp.chunk_off;
+    pp.n_instr = (uint32_t)d.plain_instr.size() - pp.instr_off;
+    if (pp.n_instr > 0xFFFF)
+      return Status::err(FSIM_E_CAPACITY, fmt("process %llu has %llu instructions; use more processes", p, pp.n_instr));
     // write-port commit, in port order
-    pp.wp_off = (uint32_t)d.plain_instr.size();
     for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
       uint32_t s = d.psinks[k];
       if (s >= d.R && s < d.R + d.W) {
         uint32_t q = s - d.R;
-        d.plain_instr.push_back(make(I_WPORT, d.mem_width[d.wp_mem[q]], 0xFFFF, (uint16_t)slot[d.wp_en[q]],
+        d.plain_instr.push_back(make(I_WPORT, d.mem_width[d.wp_mem[q]], 0, (uint16_t)slot[d.wp_en[q]],
                                      (uint16_t)slot[d.wp_addr[q]], (uint16_t)slot[d.wp_data[q]], d.wp_mem[q]));
       }
     }
-    pp.n_wp = (uint32_t)d.plain_instr.size() - pp.wp_off;
+    pp.n_wp = (uint32_t)d.plain_instr.size() - pp.instr_off - pp.n_instr;
     d.plain_max_slots = std::max(d.plain_max_slots, n);
-    d.plain_max_instr = std::max(d.plain_max_instr, (uint32_t)d.plain_instr.size() - base);
+    d.plain_max_instr = std::max(d.plain_max_instr, pp.n_instr + pp.n_wp);
+    d.plain_max_chunks = std::max(d.plain_max_chunks, pp.n_chunks);
+    d.max_plain_lvls = std::max(d.max_plain_lvls, n_lvls);
     for (uint32_t j = lo; j < hi; ++j) slot[d.proc_nodes[j]] = UINT32_MAX;
   }
   return {};
 }
 
+// Batched form: each process becomes one sequential, wave-uniform stream.
+// Order: for every sink in turn, a depth-first post-order of its cone (the
+// operand with the deeper subtree first, so fewer values are live at once);
+// each node is emitted once, leaves just before their first use.  Slots are
+// allocated per class (1-bit masks, <= 32-bit, <= 64-bit) by liveness; a slot
+// is released after its last use.  Constants are not given slots: an operand
+// of class K names an entry of the constant pool.  Register stores follow the
+// instruction that produces the value; the memory write ports come last.
 Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
-  (void)d; (void)max_slots_per_class;
-  return Status::err(FSIM_E_UNSUPPORTED, "batched form not built yet");
+  d.batch_procs.assign(d.P, BatchProc{});
+  d.batch_instr.clear();
+  d.batch_consts.clear();
+  d.batch_slots[0] = d.batch_slots[1] = d.batch_slots[2] = 0;
+  // internal register numbering: per class, in register order
+  d.reg_cls_idx.assign(d.R, 0);
+  d.reg_count[0] = d.reg_count[1] = d.reg_count[2] = 0;
+  for (uint32_t r = 0; r < d.R; ++r) {
+    uint8_t k = class_of_width(d.reg_width[r]);
+    d.reg_cls_idx[r] = ((uint32_t)k << 30) | d.reg_count[k]++;
+  }
+  std::vector<uint32_t> emitted(d.N, UINT32_MAX);   // instruction index per node (this process)
+  std::vector<uint32_t> last_use(d.N, 0), slot_of(d.N, UINT32_MAX), kidx(d.N, UINT32_MAX);
+  std::vector<uint32_t> order, stack;
+  std::vector<uint8_t> cls_of(d.N, 0);
+  std::vector<uint32_t> sub(d.N, 0);                // subtree size estimate for ordering
+  for (uint32_t n = 0; n < d.N; ++n) {
+    cls_of[n] = class_of_width(d.width[n]);
+    uint32_t s = 1;
+    for (int k = 0; k < arity(d.op[n]); ++k) s += std::min<uint32_t>(sub[d.arg[3ull * n + k]], 1u << 20);
+    sub[n] = std::min<uint32_t>(s, 1u << 20);       // nodes precede their users in level order only,
+  }                                                  // so this is a rough size (operands may follow)
+  for (uint32_t p = 0; p < d.P; ++p) {
+    BatchProc& bp = d.batch_procs[p];
+    bp.instr_off = (uint32_t)d.batch_instr.size();
+    bp.const_off = (uint32_t)d.batch_consts.size();
+    order.clear();
+    // ---- order: DFS post-order from each sink
+    auto visit = [&](uint32_t root) {
+      if (emitted[root] != UINT32_MAX) return;
+      stack.push_back(root);
+      while (!stack.empty()) {
+        uint32_t x = stack.back();
+        if (emitted[x] != UINT32_MAX) { stack.pop_back(); continue; }
+        // push operands not yet emitted, larger subtree last (visited first)
+        uint32_t ops[3]; int na = 0;
+        for (int k = 0; k < arity(d.op[x]); ++k) {
+          uint32_t y = d.arg[3ull * x + k];
+          if (emitted[y] == UINT32_MAX) ops[na++] = y;
+        }
+        if (na == 0) {
+          stack.pop_back();
+          emitted[x] = (uint32_t)order.size();
+          order.push_back(x);
+          continue;
+        }
+        std::sort(ops, ops + na, [&](uint32_t a, uint32_t b) { return sub[a] < sub[b]; });
+        for (int k = 0; k < na; ++k) stack.push_back(ops[k]);
+      }
+    };
+    for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
+      uint32_t s = d.psinks[k];
+      if (s < d.R) visit(d.reg_next[s]);
+      else if (s < d.R + d.W) { uint32_t q = s - d.R; visit(d.wp_en[q]); visit(d.wp_addr[q]); visit(d.wp_data[q]); }
+      else visit(d.out_node[s - d.R - d.W]);
+    }
+    // ---- liveness (positions in order; sinks read at their store point)
+    const uint32_t n_ord = (uint32_t)order.size();
+    for (uint32_t i = 0; i < n_ord; ++i) last_use[order[i]] = i;
+    for (uint32_t i = 0; i < n_ord; ++i) {
+      uint32_t x = order[i];
+      for (int k = 0; k < arity(d.op[x]); ++k) last_use[d.arg[3ull * x + k]] = std::max(last_use[d.arg[3ull * x + k]], i);
+    }
+    // register stores happen right after the producing node; write ports and
+    // outputs need their values until the end
+    std::vector<std::vector<uint32_t>> stores_after(n_ord);
+    for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
+      uint32_t s = d.psinks[k];
+      if (s < d.R) stores_after[emitted[d.reg_next[s]]].push_back(s);
+      else if (s < d.R + d.W) {
+        uint32_t q = s - d.R;
+        last_use[d.wp_en[q]] = last_use[d.wp_addr[q]] = last_use[d.wp_data[q]] = n_ord;
+      } else {
+        stores_after[emitted[d.out_node[s - d.R - d.W]]].push_back(s);
+      }
+    }
+    // ---- slot allocation per class and emission
+    std::vector<uint32_t> free_list[3];
+    uint32_t used[3] = {0, 0, 0};
+    std::vector<std::vector<uint32_t>> release_at(n_ord + 1);
+    for (uint32_t i = 0; i < n_ord; ++i) {
+      uint32_t x = order[i];
+      if (d.op[x] == FSIM_OP_CONST) continue;
+      release_at[std::min(last_use[x], n_ord)].push_back(x);
+    }
+    auto get_slot = [&](uint8_t k) -> uint32_t {
+      if (!free_list[k].empty()) { uint32_t s = free_list[k].back(); free_list[k].pop_back(); return s; }
+      return used[k]++;
+    };
+    auto operand = [&](uint32_t y, uint8_t& cls) -> uint16_t {
+      if (d.op[y] == FSIM_OP_CONST) { cls = 3; return (uint16_t)kidx[y]; }
+      cls = cls_of[y];
+      return (uint16_t)slot_of[y];
+    };
+    for (uint32_t i = 0; i < n_ord; ++i) {
+      uint32_t x = order[i];
+      uint8_t op = d.op[x];
+      if (op == FSIM_OP_CONST) {
+        uint32_t ci = (uint32_t)d.batch_consts.size() - bp.const_off;
+        if (ci > 0xFFFF) return Status::err(FSIM_E_CAPACITY, fmt("process %llu has too many constants", p));
+        kidx[x] = ci;
+        d.batch_consts.push_back(d.imm[x] & (~0ull >> (64 - d.width[x])));
+      } else {
+        // operands are read before the destination slot is taken, so a slot
+        // freed by this instruction's last operand use may be reused by it
+        Instr in = make(0, d.width[x], 0, 0, 0, 0, 0);
+        uint8_t ca = 0, cb = 0, cc = 0;
+        const uint32_t* a = &d.arg[3ull * x];
+        if (op == FSIM_OP_REG) {
+          const uint32_t r = (uint32_t)d.imm[x];
+          in.op = I_LDREG;
+          in.aux = d.reg_cls_idx[r] & 0x3FFFFFFF;
+          in.b = (uint16_t)(r & 0xFFFF); in.c = (uint16_t)(r >> 16);
+          ca = class_of_width(d.reg_width[r]);            // the state array it comes from
+        } else if (op == FSIM_OP_INPUT) {
+          in.op = I_LDIN;
+          in.w = std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]);
+          in.aux = (uint32_t)d.imm[x];
+        } else if (op == FSIM_OP_MEMRD) {
+          in.op = I_MEMRD; in.aux = (uint32_t)d.imm[x];
+          in.a = operand(a[0], ca);
+        } else {
+          in.op = op;
+          in.a = operand(a[0], ca);
+          if (arity(op) > 1) in.b = operand(a[1], cb); else { in.b = in.a; cb = ca; }
+          if (arity(op) > 2) in.c = operand(a[2], cc); else { in.c = in.a; cc = ca; }
+        }
+        for (uint32_t y : release_at[i]) if (y != x && slot_of[y] != UINT32_MAX) free_list[cls_of[y]].push_back(slot_of[y]);
+        const uint8_t kd = cls_of[x];
+        slot_of[x] = get_slot(kd);
+        in.dst = (uint16_t)slot_of[x];
+        in.cls = (uint8_t)(kd | (ca << 2) | (cb << 4) | (cc << 6));
+        d.batch_instr.push_back(in);
+        if (last_use[x] == i && d.op[x] != FSIM_OP_CONST) {
+          // dead on arrival (only a sink's store reads it): released after the stores
+        }
+      }
+      for (uint32_t s : stores_after[i]) {
+        uint8_t ca;
+        uint16_t sa = operand(x, ca);
+        if (s < d.R) {
+          Instr st = make(I_STREG, d.reg_width[s], 0, sa, (uint16_t)(s & 0xFFFF), (uint16_t)(s >> 16),
+                          d.reg_cls_idx[s] & 0x3FFFFFFF);
+          st.cls = (uint8_t)(class_of_width(d.reg_width[s]) | (ca << 2));
+          d.batch_instr.push_back(st);
+        } else {
+          uint32_t o = s - d.R - d.W;
+          Instr st = make(I_STOUT, d.width[d.out_node[o]], 0, sa, 0, 0, o);
+          st.cls = (uint8_t)(ca << 2);
+          d.batch_instr.push_back(st);
+        }
+      }
+      if (last_use[x] == i && slot_of[x] != UINT32_MAX && d.op[x] != FSIM_OP_CONST) {
+        free_list[cls_of[x]].push_back(slot_of[x]);
+        slot_of[x] = UINT32_MAX - 1;       // released (value no longer needed)
+      }
+    }
+    // write ports, in port order, after every read of the process
+    for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
+      uint32_t s = d.psinks[k];
+      if (s < d.R || s >= d.R + d.W) continue;
+      uint32_t q = s - d.R;
+      uint8_t ca, cb, cc;
+      uint16_t sa = operand(d.wp_en[q], ca), sb = operand(d.wp_addr[q], cb), sc = operand(d.wp_data[q], cc);
+      Instr wp = make(I_WPORT, d.mem_width[d.wp_mem[q]], 0, sa, sb, sc, d.wp_mem[q]);
+      wp.cls = (uint8_t)((ca << 2) | (cb << 4) | (cc << 6));
+      d.batch_instr.push_back(wp);
+    }
+    bp.n_instr = (uint32_t)d.batch_instr.size() - bp.instr_off;
+    bp.n_consts = (uint32_t)d.batch_consts.size() - bp.const_off;
+    for (int k = 0; k < 3; ++k) {
+      bp.slots[k] = used[k];
+      d.batch_slots[k] = std::max(d.batch_slots[k], used[k]);
+      if (max_slots_per_class && used[k] > max_slots_per_class[k])
+        return Status::err(FSIM_E_CAPACITY,
+                           fmt("process %llu needs %llu live slots of one class; use more processes", p, used[k]));
+    }
+    for (uint32_t i = 0; i < n_ord; ++i) { emitted[order[i]] = UINT32_MAX; slot_of[order[i]] = UINT32_MAX; kidx[order[i]] = UINT32_MAX; last_use[order[i]] = 0; }
+  }
+  d.batch_encoded = true;
+  return {};
 }
 
 }  // namespace fsim

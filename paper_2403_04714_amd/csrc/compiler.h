@@ -50,15 +50,19 @@ struct Design {
 
   // ---- encoded plain-form program (one process per workgroup)
   std::vector<PlainProc> plain_procs;   // [P]
-  std::vector<uint32_t> plain_levels;   // level start offsets, per process
+  std::vector<uint32_t> plain_levels;   // per process: chunk index where each level starts
+  std::vector<uint32_t> plain_chunks;   // opcode-uniform chunks of <= 64 instructions
   std::vector<Instr> plain_instr;
   std::vector<uint64_t> consts;         // constant pool (LD_CONST aux index)
   uint32_t plain_max_slots = 0;
   uint32_t plain_max_instr = 0;
+  uint32_t plain_max_chunks = 0;
+  uint32_t max_plain_lvls = 0;
 
   // ---- encoded batched-form program (one wave per instance tile)
   std::vector<BatchProc> batch_procs;   // [P]
   std::vector<Instr> batch_instr;
+  std::vector<uint64_t> batch_consts;   // per-process constant pools, back to back
   uint32_t batch_slots[3] = {0, 0, 0};  // max live slots per class over procs
   bool batch_encoded = false;
   // internal register numbering of the batched layout: class + index

@@ -24,8 +24,9 @@ enum : uint8_t {
 };
 
 // Slot classes of the batched form: 1-bit values are 64-lane ballot masks,
-// narrow values one u32 per lane, wide values one u64 per lane.
-enum : uint8_t { C_B = 0, C_W = 1, C_D = 2 };
+// narrow values one u32 per lane, wide values one u64 per lane; class K is an
+// operand read from the process's constant pool (wave-uniform).
+enum : uint8_t { C_B = 0, C_W = 1, C_D = 2, C_K = 3 };
 inline uint8_t class_of_width(uint32_t w) { return w == 1 ? C_B : (w <= 32 ? C_W : C_D); }
 
 struct Instr {
@@ -39,20 +40,31 @@ struct Instr {
 static_assert(sizeof(Instr) == 16, "Instr must be 16 bytes");
 
 // Plain form: per process, a constant prologue (run once per launch), then
-// levels 0..n_lvls-1 (leaf loads, operator levels, the store level), each a
-// contiguous instruction range; then the write-port commit, run in order by
-// one thread after every read of the cycle.
+// levels 0..n_lvls-1 (leaf loads, operator levels, the store level); the
+// instructions of a level are grouped by opcode and cut into chunks of at most
+// 64, so that a wavefront always runs one opcode (scalar dispatch, no
+// divergence).  A chunk is one u32: start (16 bits, relative to the first
+// level instruction) | (count - 1) << 16 (6 bits) | opcode << 22.  After the
+// levels comes the write-port commit, run in order by one thread after every
+// read of the cycle.
 struct PlainProc {
-  uint32_t lvl_off;    // index into the level table: n_lvls + 1 entries
+  uint32_t lvl_off;    // index into the level table: n_lvls + 1 chunk indices
   uint32_t n_lvls;
   uint32_t const_off;  // prologue instructions
   uint32_t n_consts;
-  uint32_t wp_off;     // commit instructions
-  uint32_t n_wp;
+  uint32_t instr_off;  // first level instruction
+  uint32_t n_instr;    // level instructions; the commit follows them
+  uint32_t chunk_off;  // first chunk
+  uint32_t n_chunks;
+  uint32_t n_wp;       // commit instructions
   uint32_t n_slots;    // u64 LDS slots used
-  uint32_t pad;
+  uint32_t pad[2];
 };
-static_assert(sizeof(PlainProc) == 32, "PlainProc must be 32 bytes");
+static_assert(sizeof(PlainProc) == 48, "PlainProc must be 48 bytes");
+
+inline uint32_t make_chunk(uint32_t start, uint32_t count, uint32_t op) {
+  return start | ((count - 1) << 16) | (op << 22);
+}
 
 // Batched form: per process, one sequential stream evaluated by a wave for
 // 64 instances at a time; slots are per class.
@@ -60,7 +72,9 @@ struct BatchProc {
   uint32_t instr_off;
   uint32_t n_instr;
   uint32_t slots[3];   // live slots needed per class
-  uint32_t pad[3];
+  uint32_t const_off;  // constant pool of the process (class K operands)
+  uint32_t n_consts;
+  uint32_t pad;
 };
 static_assert(sizeof(BatchProc) == 32, "BatchProc must be 32 bytes");
 

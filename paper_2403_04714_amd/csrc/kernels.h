@@ -11,7 +11,8 @@ namespace fsim {
 
 struct PlainArgs {
   const Instr* instr;
-  const uint32_t* levels;
+  const uint32_t* levels;      // per process: chunk index where each level starts
+  const uint32_t* chunks;      // opcode-uniform chunks
   const PlainProc* procs;
   const uint64_t* consts;
   uint64_t* state;            // [2][R]: cur = cycle & 1
@@ -34,12 +35,43 @@ struct PlainArgs {
   uint32_t stage_instr;       // instructions staged in LDS
   uint32_t slot_words;        // u64 words of LDS reserved for slots
   uint32_t instr_words;       // 16-byte instruction slots staged in LDS
+  uint32_t chunk_words;       // u32 chunk words reserved in LDS
   uint64_t cycle0;            // absolute cycle at the first cycle of this launch
   uint32_t n_cycles;
   uint32_t epoch0;            // barrier epoch before this launch
   const uint64_t* cycle_ptr;  // graph mode: absolute base cycle in device memory
 };
 
+// Batched form: one wave per (process, tile of 64 instances).  State is kept
+// per register class: 1-bit registers as 64-instance masks [reg][tile],
+// narrow ones as u32 [reg][instance], wide ones as u64 [reg][instance], each
+// double-buffered by cycle parity.
+struct BatchArgs {
+  const Instr* instr;
+  const BatchProc* procs;
+  const uint64_t* consts;
+  uint64_t* stB;              // [2][nB][n_tiles]
+  uint32_t* stW;              // [2][nW][n_pad]
+  uint64_t* stD;              // [2][nD][n_pad]
+  uint64_t* outputs;          // [O][n_pad]
+  uint64_t* mem;              // [words][n_pad]
+  const uint64_t* mem_off;    // [M]
+  const uint32_t* mem_depth;  // [M]
+  const uint64_t* keys;       // [I][n_pad]: H(H(seed_i) ^ p)
+  const uint64_t* in_vals;    // explicit [n][I][n_inst] or null
+  uint64_t in_first, in_count;
+  uint64_t* digest;           // [max][n_inst] or null
+  uint64_t digest_first, digest_max;
+  uint32_t* error;
+  const uint64_t* cycle_ptr;  // graph mode: base cycle in device memory
+  uint64_t cycle0;
+  uint32_t P, n_tiles, tpw, n_inst, n_pad, I;
+  uint32_t nB, nW, nD;
+  uint32_t slotsB, slotsW, slotsD;
+};
+
+hipError_t launch_batched(const BatchArgs& a, uint32_t grid, uint32_t threads, size_t lds_bytes,
+                          hipStream_t s);
 hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t lds_bytes,
                         bool persistent, hipStream_t s);
 hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged);

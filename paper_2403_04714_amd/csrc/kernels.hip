@@ -118,17 +118,18 @@ __device__ void plain_body(const PlainArgs& A) {
   __shared__ int abort_flag;
   __shared__ uint64_t red[16];
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
+  const uint32_t lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
   const PlainProc pp = A.procs[blockIdx.x];
   uint64_t* slot = lds;
-  const uint32_t ibase = A.levels[pp.lvl_off];           // first level instruction
-  const uint32_t n_instr_all = A.levels[pp.lvl_off + pp.n_lvls] - ibase + pp.n_wp;
-  const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + ibase;
+  const uint32_t n_all = pp.n_instr + pp.n_wp;
+  const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
   uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
-  // level table (relative to ibase) after the staged instructions
-  uint32_t* lvs = reinterpret_cast<uint32_t*>(Is + (STAGED ? A.instr_words : 0));
+  uint32_t* chunks = reinterpret_cast<uint32_t*>(Is + (STAGED ? A.instr_words : 0));
+  uint32_t* lvs = chunks + A.chunk_words;
   if (STAGED)
-    for (uint32_t i = tid; i < n_instr_all; i += nthr) Is[i] = Ig[i];
-  for (uint32_t L = tid; L <= pp.n_lvls; L += nthr) lvs[L] = A.levels[pp.lvl_off + L] - ibase;
+    for (uint32_t i = tid; i < n_all; i += nthr) Is[i] = Ig[i];
+  for (uint32_t i = tid; i < pp.n_chunks; i += nthr) chunks[i] = A.chunks[pp.chunk_off + i];
+  for (uint32_t L = tid; L <= pp.n_lvls; L += nthr) lvs[L] = A.levels[pp.lvl_off + L];
   for (uint32_t i = tid; i < pp.n_consts; i += nthr) {
     const Instr in = A.instr[pp.const_off + i];
     slot[in.dst] = A.consts[in.aux];
@@ -137,10 +138,9 @@ __device__ void plain_body(const PlainArgs& A) {
   __syncthreads();
   auto fetch = [&](uint32_t i) -> uint4 { return STAGED ? Is[i] : Ig[i]; };
   const uint32_t n_lvls = pp.n_lvls;
-  // the level table lives in the lanes of two registers and is read with
-  // v_readlane (no LDS round trip on the level-to-level critical path);
-  // deeper processes fall back to the LDS copy
-  const uint32_t lane = tid & 63;
+  // the level table (chunk index where each level starts) lives in the lanes
+  // of two registers and is read with v_readlane; deeper processes fall back
+  // to the LDS copy
   const uint32_t lv_lo = lane <= n_lvls ? lvs[lane] : 0;
   const uint32_t lv_hi = lane + 64 <= n_lvls ? lvs[lane + 64] : 0;
   auto lvl = [&](uint32_t L) -> uint32_t {
@@ -165,75 +165,99 @@ __device__ void plain_body(const PlainArgs& A) {
       trace_row = k < A.trace_max ? A.trace + (k * gridDim.x + blockIdx.x) * A.trace_stride : nullptr;
       if (trace_row) trace_row[0] = __builtin_amdgcn_s_memrealtime();
     }
-    uint32_t lo = lvl(0), hi = lvl(1);
-    uint4 raw = (lo + tid < hi) ? fetch(lo + tid) : make_uint4(0, 0, 0, 0);
+    // this wave's first chunk of level 0 and its instruction
+    uint32_t c_lo = lvl(0), c_hi = lvl(1);
+    uint32_t ch_first = c_lo + wave < c_hi ? chunks[c_lo + wave] : 0;
+    ch_first = __builtin_amdgcn_readfirstlane(ch_first);
+    uint4 raw_first = make_uint4(0, 0, 0, 0);
+    if (c_lo + wave < c_hi && lane <= ((ch_first >> 16) & 63)) raw_first = fetch((ch_first & 0xFFFF) + lane);
     for (uint32_t L = 0; L < n_lvls; ++L) {
-      // next level's bounds and this thread's first instruction there, issued
-      // before this level's operand reads so that their wait covers it
-      const uint32_t nhi = L + 1 < n_lvls ? lvl(L + 2) : hi;
-      const bool have_next = L + 1 < n_lvls && hi + tid < nhi;
-      uint4 raw_next = have_next ? fetch(hi + tid) : raw;
-      if (L == 0) {
-        // leaf level: current register values and this cycle's inputs
-        for (uint32_t i = lo + tid; i < hi; i += nthr) {
-          if (i != lo + tid) raw = fetch(i);
-          const Dec in = decode(raw);
-          uint64_t v;
-          if (in.op == I_LDREG) {
-            v = cur[in.aux];
-          } else if (A.in_vals) {
-            if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v = 0; }
-            else v = A.in_vals[(cyc - A.in_first) * A.I + in.aux];
-          } else {
-            v = hmix(A.in_keys[in.aux] ^ cyc);
+      // the next level's first chunk word for this wave, issued early
+      const uint32_t n_lo = c_hi, n_hi = L + 1 < n_lvls ? lvl(L + 2) : c_hi;
+      const bool have_next = n_lo + wave < n_hi;
+      uint32_t ch_next = have_next ? chunks[n_lo + wave] : 0;
+      bool first = true;
+      for (uint32_t c = c_lo + wave; c < c_hi; c += nwaves) {
+        uint32_t ch = first ? ch_first : __builtin_amdgcn_readfirstlane(chunks[c]);
+        const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 63) + 1, op = ch >> 22;
+        if (lane < cnt) {
+          const Dec in = decode(first ? raw_first : fetch(start + lane));
+          const uint32_t w = in.w;
+          switch (op) {          // op is wave-uniform: scalar branches only
+            case I_LDREG:
+              slot[in.dst] = cur[in.aux] & wmask(w);
+              break;
+            case I_LDIN: {
+              uint64_t v;
+              if (A.in_vals) {
+                if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v = 0; }
+                else v = A.in_vals[(cyc - A.in_first) * A.I + in.aux];
+              } else {
+                v = hmix(A.in_keys[in.aux] ^ cyc);
+              }
+              slot[in.dst] = v & wmask(w);   // LDIN widths fold in the port width
+              break;
+            }
+            case I_MEMRD: {
+              const uint64_t a = slot[in.a];
+              const uint64_t depth = A.mem_depth[in.aux];
+              const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
+              slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(w);
+              break;
+            }
+            case I_AND: slot[in.dst] = (slot[in.a] & slot[in.b]) & wmask(w); break;
+            case I_OR:  slot[in.dst] = (slot[in.a] | slot[in.b]) & wmask(w); break;
+            case I_XOR: slot[in.dst] = (slot[in.a] ^ slot[in.b]) & wmask(w); break;
+            case I_NOT: slot[in.dst] = ~slot[in.a] & wmask(w); break;
+            case I_ADD: slot[in.dst] = (slot[in.a] + slot[in.b]) & wmask(w); break;
+            case I_SUB: slot[in.dst] = (slot[in.a] - slot[in.b]) & wmask(w); break;
+            case I_MUX: {
+              const uint64_t s = slot[in.a], a = slot[in.b], b = slot[in.c];
+              slot[in.dst] = (s ? a : b) & wmask(w);
+              break;
+            }
+            case I_SHL: {
+              const uint64_t a = slot[in.a], b = slot[in.b];
+              slot[in.dst] = (b >= 64 ? 0 : (a << b)) & wmask(w);   // the hardware takes
+              break;                                                 // amounts mod 64
+            }
+            case I_SHR: {
+              const uint64_t a = slot[in.a], b = slot[in.b];
+              slot[in.dst] = (b >= 64 ? 0 : (a >> b)) & wmask(w);
+              break;
+            }
+            case I_EQ: slot[in.dst] = (slot[in.a] == slot[in.b]) ? 1 : 0; break;
+            case I_LT: slot[in.dst] = (slot[in.a] < slot[in.b]) ? 1 : 0; break;
+            case I_MUL: slot[in.dst] = (slot[in.a] * slot[in.b]) & wmask(w); break;
+            case I_STREG: {
+              const uint64_t v = slot[in.a] & wmask(w);
+              nxt[in.aux] = v;
+              if (A.digest_part) dacc += hmix((uint64_t)in.aux ^ hmix(v));
+              break;
+            }
+            case I_STOUT:
+              A.outputs[in.aux] = slot[in.a] & wmask(w);
+              break;
+            default:
+              break;
           }
-          slot[in.dst] = v & wmask(in.w);   // LDIN widths fold in the port width
         }
-      } else if (L + 1 < n_lvls) {
-        // operator level: every operand slot is valid (unused ones repeat a),
-        // so the three LDS reads issue together and one wait covers them
-        for (uint32_t i = lo + tid; i < hi; i += nthr) {
-          if (i != lo + tid) raw = fetch(i);
-          const Dec in = decode(raw);
-          uint64_t a = slot[in.a], b = slot[in.b], c = slot[in.c];
-          // keep the three reads (and their single wait) ahead of the
-          // per-opcode branches: without this the compiler sinks each read
-          // into the cases that use it and every case then waits on its own
-          asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
-          if (in.op == I_MEMRD) {
-            const uint64_t depth = A.mem_depth[in.aux];
-            const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-            slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
-          } else {
-            slot[in.dst] = alu(in.op, in.w, a, b, c);
-          }
-        }
-      } else {
-        // store level: next register values and outputs
-        for (uint32_t i = lo + tid; i < hi; i += nthr) {
-          if (i != lo + tid) raw = fetch(i);
-          const Dec in = decode(raw);
-          const uint64_t v = slot[in.a] & wmask(in.w);
-          if (in.op == I_STREG) {
-            nxt[in.aux] = v;
-            if (A.digest_part) dacc += hmix((uint64_t)in.aux ^ hmix(v));
-          } else {
-            A.outputs[in.aux] = v;
-          }
-        }
+        first = false;
       }
-      raw = raw_next;
-      lo = hi;
-      hi = nhi;
+      // the next level's first instruction for this wave, before the barrier
+      ch_next = __builtin_amdgcn_readfirstlane(ch_next);
+      if (have_next && lane <= ((ch_next >> 16) & 63)) raw_first = fetch((ch_next & 0xFFFF) + lane);
+      ch_first = ch_next;
+      c_lo = n_lo;
+      c_hi = n_hi;
       if (one_wave) asm volatile("" ::: "memory");
       else __syncthreads();
       if (trace_row && L + 2 < A.trace_stride) trace_row[L + 1] = __builtin_amdgcn_s_memrealtime();
     }
     // memory commit after every read of this cycle, in port order
     if (tid == 0) {
-      const uint32_t wlo = lvs[n_lvls];
       for (uint32_t k = 0; k < pp.n_wp; ++k) {
-        const Dec in = decode(fetch(wlo + k));
+        const Dec in = decode(fetch(pp.n_instr + k));
         if (slot[in.a] != 0) {
           const uint32_t m = in.aux;
           const uint64_t depth = A.mem_depth[m], av = slot[in.b];
@@ -245,11 +269,11 @@ __device__ void plain_body(const PlainArgs& A) {
     if (A.digest_part) {
       // workgroup reduction of the digest terms; partial per workgroup
       for (int off = 32; off > 0; off >>= 1) dacc += __shfl_xor(dacc, off);
-      if ((tid & 63) == 0) red[tid >> 6] = dacc;
+      if (lane == 0) red[wave] = dacc;
       __syncthreads();
       if (tid == 0) {
         uint64_t s = 0;
-        for (uint32_t k = 0; k < (nthr + 63) / 64; ++k) s += red[k];
+        for (uint32_t k = 0; k < nwaves; ++k) s += red[k];
         const uint64_t k = cyc - A.digest_first;
         if (k < A.digest_max) A.digest_part[k * gridDim.x + blockIdx.x] = s;
       }
@@ -284,12 +308,184 @@ __global__ void add_u64(uint64_t* p, uint64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p += v;
 }
 
-// stimulus keys: keys[i * I + p] = H(H(seed_base + i) ^ p)
+// stimulus keys, instance-minor: keys[p * n_inst + i] = H(H(seed_base + i) ^ p)
 __global__ void stim_keys(uint64_t* keys, uint64_t seed_base, uint32_t n_inst, uint32_t I) {
   uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_inst * I) return;
-  uint32_t i = k / I, p = k % I;
+  uint32_t i = k % n_inst, p = k / n_inst;
   keys[k] = hmix(hmix(seed_base + i) ^ (uint64_t)p);
+}
+
+
+// ------------------------------------------------------------ batched form
+//
+// A wave evaluates one process for 64 instances (one lane per instance,
+// Sec. 6.4's many-independent-tests scenario).  The instruction stream is
+// wave-uniform, so it is fetched with scalar loads and dispatched with scalar
+// branches.  Values live in LDS slots per class: a 1-bit value is one 64-lane
+// ballot mask, a narrow value one u32 per lane, a wide value one u64 per lane.
+// Operators whose operands and result are all 1-bit work on the masks
+// directly.
+
+struct WaveSlots {
+  uint64_t* B;   // [slotsB]
+  uint32_t* W;   // [slotsW][64]
+  uint64_t* D;   // [slotsD][64]
+};
+
+__device__ __forceinline__ uint64_t bread(const WaveSlots& S, const uint64_t* K, uint32_t cls, uint32_t s,
+                                          uint32_t lane) {
+  switch (cls) {
+    case C_B: return (S.B[s] >> lane) & 1;
+    case C_W: return S.W[s * 64 + lane];
+    case C_D: return S.D[s * 64 + lane];
+    default:  return K[s];
+  }
+}
+
+__device__ __forceinline__ void bwrite(const WaveSlots& S, uint32_t cls, uint32_t s, uint32_t lane, uint64_t v) {
+  switch (cls) {
+    case C_B: {
+      const uint64_t m = __ballot(v & 1);
+      if (lane == 0) S.B[s] = m;
+      break;
+    }
+    case C_W: S.W[s * 64 + lane] = (uint32_t)v; break;
+    default:  S.D[s * 64 + lane] = v; break;
+  }
+}
+
+// the 64-lane mask of a 1-bit operand: B slots as stored, constants by bit 0
+__device__ __forceinline__ uint64_t bmask(const WaveSlots& S, const uint64_t* K, uint32_t cls, uint32_t s) {
+  return cls == C_B ? S.B[s] : ((K[s] & 1) ? ~0ull : 0ull);
+}
+
+__global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
+  extern __shared__ uint64_t lds[];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t p = blockIdx.x % A.P, grp = blockIdx.x / A.P;
+  const uint32_t tile = grp * A.tpw + wave;
+  if (tile >= A.n_tiles) return;                 // no barriers below: a wave may leave early
+  const uint32_t inst = tile * 64 + lane;        // < n_pad
+  const bool real = inst < A.n_inst;
+  const size_t wave_words = A.slotsB + (A.slotsW * 64 + 1) / 2 + A.slotsD * 64;
+  WaveSlots S;
+  S.B = lds + wave * wave_words;
+  S.W = reinterpret_cast<uint32_t*>(S.B + A.slotsB);
+  S.D = S.B + A.slotsB + (A.slotsW * 64 + 1) / 2;
+  const BatchProc bp = A.procs[p];
+  const Instr* __restrict__ prog = A.instr + bp.instr_off;
+  const uint64_t* __restrict__ K = A.consts + bp.const_off;
+  const uint64_t cyc = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
+  const uint32_t cur = cyc & 1, nxt = cur ^ 1;
+  const uint64_t* stB_cur = A.stB + (size_t)cur * A.nB * A.n_tiles;
+  uint64_t* stB_nxt = A.stB + (size_t)nxt * A.nB * A.n_tiles;
+  const uint32_t* stW_cur = A.stW + (size_t)cur * A.nW * A.n_pad;
+  uint32_t* stW_nxt = A.stW + (size_t)nxt * A.nW * A.n_pad;
+  const uint64_t* stD_cur = A.stD + (size_t)cur * A.nD * A.n_pad;
+  uint64_t* stD_nxt = A.stD + (size_t)nxt * A.nD * A.n_pad;
+  uint64_t dacc = 0;
+  for (uint32_t i = 0; i < bp.n_instr; ++i) {
+    // wave-uniform instruction (scalar registers)
+    const uint4 raw = reinterpret_cast<const uint4*>(prog)[i];
+    const uint32_t x = __builtin_amdgcn_readfirstlane(raw.x), y = __builtin_amdgcn_readfirstlane(raw.y);
+    const uint32_t z = __builtin_amdgcn_readfirstlane(raw.z), aux = __builtin_amdgcn_readfirstlane(raw.w);
+    const uint32_t op = x & 0xFF, w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
+    const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
+    const uint32_t dst = y & 0xFFFF, sa = y >> 16, sb = z & 0xFFFF, sc = z >> 16;
+    switch (op) {
+      case I_LDREG: {
+        // ca: class of the register's state array; cd: class of the node
+        if (ca == C_B) {
+          const uint64_t m = stB_cur[(size_t)aux * A.n_tiles + tile];
+          if (cd == C_B) { if (lane == 0) S.B[dst] = m; }
+          else bwrite(S, cd, dst, lane, (m >> lane) & 1);
+        } else {
+          const uint64_t v = ca == C_W ? (uint64_t)stW_cur[(size_t)aux * A.n_pad + inst]
+                                       : stD_cur[(size_t)aux * A.n_pad + inst];
+          bwrite(S, cd, dst, lane, v & wmask(w));
+        }
+        break;
+      }
+      case I_LDIN: {
+        uint64_t v;
+        if (A.in_vals) {
+          if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v = 0; }
+          else v = real ? A.in_vals[((cyc - A.in_first) * A.I + aux) * A.n_inst + inst] : 0;
+        } else {
+          v = hmix(A.keys[(size_t)aux * A.n_pad + inst] ^ cyc);
+        }
+        bwrite(S, cd, dst, lane, v & wmask(w));
+        break;
+      }
+      case I_MEMRD: {
+        const uint64_t a = bread(S, K, ca, sa, lane);
+        const uint64_t depth = A.mem_depth[aux];
+        const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
+        bwrite(S, cd, dst, lane, A.mem[(A.mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
+        break;
+      }
+      case I_STREG: {
+        // cd: class of the register's state array, ca: class of the value
+        const uint64_t v = bread(S, K, ca, sa, lane) & wmask(w);
+        if (cd == C_B) {
+          const uint64_t m = __ballot(v & 1);
+          if (lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile] = m;
+        } else if (cd == C_W) {
+          stW_nxt[(size_t)aux * A.n_pad + inst] = (uint32_t)v;
+        } else {
+          stD_nxt[(size_t)aux * A.n_pad + inst] = v;
+        }
+        if (A.digest) dacc += hmix((uint64_t)(sb | (sc << 16)) ^ hmix(v));
+        break;
+      }
+      case I_STOUT:
+        A.outputs[(size_t)aux * A.n_pad + inst] = bread(S, K, ca, sa, lane) & wmask(w);
+        break;
+      case I_WPORT: {
+        const uint64_t en = bread(S, K, ca, sa, lane), a = bread(S, K, cb, sb, lane);
+        const uint64_t v = bread(S, K, cc, sc, lane);
+        if (en) {
+          const uint64_t depth = A.mem_depth[aux];
+          const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
+          A.mem[(A.mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
+        }
+        break;
+      }
+      default: {
+        // 1-bit logic on whole masks when every operand and the result are 1-bit
+        const bool mask_ok = cd == C_B &&
+            ((op == I_AND || op == I_OR || op == I_XOR || op == I_ADD || op == I_SUB) &&
+                 (ca == C_B || ca == C_K) && (cb == C_B || cb == C_K) ||
+             op == I_NOT && (ca == C_B || ca == C_K) ||
+             (op == I_EQ || op == I_LT) && ca == C_B && cb == C_B ||
+             op == I_MUX && ca == C_B && (cb == C_B || cb == C_K) && (cc == C_B || cc == C_K));
+        if (mask_ok) {
+          const uint64_t ma = bmask(S, K, ca, sa), mb = bmask(S, K, cb, sb), mc = bmask(S, K, cc, sc);
+          uint64_t r;
+          switch (op) {
+            case I_AND: r = ma & mb; break;
+            case I_OR:  r = ma | mb; break;
+            case I_XOR: case I_ADD: case I_SUB: r = ma ^ mb; break;   // mod 2 sums
+            case I_NOT: r = ~ma; break;
+            case I_EQ:  r = ~(ma ^ mb); break;
+            case I_LT:  r = ~ma & mb; break;
+            default:    r = (ma & mb) | (~ma & mc); break;             // MUX
+          }
+          if (lane == 0) S.B[dst] = r;
+        } else {
+          const uint64_t a = bread(S, K, ca, sa, lane), b = bread(S, K, cb, sb, lane);
+          const uint64_t c = bread(S, K, cc, sc, lane);
+          bwrite(S, cd, dst, lane, alu(op, w, a, b, c));
+        }
+        break;
+      }
+    }
+  }
+  if (A.digest && real) {
+    const uint64_t k = cyc - A.digest_first;
+    if (k < A.digest_max) atomicAdd((unsigned long long*)&A.digest[k * A.n_inst + inst], (unsigned long long)dacc);
+  }
 }
 
 }  // namespace fsim
@@ -306,6 +502,12 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t
   }
   if (a.stage_instr) hipLaunchKernelGGL(plain_cycle, dim3(G), dim3(threads), lds_bytes, s, a);
   else hipLaunchKernelGGL(plain_cycle_g, dim3(G), dim3(threads), lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchArgs& a, uint32_t grid, uint32_t threads, size_t lds_bytes,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(batched_cycle, dim3(grid), dim3(threads), lds_bytes, s, a);
   return hipGetLastError();
 }
 

@@ -62,13 +62,21 @@ struct fsim_design {
   Design d;
   fsim_design_info info{};
   // plain-form program on the device
-  DevBuf instr, levels, procs, consts, mem_off, mem_depth, in_width;
-  uint32_t slot_words = 0, max_proc_instr = 0, max_lvls = 0;
+  DevBuf instr, levels, chunks, procs, consts, mem_off, mem_depth, in_width;
+  uint32_t slot_words = 0, max_proc_instr = 0, max_lvls = 0, max_chunks = 0;
+  // batched-form program, encoded on first use
+  std::mutex batch_mu;
+  bool batch_ready = false;
+  DevBuf b_instr, b_procs, b_consts;
 };
 
 struct fsim_sim {
   fsim_design* d = nullptr;
   uint32_t n_inst = 1;
+  bool batched = false;
+  uint32_t n_tiles = 1, n_pad = 64, tpw = 1;
+  uint64_t *stB = nullptr, *stD = nullptr;
+  uint32_t* stW = nullptr;
   uint32_t G = 1, threads = 256, launch = FSIM_LAUNCH_PERSISTENT, graph_cycles = 64;
   size_t lds_bytes = 0;
   bool stage_instr = false;
@@ -168,15 +176,10 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   if (!s.ok()) return fail(s);
   s = fsim::encode_plain(d, std::min<uint32_t>(max_slots, 0xFFFE));
   if (!s.ok()) return fail(s);
-  // per-process instruction span (levels + commit), for LDS staging
-  uint32_t mx = 0, ml = 0;
-  for (const auto& pp : d.plain_procs) {
-    uint32_t n = d.plain_levels[pp.lvl_off + pp.n_lvls] - d.plain_levels[pp.lvl_off] + pp.n_wp;
-    mx = std::max(mx, n);
-    ml = std::max(ml, pp.n_lvls);
-  }
-  dz->max_proc_instr = mx;
-  dz->max_lvls = ml;
+  // per-process spans, for the LDS layout
+  dz->max_proc_instr = d.plain_max_instr;
+  dz->max_lvls = d.max_plain_lvls;
+  dz->max_chunks = d.plain_max_chunks;
   dz->slot_words = (d.plain_max_slots + 1) & ~1u;
   d.compile_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   fsim_design_info& I = dz->info;
@@ -193,6 +196,7 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   I.max_fiber_cost = d.max_fiber_cost;
   I.max_process_cost = d.max_process_cost;
   I.program_bytes = d.plain_instr.size() * sizeof(fsim::Instr) + d.plain_levels.size() * 4 +
+                    d.plain_chunks.size() * 4 +
                     d.plain_procs.size() * sizeof(fsim::PlainProc) + d.consts.size() * 8;
   I.max_process_levels = d.max_process_levels;
   I.max_process_nodes = d.max_process_nodes;
@@ -204,6 +208,7 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
     int rc;
     if ((rc = upload(dz->instr, d.plain_instr, st))) return rc;
     if ((rc = upload(dz->levels, d.plain_levels, st))) return rc;
+    if ((rc = upload(dz->chunks, d.plain_chunks, st))) return rc;
     if ((rc = upload(dz->procs, d.plain_procs, st))) return rc;
     if ((rc = upload(dz->consts, d.consts, st))) return rc;
     std::vector<uint64_t> moff(d.mem_off.begin(), d.mem_off.end() - (d.M ? 1 : 0));
@@ -242,17 +247,34 @@ extern "C" void fsim_design_free(fsim_design* d) { design_release(d); }
 // ---------------------------------------------------------------------- sim
 namespace {
 struct Layout {
-  size_t state, outputs, mem, keys, flags, error, cyc, total;
+  size_t state, stB, stW, stD, outputs, mem, keys, flags, error, cyc, total;
 };
 
-Layout layout(const Design& d, uint32_t n_inst, uint32_t G) {
+// Plain form: state u64 [2][R]; outputs [O]; memories [words]; keys [I].
+// Batched form: state per register class, 1-bit as masks [2][nB][tiles],
+// narrow u32 [2][nW][n_pad], wide u64 [2][nD][n_pad]; outputs [O][n_pad];
+// memories [words][n_pad]; keys [I][n_pad].
+Layout layout(const Design& d, uint32_t n_inst, uint32_t G, bool batched) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
-  L.state = take(2ull * d.R * 8 * n_inst);
-  L.outputs = take((size_t)d.O * 8 * n_inst);
-  L.mem = take(d.mem_off[d.M] * 8 * n_inst);
-  L.keys = take((size_t)d.I * 8 * n_inst);
+  const size_t n_pad = batched ? ((size_t)n_inst + 63) / 64 * 64 : 1;
+  const size_t tiles = n_pad / 64;
+  if (batched) {
+    size_t nb = 0, nw = 0, nd = 0;
+    for (uint32_t r = 0; r < d.R; ++r) {
+      uint8_t k = fsim::class_of_width(d.reg_width[r]);
+      (k == fsim::C_B ? nb : k == fsim::C_W ? nw : nd)++;
+    }
+    L.stB = take(2 * nb * tiles * 8);
+    L.stW = take(2 * nw * n_pad * 4);
+    L.stD = take(2 * nd * n_pad * 8);
+  } else {
+    L.state = take(2ull * d.R * 8);
+  }
+  L.outputs = take((size_t)d.O * 8 * n_pad);
+  L.mem = take(d.mem_off[d.M] * 8 * n_pad);
+  L.keys = take((size_t)d.I * 8 * n_pad);
   L.flags = take((size_t)std::max(G, 1u) * 4);
   L.error = take(16);
   L.cyc = take(8);
@@ -264,18 +286,45 @@ Layout layout(const Design& d, uint32_t n_inst, uint32_t G) {
 extern "C" int fsim_sim_footprint(const fsim_design* d, uint32_t n_instances, size_t* bytes) {
   if (!d || !bytes) return fail(FSIM_E_ARG, "NULL argument");
   if (n_instances == 0) return fail(FSIM_E_ARG, "n_instances must be >= 1");
-  *bytes = layout(d->d, n_instances, d->d.P).total;
+  // one instance may run either form: report the larger of the two layouts
+  *bytes = layout(d->d, n_instances, d->d.P, true).total;
+  if (n_instances == 1) *bytes = std::max(*bytes, layout(d->d, 1, d->d.P, false).total);
   return FSIM_OK;
 }
 
 static int sim_reset_state(fsim_sim* s) {
   const Design& d = s->d->d;
   hipStream_t st = s->d->ctx->stream;
-  HIP_TRY(hipMemcpyAsync(s->state, d.reg_init.data(), (size_t)d.R * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemsetAsync(s->state + d.R, 0, (size_t)d.R * 8, st));
-  if (d.mem_off[d.M])
-    HIP_TRY(hipMemcpyAsync(s->mem, d.mem_init.data(), d.mem_off[d.M] * 8, hipMemcpyHostToDevice, st));
-  if (d.O) HIP_TRY(hipMemsetAsync(s->outputs, 0, (size_t)d.O * 8, st));
+  if (!s->batched) {
+    HIP_TRY(hipMemcpyAsync(s->state, d.reg_init.data(), (size_t)d.R * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(s->state + d.R, 0, (size_t)d.R * 8, st));
+    if (d.mem_off[d.M])
+      HIP_TRY(hipMemcpyAsync(s->mem, d.mem_init.data(), d.mem_off[d.M] * 8, hipMemcpyHostToDevice, st));
+    if (d.O) HIP_TRY(hipMemsetAsync(s->outputs, 0, (size_t)d.O * 8, st));
+  } else {
+    // every instance starts from the netlist's initial state
+    const size_t T = s->n_tiles, NP = s->n_pad;
+    std::vector<uint64_t> b(2 * (size_t)d.reg_count[0] * T, 0), dd(2 * (size_t)d.reg_count[2] * NP, 0);
+    std::vector<uint32_t> w(2 * (size_t)d.reg_count[1] * NP, 0);
+    for (uint32_t r = 0; r < d.R; ++r) {
+      const uint32_t k = d.reg_cls_idx[r] >> 30, i = d.reg_cls_idx[r] & 0x3FFFFFFF;
+      const uint64_t v = d.reg_init[r];
+      if (k == fsim::C_B) std::fill(b.begin() + i * T, b.begin() + (i + 1) * T, (v & 1) ? ~0ull : 0ull);
+      else if (k == fsim::C_W) std::fill(w.begin() + i * NP, w.begin() + (i + 1) * NP, (uint32_t)v);
+      else std::fill(dd.begin() + i * NP, dd.begin() + (i + 1) * NP, v);
+    }
+    if (!b.empty()) HIP_TRY(hipMemcpyAsync(s->stB, b.data(), b.size() * 8, hipMemcpyHostToDevice, st));
+    if (!w.empty()) HIP_TRY(hipMemcpyAsync(s->stW, w.data(), w.size() * 4, hipMemcpyHostToDevice, st));
+    if (!dd.empty()) HIP_TRY(hipMemcpyAsync(s->stD, dd.data(), dd.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (d.mem_off[d.M]) {
+      std::vector<uint64_t> m(d.mem_off[d.M] * NP);
+      for (uint64_t a = 0; a < d.mem_off[d.M]; ++a) std::fill(m.begin() + a * NP, m.begin() + (a + 1) * NP, d.mem_init[a]);
+      HIP_TRY(hipMemcpyAsync(s->mem, m.data(), m.size() * 8, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (d.O) HIP_TRY(hipMemsetAsync(s->outputs, 0, (size_t)d.O * 8 * NP, st));
+  }
   HIP_TRY(hipMemsetAsync(s->flags, 0, (size_t)s->G * 4, st));
   HIP_TRY(hipMemsetAsync(s->error, 0, 16, st));
   HIP_TRY(hipMemsetAsync(s->cyc_dev, 0, 8, st));
@@ -288,8 +337,70 @@ extern "C" int fsim_set_stimulus_seed(fsim_sim* s, uint64_t seed_base) {
   if (s->poisoned) return fail(FSIM_E_STATE, "sim is poisoned by an earlier device error");
   s->seed = seed_base;
   s->explicit_inputs = false;
-  HIP_TRY(fsim::launch_stim_keys(s->keys, seed_base, s->n_inst, s->d->d.I, s->d->ctx->stream));
+  HIP_TRY(fsim::launch_stim_keys(s->keys, seed_base, s->batched ? s->n_pad : 1, s->d->d.I, s->d->ctx->stream));
   return FSIM_OK;
+}
+
+static int ensure_batched(fsim_design* d) {
+  std::lock_guard<std::mutex> g(d->batch_mu);
+  if (d->batch_ready) return FSIM_OK;
+  Design& D = d->d;
+  Status st = fsim::encode_batched(D, nullptr);
+  if (!st.ok()) return fail(st);
+  hipStream_t s = d->ctx->stream;
+  int rc;
+  if ((rc = upload(d->b_instr, D.batch_instr, s))) return rc;
+  if ((rc = upload(d->b_procs, D.batch_procs, s))) return rc;
+  if ((rc = upload(d->b_consts, D.batch_consts, s))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  d->batch_ready = true;
+  return FSIM_OK;
+}
+
+static size_t batched_wave_bytes(const Design& D) {
+  return ((size_t)D.batch_slots[0] + ((size_t)D.batch_slots[1] * 64 + 1) / 2 + (size_t)D.batch_slots[2] * 64) * 8;
+}
+
+static int sim_create_batched(fsim_sim* s, void* workspace, size_t ws_bytes, const fsim_sim_opts& o) {
+  fsim_design* d = s->d;
+  HIP_TRY(hipSetDevice(d->ctx->device));
+  int rc = ensure_batched(d);
+  if (rc) return rc;
+  const Design& D = d->d;
+  s->G = 1;
+  s->n_pad = (s->n_inst + 63) / 64 * 64;
+  s->n_tiles = s->n_pad / 64;
+  s->tpw = o.wg_threads ? o.wg_threads / 64 : std::min<uint32_t>(s->n_tiles, 4);
+  if (s->tpw < 1 || s->tpw > 4 || (o.wg_threads && o.wg_threads % 64))
+    return fail(FSIM_E_ARG, "batched form: wg_threads must be 64, 128, 192 or 256");
+  s->threads = 64 * s->tpw;
+  s->launch = o.launch ? o.launch : FSIM_LAUNCH_GRAPH;
+  if (s->launch == FSIM_LAUNCH_PERSISTENT) s->launch = FSIM_LAUNCH_GRAPH;   // kernel boundary is the barrier
+  s->graph_cycles = o.graph_cycles ? o.graph_cycles : 64;
+  s->lds_bytes = batched_wave_bytes(D) * s->tpw;
+  if (s->lds_bytes > d->ctx->lds_bytes)
+    return fail(FSIM_E_CAPACITY, "batched form: a process's live values exceed LDS (" +
+                                     std::to_string(s->lds_bytes) + " bytes); use more processes");
+  Layout L = layout(D, s->n_inst, 1, true);
+  if (workspace) {
+    if (ws_bytes < L.total) return fail(FSIM_E_ARG, "workspace smaller than fsim_sim_footprint()");
+    if ((uintptr_t)workspace % 256) return fail(FSIM_E_ARG, "workspace must be 256-byte aligned");
+    s->ws = (char*)workspace;
+  } else {
+    HIP_TRY(s->own_ws.alloc(L.total));
+    s->ws = (char*)s->own_ws.p;
+  }
+  s->stB = (uint64_t*)(s->ws + L.stB);
+  s->stW = (uint32_t*)(s->ws + L.stW);
+  s->stD = (uint64_t*)(s->ws + L.stD);
+  s->outputs = (uint64_t*)(s->ws + L.outputs);
+  s->mem = (uint64_t*)(s->ws + L.mem);
+  s->keys = (uint64_t*)(s->ws + L.keys);
+  s->flags = (uint32_t*)(s->ws + L.flags);
+  s->error = (uint32_t*)(s->ws + L.error);
+  s->cyc_dev = (uint64_t*)(s->ws + L.cyc);
+  if ((rc = sim_reset_state(s))) return rc;
+  return fsim_set_stimulus_seed(s, 0);
 }
 
 extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* workspace, size_t ws_bytes,
@@ -297,12 +408,21 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
   if (!d || !out) return fail(FSIM_E_ARG, "NULL argument");
   *out = nullptr;
   if (!d->ctx) return fail(FSIM_E_STATE, "design was compiled without a device context");
-  if (n_instances != 1) return fail(FSIM_E_UNSUPPORTED, "batched form: n_instances > 1 not built yet");
+  if (n_instances == 0) return fail(FSIM_E_ARG, "n_instances must be >= 1");
   fsim_sim_opts o{};
   if (opts) o = *opts;
   auto s = std::make_unique<fsim_sim>();
   s->d = d;
   s->n_inst = n_instances;
+  s->batched = o.form == FSIM_FORM_BATCHED || (o.form == FSIM_FORM_AUTO && n_instances > 1);
+  if (!s->batched && n_instances != 1) return fail(FSIM_E_ARG, "the plain form runs exactly one instance");
+  if (s->batched) {
+    int rc = sim_create_batched(s.get(), workspace, ws_bytes, o);
+    if (rc) return rc;
+    d->refs++;
+    *out = s.release();
+    return FSIM_OK;
+  }
   s->G = d->d.P;
   s->threads = o.wg_threads ? o.wg_threads : 256;
   if (s->threads < 64 || s->threads > 1024 || s->threads % 64)
@@ -311,13 +431,14 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
     return fail(FSIM_E_ARG, "plain form: grid must equal the design's process count");
   s->launch = o.launch ? o.launch : FSIM_LAUNCH_PERSISTENT;
   if (s->launch > FSIM_LAUNCH_GRAPH) return fail(FSIM_E_ARG, "unknown launch mode");
+  if (o.form > FSIM_FORM_PLAIN) return fail(FSIM_E_ARG, "unknown form");
   s->graph_cycles = o.graph_cycles ? o.graph_cycles : 64;
   if (s->graph_cycles % 2) s->graph_cycles++;      // keeps the state parity of the base cycle even
   HIP_TRY(hipSetDevice(d->ctx->device));
   // LDS: slots, plus the process's instructions when they fit
   const size_t lds_limit = d->ctx->lds_bytes - kStaticLds;
   // slots, then (when they fit) the process's instructions, then the level table
-  const size_t lvl_bytes = ((size_t)d->max_lvls + 1) * 4;
+  const size_t lvl_bytes = ((size_t)d->max_lvls + 1) * 4 + (size_t)d->max_chunks * 4;
   size_t lds = (size_t)d->slot_words * 8 + lvl_bytes;
   if (lds + (size_t)d->max_proc_instr * sizeof(fsim::Instr) <= lds_limit) {
     s->stage_instr = true;
@@ -332,7 +453,7 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
       return fail(FSIM_E_CAPACITY, "persistent launch: " + std::to_string(s->G) +
                                        " workgroups are not co-resident; use fewer processes");
   }
-  Layout L = layout(d->d, n_instances, s->G);
+  Layout L = layout(d->d, n_instances, s->G, false);
   if (workspace) {
     if (ws_bytes < L.total) return fail(FSIM_E_ARG, "workspace smaller than fsim_sim_footprint()");
     if ((uintptr_t)workspace % 256) return fail(FSIM_E_ARG, "workspace must be 256-byte aligned");
@@ -386,6 +507,7 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   fsim::PlainArgs a{};
   a.instr = (const fsim::Instr*)dd->instr.p;
   a.levels = (const uint32_t*)dd->levels.p;
+  a.chunks = (const uint32_t*)dd->chunks.p;
   a.procs = (const fsim::PlainProc*)dd->procs.p;
   a.consts = (const uint64_t*)dd->consts.p;
   a.state = s->state;
@@ -412,8 +534,38 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   a.stage_instr = s->stage_instr ? 1 : 0;
   a.slot_words = dd->slot_words;
   a.instr_words = dd->max_proc_instr;
+  a.chunk_words = dd->max_chunks;
   a.cycle_ptr = nullptr;
   return a;
+}
+
+static fsim::BatchArgs batch_args(fsim_sim* s) {
+  const fsim_design* dd = s->d;
+  const Design& D = dd->d;
+  fsim::BatchArgs a{};
+  a.instr = (const fsim::Instr*)dd->b_instr.p;
+  a.procs = (const fsim::BatchProc*)dd->b_procs.p;
+  a.consts = (const uint64_t*)dd->b_consts.p;
+  a.stB = s->stB; a.stW = s->stW; a.stD = s->stD;
+  a.outputs = s->outputs;
+  a.mem = s->mem;
+  a.mem_off = (const uint64_t*)dd->mem_off.p;
+  a.mem_depth = (const uint32_t*)dd->mem_depth.p;
+  a.keys = s->keys;
+  a.in_vals = s->explicit_inputs ? (const uint64_t*)s->in_vals.p : nullptr;
+  a.in_first = s->in_first; a.in_count = s->in_count;
+  a.digest = s->dig_out;
+  a.digest_first = s->dig_first; a.digest_max = s->dig_max;
+  a.error = s->error;
+  a.cycle_ptr = nullptr;
+  a.P = D.P; a.n_tiles = s->n_tiles; a.tpw = s->tpw; a.n_inst = s->n_inst; a.n_pad = s->n_pad; a.I = D.I;
+  a.nB = D.reg_count[0]; a.nW = D.reg_count[1]; a.nD = D.reg_count[2];
+  a.slotsB = D.batch_slots[0]; a.slotsW = D.batch_slots[1]; a.slotsD = D.batch_slots[2];
+  return a;
+}
+
+static uint32_t batch_grid(const fsim_sim* s) {
+  return s->d->d.P * ((s->n_tiles + s->tpw - 1) / s->tpw);
 }
 
 static int build_graph(fsim_sim* s) {
@@ -423,10 +575,17 @@ static int build_graph(fsim_sim* s) {
   fsim::PlainArgs a = plain_args(s);
   a.cycle_ptr = s->cyc_dev;
   a.n_cycles = 1;
+  fsim::BatchArgs ba = batch_args(s);
+  ba.cycle_ptr = s->cyc_dev;
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   for (uint32_t k = 0; e == hipSuccess && k < s->graph_cycles; ++k) {
-    a.cycle0 = k;
-    e = fsim::launch_plain(a, s->G, s->threads, s->lds_bytes, false, cap);
+    if (s->batched) {
+      ba.cycle0 = k;
+      e = fsim::launch_batched(ba, batch_grid(s), s->threads, s->lds_bytes, cap);
+    } else {
+      a.cycle0 = k;
+      e = fsim::launch_plain(a, s->G, s->threads, s->lds_bytes, false, cap);
+    }
   }
   if (e == hipSuccess) e = fsim::launch_add_u64(s->cyc_dev, s->graph_cycles, cap);
   hipGraph_t g = nullptr;
@@ -485,15 +644,22 @@ extern "C" int fsim_step(fsim_sim* s, uint64_t n_cycles) {
         }
         continue;
       }
-      a.cycle0 = s->cycle;
-      a.n_cycles = 1;
-      hipError_t e = fsim::launch_plain(a, s->G, s->threads, s->lds_bytes, false, st);
+      hipError_t e;
+      if (s->batched) {
+        fsim::BatchArgs ba = batch_args(s);
+        ba.cycle0 = s->cycle;
+        e = fsim::launch_batched(ba, batch_grid(s), s->threads, s->lds_bytes, st);
+      } else {
+        a.cycle0 = s->cycle;
+        a.n_cycles = 1;
+        e = fsim::launch_plain(a, s->G, s->threads, s->lds_bytes, false, st);
+      }
       if (e != hipSuccess) { s->poisoned = true; return fail(FSIM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e)); }
       s->cycle += 1;
       left -= 1;
     }
   }
-  if (s->dig_out) {
+  if (s->dig_out && !s->batched) {
     uint64_t lo = std::max(c_begin, s->dig_first), hi = std::min(s->cycle, s->dig_first + s->dig_max);
     if (hi > lo) {
       uint64_t k0 = lo - s->dig_first;
@@ -526,12 +692,52 @@ static int check_inst(fsim_sim* s, uint32_t inst) {
   return fsim_sync(s);
 }
 
+// batched layout helpers: one instance's column of a [rows][pitch] array
+static int col_read(const void* base, size_t elem, size_t pitch_elems, size_t col, size_t rows, void* out) {
+  if (!rows) return FSIM_OK;
+  HIP_TRY(hipMemcpy2D(out, elem, (const char*)base + col * elem, pitch_elems * elem, elem, rows,
+                      hipMemcpyDeviceToHost));
+  return FSIM_OK;
+}
+static int col_write(void* base, size_t elem, size_t pitch_elems, size_t col, size_t rows, const void* in) {
+  if (!rows) return FSIM_OK;
+  HIP_TRY(hipMemcpy2D((char*)base + col * elem, pitch_elems * elem, in, elem, elem, rows,
+                      hipMemcpyHostToDevice));
+  return FSIM_OK;
+}
+
+// the current-parity register state of one batched instance, per class
+struct BatchedRegs {
+  std::vector<uint64_t> b, d;
+  std::vector<uint32_t> w;
+};
+static int batched_regs_read(fsim_sim* s, uint32_t inst, BatchedRegs& R) {
+  const Design& D = s->d->d;
+  const size_t cur = s->cycle & 1, T = s->n_tiles, NP = s->n_pad;
+  R.b.assign(D.reg_count[0], 0); R.w.assign(D.reg_count[1], 0); R.d.assign(D.reg_count[2], 0);
+  int rc;
+  if ((rc = col_read(s->stB + cur * D.reg_count[0] * T, 8, T, inst / 64, D.reg_count[0], R.b.data()))) return rc;
+  if ((rc = col_read(s->stW + cur * D.reg_count[1] * NP, 4, NP, inst, D.reg_count[1], R.w.data()))) return rc;
+  if ((rc = col_read(s->stD + cur * D.reg_count[2] * NP, 8, NP, inst, D.reg_count[2], R.d.data()))) return rc;
+  return FSIM_OK;
+}
+
 extern "C" int fsim_read_regs(fsim_sim* s, uint32_t inst, uint64_t* out) {
   int rc = check_inst(s, inst);
   if (rc) return rc;
   if (!out && s->d->d.R) return fail(FSIM_E_ARG, "out is NULL");
   const uint32_t R = s->d->d.R;
-  HIP_TRY(hipMemcpy(out, s->state + (s->cycle & 1) * R, (size_t)R * 8, hipMemcpyDeviceToHost));
+  if (!s->batched) {
+    HIP_TRY(hipMemcpy(out, s->state + (s->cycle & 1) * R, (size_t)R * 8, hipMemcpyDeviceToHost));
+    return FSIM_OK;
+  }
+  BatchedRegs B;
+  if ((rc = batched_regs_read(s, inst, B))) return rc;
+  const Design& D = s->d->d;
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t k = D.reg_cls_idx[r] >> 30, i = D.reg_cls_idx[r] & 0x3FFFFFFF;
+    out[r] = k == fsim::C_B ? (B.b[i] >> (inst % 64)) & 1 : k == fsim::C_W ? B.w[i] : B.d[i];
+  }
   return FSIM_OK;
 }
 
@@ -542,7 +748,22 @@ extern "C" int fsim_write_regs(fsim_sim* s, uint32_t inst, const uint64_t* in) {
   if (!in && d.R) return fail(FSIM_E_ARG, "in is NULL");
   std::vector<uint64_t> v(in, in + d.R);
   for (uint32_t r = 0; r < d.R; ++r) v[r] &= ~0ull >> (64 - d.reg_width[r]);
-  HIP_TRY(hipMemcpy(s->state + (s->cycle & 1) * d.R, v.data(), (size_t)d.R * 8, hipMemcpyHostToDevice));
+  if (!s->batched) {
+    HIP_TRY(hipMemcpy(s->state + (s->cycle & 1) * d.R, v.data(), (size_t)d.R * 8, hipMemcpyHostToDevice));
+    return FSIM_OK;
+  }
+  BatchedRegs B;
+  if ((rc = batched_regs_read(s, inst, B))) return rc;
+  for (uint32_t r = 0; r < d.R; ++r) {
+    const uint32_t k = d.reg_cls_idx[r] >> 30, i = d.reg_cls_idx[r] & 0x3FFFFFFF;
+    if (k == fsim::C_B) B.b[i] = (B.b[i] & ~(1ull << (inst % 64))) | ((v[r] & 1) << (inst % 64));
+    else if (k == fsim::C_W) B.w[i] = (uint32_t)v[r];
+    else B.d[i] = v[r];
+  }
+  const size_t cur = s->cycle & 1, T = s->n_tiles, NP = s->n_pad;
+  if ((rc = col_write(s->stB + cur * d.reg_count[0] * T, 8, T, inst / 64, d.reg_count[0], B.b.data()))) return rc;
+  if ((rc = col_write(s->stW + cur * d.reg_count[1] * NP, 4, NP, inst, d.reg_count[1], B.w.data()))) return rc;
+  if ((rc = col_write(s->stD + cur * d.reg_count[2] * NP, 8, NP, inst, d.reg_count[2], B.d.data()))) return rc;
   return FSIM_OK;
 }
 
@@ -551,8 +772,11 @@ extern "C" int fsim_read_outputs(fsim_sim* s, uint32_t inst, uint64_t* out) {
   if (rc) return rc;
   const uint32_t O = s->d->d.O;
   if (!out && O) return fail(FSIM_E_ARG, "out is NULL");
-  if (O) HIP_TRY(hipMemcpy(out, s->outputs, (size_t)O * 8, hipMemcpyDeviceToHost));
-  return FSIM_OK;
+  if (!s->batched) {
+    if (O) HIP_TRY(hipMemcpy(out, s->outputs, (size_t)O * 8, hipMemcpyDeviceToHost));
+    return FSIM_OK;
+  }
+  return col_read(s->outputs, 8, s->n_pad, inst, O, out);
 }
 
 extern "C" int fsim_read_mem(fsim_sim* s, uint32_t inst, uint32_t m, uint64_t* out) {
@@ -561,8 +785,11 @@ extern "C" int fsim_read_mem(fsim_sim* s, uint32_t inst, uint32_t m, uint64_t* o
   const Design& d = s->d->d;
   if (m >= d.M) return fail(FSIM_E_ARG, "memory out of range");
   if (!out) return fail(FSIM_E_ARG, "out is NULL");
-  HIP_TRY(hipMemcpy(out, s->mem + d.mem_off[m], (size_t)d.mem_depth[m] * 8, hipMemcpyDeviceToHost));
-  return FSIM_OK;
+  if (!s->batched) {
+    HIP_TRY(hipMemcpy(out, s->mem + d.mem_off[m], (size_t)d.mem_depth[m] * 8, hipMemcpyDeviceToHost));
+    return FSIM_OK;
+  }
+  return col_read(s->mem + d.mem_off[m] * s->n_pad, 8, s->n_pad, inst, d.mem_depth[m], out);
 }
 
 extern "C" int fsim_write_mem(fsim_sim* s, uint32_t inst, uint32_t m, const uint64_t* in) {
@@ -573,17 +800,29 @@ extern "C" int fsim_write_mem(fsim_sim* s, uint32_t inst, uint32_t m, const uint
   if (!in) return fail(FSIM_E_ARG, "in is NULL");
   std::vector<uint64_t> v(in, in + d.mem_depth[m]);
   for (auto& x : v) x &= ~0ull >> (64 - d.mem_width[m]);
-  HIP_TRY(hipMemcpy(s->mem + d.mem_off[m], v.data(), v.size() * 8, hipMemcpyHostToDevice));
-  return FSIM_OK;
+  if (!s->batched) {
+    HIP_TRY(hipMemcpy(s->mem + d.mem_off[m], v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    return FSIM_OK;
+  }
+  return col_write(s->mem + d.mem_off[m] * s->n_pad, 8, s->n_pad, inst, d.mem_depth[m], v.data());
 }
 
 extern "C" int fsim_set_cycle(fsim_sim* s, uint64_t cycle) {
   int rc = check_inst(s, 0);
   if (rc) return rc;
-  const uint32_t R = s->d->d.R;
-  if ((cycle & 1) != (s->cycle & 1) && R)
-    HIP_TRY(hipMemcpy(s->state + (cycle & 1) * R, s->state + (s->cycle & 1) * R, (size_t)R * 8 * s->n_inst,
-                      hipMemcpyDeviceToDevice));
+  const Design& d = s->d->d;
+  if ((cycle & 1) != (s->cycle & 1)) {
+    const size_t from = s->cycle & 1, to = cycle & 1;
+    if (!s->batched) {
+      if (d.R) HIP_TRY(hipMemcpy(s->state + to * d.R, s->state + from * d.R, (size_t)d.R * 8, hipMemcpyDeviceToDevice));
+    } else {
+      const size_t nb = (size_t)d.reg_count[0] * s->n_tiles, nw = (size_t)d.reg_count[1] * s->n_pad,
+                   nd = (size_t)d.reg_count[2] * s->n_pad;
+      if (nb) HIP_TRY(hipMemcpy(s->stB + to * nb, s->stB + from * nb, nb * 8, hipMemcpyDeviceToDevice));
+      if (nw) HIP_TRY(hipMemcpy(s->stW + to * nw, s->stW + from * nw, nw * 4, hipMemcpyDeviceToDevice));
+      if (nd) HIP_TRY(hipMemcpy(s->stD + to * nd, s->stD + from * nd, nd * 8, hipMemcpyDeviceToDevice));
+    }
+  }
   s->cycle = cycle;
   return FSIM_OK;
 }
@@ -598,8 +837,10 @@ extern "C" int fsim_enable_digest(fsim_sim* s, uint64_t* dev_out, uint64_t max_c
     s->dig_max = 0;
     return FSIM_OK;
   }
-  HIP_TRY(s->dig_part.alloc((size_t)max_cycles * s->G * 8 * s->n_inst));
-  HIP_TRY(hipMemsetAsync(s->dig_part.p, 0, (size_t)max_cycles * s->G * 8 * s->n_inst, st));
+  if (!s->batched) {           // plain: per-workgroup partials, reduced after each step
+    HIP_TRY(s->dig_part.alloc((size_t)max_cycles * s->G * 8));
+    HIP_TRY(hipMemsetAsync(s->dig_part.p, 0, (size_t)max_cycles * s->G * 8, st));
+  }
   HIP_TRY(hipMemsetAsync(dev_out, 0, (size_t)max_cycles * 8 * s->n_inst, st));
   HIP_TRY(hipStreamSynchronize(st));
   s->dig_out = dev_out;
@@ -634,7 +875,7 @@ extern "C" int fsim_enable_trace(fsim_sim* s, uint64_t* dev_out, uint64_t max_cy
 extern "C" int fsim_sim_layout(const fsim_sim* s, uint32_t* workgroups, uint32_t* threads,
                                uint32_t* launch, uint32_t* staged) {
   if (!s) return fail(FSIM_E_ARG, "sim is NULL");
-  if (workgroups) *workgroups = s->G;
+  if (workgroups) *workgroups = s->batched ? batch_grid(s) : s->G;
   if (threads) *threads = s->threads;
   if (launch) *launch = s->launch;
   if (staged) *staged = s->stage_instr ? 1 : 0;
