@@ -166,6 +166,12 @@ int fsim_design_info_get(const fsim_design* d, fsim_design_info* out);
 int fsim_design_partition(const fsim_design* d, uint32_t* sink_to_process,
                           uint32_t* proc_off, uint32_t* proc_nodes);
 void fsim_design_free(fsim_design* d);
+/* Batched-form encoding (done on first use, also on a host-only design): the
+ * most live LDS slots any process needs per class (1-bit masks, <= 32-bit,
+ * <= 64-bit values), the instruction count, and the LDS bytes one wave of 64
+ * instances needs.  Any output pointer may be NULL. */
+int fsim_design_batched_info(fsim_design* d, uint32_t* slots_b, uint32_t* slots_w,
+                             uint32_t* slots_d, uint64_t* n_instr, uint64_t* wave_lds_bytes);
 
 /* ------------------------------------------------------------ simulation
  * A sim holds n_instances independent copies of the design state.  One
@@ -250,6 +256,74 @@ int fsim_enable_trace(fsim_sim* s, uint64_t* dev_out, uint64_t max_cycles, uint3
  * launch mode, and whether the process instructions are staged in LDS. */
 int fsim_sim_layout(const fsim_sim* s, uint32_t* workgroups, uint32_t* threads,
                     uint32_t* launch, uint32_t* staged);
+
+/* ---------------------------------------------------------------- serving
+ * A request loop with continuous batching (the many-short-tests scenario of
+ * Sec. 6.4 sharing one GPU).  Jobs (design, instances, cycle budget, stimulus
+ * seed) are admitted while their device footprint (fsim_sim_footprint) fits
+ * the HBM budget -- first fit in arrival order, a long-blocked head job stops
+ * later ones from overtaking it -- keep their state resident, and advance
+ * together: each tick is one launch in which every resident job simulates one
+ * cycle (batched form).  Every quantum_cycles cycles finished jobs retire
+ * (final registers and outputs copied to host memory, device memory freed)
+ * and queued jobs are admitted.  A job's results do not depend on the other
+ * jobs in the mix.  ctx = NULL gives a host-only executor that advances cycle
+ * counters without simulating (for testing the scheduling logic); it keeps
+ * no results.  All server calls are thread-safe. */
+typedef struct fsim_server fsim_server;
+
+#define FSIM_JOB_QUEUED     0
+#define FSIM_JOB_RUNNING    1
+#define FSIM_JOB_DONE       2
+#define FSIM_JOB_CANCELLED  3
+#define FSIM_JOB_FAILED     4
+
+typedef struct fsim_server_opts {
+  uint32_t quantum_cycles;  /* cycles between retire/admit points (256)     */
+  uint32_t max_jobs;        /* resident jobs at once (64)                   */
+  uint32_t max_queue;       /* queued jobs before FSIM_E_BUSY (4096)        */
+  uint32_t host_cycle_ns;   /* host-only executor: wall time per simulated
+                               cycle of a quantum (1000)                    */
+} fsim_server_opts;
+
+typedef struct fsim_job_status {
+  int32_t state;            /* FSIM_JOB_*                                    */
+  uint32_t n_instances;
+  uint64_t cycles_done, n_cycles;
+  uint64_t device_bytes;    /* footprint counted against the budget          */
+  double t_submit, t_start, t_done;   /* seconds since server creation; -1 = not yet */
+} fsim_job_status;
+
+typedef struct fsim_server_stats {
+  uint64_t submitted, completed, cancelled, rejected, failed, running, queued;
+  uint64_t quanta;
+  uint64_t instance_cycles; /* simulated cycles x instances executed         */
+  double busy_seconds;      /* wall time of quanta with device work          */
+  double elapsed_seconds;   /* since creation                                */
+  uint64_t hbm_used, hbm_budget;
+} fsim_server_stats;
+
+int fsim_server_create(fsim_ctx* ctx, size_t hbm_budget, const fsim_server_opts* opts,
+                       fsim_server** out);
+/* Non-blocking.  FSIM_E_CAPACITY if the job can never fit the budget,
+ * FSIM_E_BUSY if the queue is full.  The design stays referenced until the
+ * job is released. */
+int fsim_server_submit(fsim_server* s, fsim_design* d, uint32_t n_instances, uint64_t n_cycles,
+                       uint64_t seed_base, uint64_t* job_id);
+int fsim_server_poll(fsim_server* s, uint64_t job_id, fsim_job_status* st);
+/* Blocks until the job is done, cancelled or failed; timeout_s < 0 waits
+ * forever; FSIM_E_BUSY on timeout. */
+int fsim_server_wait(fsim_server* s, uint64_t job_id, double timeout_s);
+/* Final registers (n_regs) and outputs (n_outputs) of one instance of a
+ * finished job; either pointer may be NULL. */
+int fsim_server_result(fsim_server* s, uint64_t job_id, uint32_t inst, uint64_t* regs_out,
+                       uint64_t* outputs_out);
+/* A queued job is dropped at once, a running one at the next quantum end. */
+int fsim_server_cancel(fsim_server* s, uint64_t job_id);
+/* Forget a finished job and its stored results. */
+int fsim_server_release(fsim_server* s, uint64_t job_id);
+int fsim_server_stats_get(fsim_server* s, fsim_server_stats* out);
+void fsim_server_destroy(fsim_server* s);
 
 #ifdef __cplusplus
 }

@@ -26,10 +26,12 @@ def build(verbose: bool = False) -> str:
     common = ["-O3", "-std=c++17", "-fPIC", f"-I{CSRC}", f"-I{os.path.join(HERE, '..', 'include')}"]
     for src in sources():
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")
-        cmd = ["hipcc", *common, "-c", src, "-o", obj]
+        # every translation unit targets gfx950 only (host-only files carry no
+        # device code, but must not default to another architecture)
+        cmd = ["hipcc", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+               "-packed-fp32-ops", *common, "-c", src, "-o", obj]
         if src.endswith(".hip"):
-            cmd[1:1] = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-                        "-packed-fp32-ops", "-x", "hip"]
+            cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -20,6 +20,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <queue>
@@ -27,6 +29,16 @@
 #include <unordered_set>
 
 namespace fsim {
+
+// phase timing of the compiler, printed to stderr when FSIM_VERBOSE is set
+static void phase(const char* what) {
+  static const bool on = getenv("FSIM_VERBOSE") != nullptr;
+  static auto t0 = std::chrono::steady_clock::now();
+  if (!on) return;
+  auto t = std::chrono::steady_clock::now();
+  fprintf(stderr, "fsim compile: %-28s %8.3f s\n", what, std::chrono::duration<double>(t - t0).count());
+  t0 = t;
+}
 
 static inline int arity(uint8_t op) {
   switch (op) {
@@ -144,6 +156,7 @@ Status copy_and_validate(const fsim_netlist* nl, Design& d) {
     }
   }
   if (q.size() != d.N) return Status::err(FSIM_E_COMB_LOOP, "combinational loop in the netlist");
+  phase("validate + levels");
   d.cost.assign(d.N, 0);
   for (uint32_t n = 0; n < d.N; ++n) {
     uint8_t op = d.op[n];
@@ -219,7 +232,20 @@ std::vector<uint32_t> set_union(const std::vector<uint32_t>& a, const std::vecto
 struct SlbResult {
   uint32_t n_alive = 0;
   std::vector<uint32_t> proc_of_sink;
+  // the surviving processes, for a later stage to continue from
+  std::vector<std::vector<uint32_t>> nodes, sinks;
+  std::vector<uint64_t> cost;
 };
+
+// who reads each register: the processes whose node sets hold its REG node
+std::vector<std::vector<uint32_t>> register_readers(const Design& d,
+                                                    const std::vector<std::vector<uint32_t>>& nodes) {
+  std::vector<std::vector<uint32_t>> readers(d.R);
+  for (uint32_t p = 0; p < (uint32_t)nodes.size(); ++p)
+    for (uint32_t x : nodes[p])
+      if (d.op[x] == FSIM_OP_REG) readers[d.imm[x]].push_back(p);
+  return readers;
+}
 
 SlbResult slb_merge(const Design& d, const std::vector<std::vector<uint32_t>>& nodes0,
                     const std::vector<uint64_t>& cost0, const std::vector<std::vector<uint32_t>>& sinks0,
@@ -315,7 +341,13 @@ SlbResult slb_merge(const Design& d, const std::vector<std::vector<uint32_t>>& n
   r.n_alive = 0;
   r.proc_of_sink.assign(d.n_sinks(), 0);
   for (uint32_t p = 0; p < P0; ++p)
-    if (alive[p]) { for (uint32_t s : sinks[p]) r.proc_of_sink[s] = r.n_alive; r.n_alive++; }
+    if (alive[p]) {
+      for (uint32_t s : sinks[p]) r.proc_of_sink[s] = r.n_alive;
+      r.n_alive++;
+      r.nodes.push_back(std::move(nodes[p]));
+      r.sinks.push_back(std::move(sinks[p]));
+      r.cost.push_back(cost[p]);
+    }
   return r;
 }
 
@@ -365,6 +397,7 @@ Status partition_design(Design& d, const fsim_partition* part, const fsim_compil
   }
   d.n_live_ops = 0;
   for (uint32_t n = 0; n < d.N; ++n) if (live[n] && d.op[n] >= FSIM_OP_MEMRD) d.n_live_ops++;
+  phase("fibers (reverse crawl)");
 
   // ---- stage 1: every sink that reads memory m shares a process with m's
   // write ports, so the end-of-cycle commit never races a read elsewhere
@@ -430,37 +463,60 @@ Status partition_design(Design& d, const fsim_partition* part, const fsim_compil
         straggler = std::max(straggler, cost0[p]);
         total += cost0[p];
       }
-      std::vector<std::vector<uint32_t>> readers(d.R);
-      for (uint32_t p = 0; p < P0; ++p)
-        for (uint32_t x : nodes0[p])
-          if (d.op[x] == FSIM_OP_REG) readers[d.imm[x]].push_back(p);
+      std::vector<std::vector<uint32_t>> readers = register_readers(d, nodes0);
+      phase("initial processes");
       SlbResult best;
       // stage 3: conservative merge, the straggler bound stays put
       SlbResult r3 = slb_merge(d, nodes0, cost0, sinks0, readers, straggler, target, max_nodes);
+      phase("stage 3");
       if (r3.n_alive <= target) {
         best = std::move(r3);
       } else {
-        // stage 4: the straggler may grow; the smallest bound under which the
-        // same merge reaches the target is found by bisection
-        uint64_t lo = std::max<uint64_t>(straggler, (total + target - 1) / target), hi = total;
-        SlbResult r = slb_merge(d, nodes0, cost0, sinks0, readers, hi, target, max_nodes);
-        if (r.n_alive > target)
-          return Status::err(FSIM_E_CAPACITY,
-              fmt("cannot pack the design into %llu processes of at most %llu nodes", target, max_nodes));
-        best = std::move(r);
-        for (int it = 0; it < 18 && lo < hi; ++it) {
+        // stage 4 continues from stage 3's processes; the straggler may now
+        // grow.  The smallest bound under which the merge reaches the target
+        // is searched upward from max(straggler, total / target):
+        // geometrically, then by bisection between the last failing and the
+        // first passing bound.
+        std::vector<std::vector<uint32_t>> n3 = std::move(r3.nodes), s3 = std::move(r3.sinks);
+        std::vector<uint64_t> c3 = std::move(r3.cost);
+        const uint32_t P3 = (uint32_t)n3.size();
+        uint64_t total3 = 0;
+        for (uint64_t x : c3) total3 += x;
+        std::vector<std::vector<uint32_t>> readers3 = register_readers(d, n3);
+        uint64_t lo = std::max<uint64_t>(straggler, (total3 + target - 1) / target), hi = 0;
+        bool found = false;
+        const double grow = P3 > 20000 ? 1.04 : 1.1;
+        for (uint64_t B = lo; B <= total3; B = std::max<uint64_t>(B + 1, (uint64_t)(B * grow))) {
+          SlbResult t = slb_merge(d, n3, c3, s3, readers3, B, target, max_nodes);
+          phase("stage 4 trial");
+          if (t.n_alive <= target) { hi = B; best = std::move(t); found = true; break; }
+          lo = B + 1;
+          if (B == total3) break;
+          if (B * grow >= total3) B = total3 - 1;
+        }
+        if (!found) {
+          SlbResult t = slb_merge(d, n3, c3, s3, readers3, total3, target, max_nodes);
+          if (t.n_alive > target)
+            return Status::err(FSIM_E_CAPACITY,
+                fmt("cannot pack the design into %llu processes of at most %llu nodes", target, max_nodes));
+          best = std::move(t);
+          hi = total3;
+        }
+        const int max_bisect = P3 > 20000 ? 3 : 16;
+        for (int it = 0; it < max_bisect && lo < hi; ++it) {
           uint64_t mid = lo + (hi - lo) / 2;
-          SlbResult t = slb_merge(d, nodes0, cost0, sinks0, readers, mid, target, max_nodes);
+          SlbResult t = slb_merge(d, n3, c3, s3, readers3, mid, target, max_nodes);
           if (t.n_alive <= target) { hi = mid; best = std::move(t); }
           else lo = mid + 1;
-          if (hi - lo <= std::max<uint64_t>(1, hi / 100)) break;
         }
       }
       for (uint32_t s = 0; s < S; ++s) d.sink_proc[s] = best.proc_of_sink[s];
       d.P = std::max(best.n_alive, 1u);
+      phase("stage 4");
     }
   }
 
+  phase("packing");
   // ---- process node lists: union of member cones, ordered by level
   d.psink_off.assign(d.P + 1, 0);
   for (uint32_t s = 0; s < S; ++s) d.psink_off[d.sink_proc[s] + 1]++;
@@ -513,6 +569,7 @@ static Instr make(uint8_t op, uint8_t w, uint16_t dst, uint16_t a, uint16_t b, u
 }
 
 Status encode_plain(Design& d, uint32_t max_slots) {
+  phase("process node lists");
   d.plain_procs.assign(d.P, PlainProc{});
   d.plain_levels.clear();
   d.plain_instr.clear();
@@ -630,6 +687,7 @@ Status encode_plain(Design& d, uint32_t max_slots) {
     d.max_plain_lvls = std::max(d.max_plain_lvls, n_lvls);
     for (uint32_t j = lo; j < hi; ++j) slot[d.proc_nodes[j]] = UINT32_MAX;
   }
+  phase("encode plain");
   return {};
 }
 
@@ -698,15 +756,38 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
       else if (s < d.R + d.W) { uint32_t q = s - d.R; visit(d.wp_en[q]); visit(d.wp_addr[q]); visit(d.wp_data[q]); }
       else visit(d.out_node[s - d.R - d.W]);
     }
-    // ---- liveness (positions in order; sinks read at their store point)
+    // ---- leaf loads in groups: the order is cut into segments holding at
+    // most kGroup register/input leaves, and each segment's leaves move to its
+    // start (a leaf has no operands, so any earlier position is valid).  The
+    // kernel then issues a group's loads back to back and waits once, instead
+    // of one full memory latency per leaf.
+    {
+      const size_t kGroup = 16;
+      std::vector<uint32_t> out, leaves, rest;
+      out.reserve(order.size());
+      auto flush = [&]() {
+        out.insert(out.end(), leaves.begin(), leaves.end());
+        out.insert(out.end(), rest.begin(), rest.end());
+        leaves.clear(); rest.clear();
+      };
+      for (uint32_t x : order) {
+        const bool leaf = d.op[x] == FSIM_OP_REG || d.op[x] == FSIM_OP_INPUT;
+        if (leaf && leaves.size() == kGroup) flush();
+        (leaf ? leaves : rest).push_back(x);
+      }
+      flush();
+      order.swap(out);
+      for (uint32_t i = 0; i < (uint32_t)order.size(); ++i) emitted[order[i]] = i;
+    }
+    // ---- liveness (positions in order; sinks read at the end)
     const uint32_t n_ord = (uint32_t)order.size();
     for (uint32_t i = 0; i < n_ord; ++i) last_use[order[i]] = i;
     for (uint32_t i = 0; i < n_ord; ++i) {
       uint32_t x = order[i];
       for (int k = 0; k < arity(d.op[x]); ++k) last_use[d.arg[3ull * x + k]] = std::max(last_use[d.arg[3ull * x + k]], i);
     }
-    // register stores happen right after the producing node; write ports and
-    // outputs need their values until the end
+    // register and output stores follow the instruction that produces the
+    // value (short live ranges); write ports need their values until the end
     std::vector<std::vector<uint32_t>> stores_after(n_ord);
     for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
       uint32_t s = d.psinks[k];
@@ -812,6 +893,16 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
     }
     bp.n_instr = (uint32_t)d.batch_instr.size() - bp.instr_off;
     bp.n_consts = (uint32_t)d.batch_consts.size() - bp.const_off;
+    // runs of consecutive leaf loads (at most 16): the first carries the run
+    // length in flags, the kernel executes the run as one group
+    for (uint32_t i = bp.instr_off; i < bp.instr_off + bp.n_instr;) {
+      auto is_leaf = [&](uint32_t j) { return d.batch_instr[j].op == I_LDREG || d.batch_instr[j].op == I_LDIN; };
+      if (!is_leaf(i)) { ++i; continue; }
+      uint32_t j = i;
+      while (j < bp.instr_off + bp.n_instr && j - i < 16 && is_leaf(j)) ++j;
+      d.batch_instr[i].flags = (uint8_t)(j - i);
+      i = j;
+    }
     for (int k = 0; k < 3; ++k) {
       bp.slots[k] = used[k];
       d.batch_slots[k] = std::max(d.batch_slots[k], used[k]);

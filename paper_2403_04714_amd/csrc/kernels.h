@@ -72,6 +72,9 @@ struct BatchArgs {
 
 hipError_t launch_batched(const BatchArgs& a, uint32_t grid, uint32_t threads, size_t lds_bytes,
                           hipStream_t s);
+hipError_t launch_batched_multi(const BatchArgs* jobs, const uint32_t* wg_start, const uint64_t* cycle_base,
+                                const uint32_t* ticks, uint32_t n_jobs, uint32_t tick, uint32_t grid,
+                                size_t lds_bytes, hipStream_t s);
 hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t lds_bytes,
                         bool persistent, hipStream_t s);
 hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged);

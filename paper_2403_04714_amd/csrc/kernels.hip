@@ -327,13 +327,24 @@ __global__ void stim_keys(uint64_t* keys, uint64_t seed_base, uint32_t n_inst, u
 // Operators whose operands and result are all 1-bit work on the masks
 // directly.
 
+// Read-only for the whole launch (program, constant pool, memory tables, the
+// current half of the state): reading through the constant address space lets
+// the compiler use scalar loads for wave-uniform addresses instead of a vector
+// load plus a wait for every interpreted instruction.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+
 struct WaveSlots {
   uint64_t* B;   // [slotsB]
   uint32_t* W;   // [slotsW][64]
   uint64_t* D;   // [slotsD][64]
 };
 
-__device__ __forceinline__ uint64_t bread(const WaveSlots& S, const uint64_t* K, uint32_t cls, uint32_t s,
+__device__ __forceinline__ uint64_t bread(const WaveSlots& S, cptr<uint64_t> K, uint32_t cls, uint32_t s,
                                           uint32_t lane) {
   switch (cls) {
     case C_B: return (S.B[s] >> lane) & 1;
@@ -356,14 +367,14 @@ __device__ __forceinline__ void bwrite(const WaveSlots& S, uint32_t cls, uint32_
 }
 
 // the 64-lane mask of a 1-bit operand: B slots as stored, constants by bit 0
-__device__ __forceinline__ uint64_t bmask(const WaveSlots& S, const uint64_t* K, uint32_t cls, uint32_t s) {
+__device__ __forceinline__ uint64_t bmask(const WaveSlots& S, cptr<uint64_t> K, uint32_t cls, uint32_t s) {
   return cls == C_B ? S.B[s] : ((K[s] & 1) ? ~0ull : 0ull);
 }
 
-__global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
-  extern __shared__ uint64_t lds[];
+// One simulated cycle of one (process, tile group) work item of a batched sim.
+__device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block, uint64_t cyc, uint64_t* lds) {
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t p = blockIdx.x % A.P, grp = blockIdx.x / A.P;
+  const uint32_t p = block % A.P, grp = block / A.P;
   const uint32_t tile = grp * A.tpw + wave;
   if (tile >= A.n_tiles) return;                 // no barriers below: a wave may leave early
   const uint32_t inst = tile * 64 + lane;        // < n_pad
@@ -374,11 +385,12 @@ __global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
   S.W = reinterpret_cast<uint32_t*>(S.B + A.slotsB);
   S.D = S.B + A.slotsB + (A.slotsW * 64 + 1) / 2;
   const BatchProc bp = A.procs[p];
-  const Instr* __restrict__ prog = A.instr + bp.instr_off;
-  const uint64_t* __restrict__ K = A.consts + bp.const_off;
-  const uint64_t cyc = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
+  const cptr<uint32_t> prog = as_const(reinterpret_cast<const uint32_t*>(A.instr + bp.instr_off));
+  const cptr<uint64_t> K = as_const(A.consts + bp.const_off);
+  const cptr<uint64_t> mem_off = as_const(A.mem_off);
+  const cptr<uint32_t> mem_depth = as_const(A.mem_depth);
   const uint32_t cur = cyc & 1, nxt = cur ^ 1;
-  const uint64_t* stB_cur = A.stB + (size_t)cur * A.nB * A.n_tiles;
+  const cptr<uint64_t> stB_cur = as_const(A.stB + (size_t)cur * A.nB * A.n_tiles);
   uint64_t* stB_nxt = A.stB + (size_t)nxt * A.nB * A.n_tiles;
   const uint32_t* stW_cur = A.stW + (size_t)cur * A.nW * A.n_pad;
   uint32_t* stW_nxt = A.stW + (size_t)nxt * A.nW * A.n_pad;
@@ -387,42 +399,65 @@ __global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
   uint64_t dacc = 0;
   for (uint32_t i = 0; i < bp.n_instr; ++i) {
     // wave-uniform instruction (scalar registers)
-    const uint4 raw = reinterpret_cast<const uint4*>(prog)[i];
-    const uint32_t x = __builtin_amdgcn_readfirstlane(raw.x), y = __builtin_amdgcn_readfirstlane(raw.y);
-    const uint32_t z = __builtin_amdgcn_readfirstlane(raw.z), aux = __builtin_amdgcn_readfirstlane(raw.w);
+    const uint32_t x = prog[4 * i], y = prog[4 * i + 1], z = prog[4 * i + 2], aux = prog[4 * i + 3];
     const uint32_t op = x & 0xFF, w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
     const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
     const uint32_t dst = y & 0xFFFF, sa = y >> 16, sb = z & 0xFFFF, sc = z >> 16;
     switch (op) {
-      case I_LDREG: {
-        // ca: class of the register's state array; cd: class of the node
-        if (ca == C_B) {
-          const uint64_t m = stB_cur[(size_t)aux * A.n_tiles + tile];
-          if (cd == C_B) { if (lane == 0) S.B[dst] = m; }
-          else bwrite(S, cd, dst, lane, (m >> lane) & 1);
-        } else {
-          const uint64_t v = ca == C_W ? (uint64_t)stW_cur[(size_t)aux * A.n_pad + inst]
-                                       : stD_cur[(size_t)aux * A.n_pad + inst];
-          bwrite(S, cd, dst, lane, v & wmask(w));
-        }
-        break;
-      }
+      case I_LDREG:
       case I_LDIN: {
-        uint64_t v;
-        if (A.in_vals) {
-          if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v = 0; }
-          else v = real ? A.in_vals[((cyc - A.in_first) * A.I + aux) * A.n_inst + inst] : 0;
-        } else {
-          v = hmix(A.keys[(size_t)aux * A.n_pad + inst] ^ cyc);
+        // a run of up to 16 leaf loads (length in flags): every load is issued
+        // before any result is used, so the run costs one memory latency
+        const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
+        uint64_t val[16];
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k) {
+          if (k < n) {
+            const uint32_t xk = prog[4 * (i + k)], auxk = prog[4 * (i + k) + 3];
+            const uint32_t cak = (xk >> 18) & 3;
+            if ((xk & 0xFF) == I_LDREG) {
+              val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
+                     : cak == C_W ? (uint64_t)stW_cur[(size_t)auxk * A.n_pad + inst]
+                                  : stD_cur[(size_t)auxk * A.n_pad + inst];
+            } else if (A.in_vals) {
+              val[k] = (real && cyc >= A.in_first && cyc < A.in_first + A.in_count)
+                           ? A.in_vals[((cyc - A.in_first) * A.I + auxk) * A.n_inst + inst] : 0;
+            } else {
+              val[k] = A.keys[(size_t)auxk * A.n_pad + inst];
+            }
+          }
         }
-        bwrite(S, cd, dst, lane, v & wmask(w));
+#pragma unroll
+        for (uint32_t k = 0; k < 16; ++k) {
+          if (k < n) {
+            const uint32_t xk = prog[4 * (i + k)], yk = prog[4 * (i + k) + 1];
+            const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
+            const uint32_t dk = yk & 0xFFFF;
+            if ((xk & 0xFF) == I_LDREG) {
+              if (cak == C_B) {
+                if (cdk == C_B) { if (lane == 0) S.B[dk] = val[k]; }
+                else bwrite(S, cdk, dk, lane, (val[k] >> lane) & 1);
+              } else {
+                bwrite(S, cdk, dk, lane, val[k] & wmask(wk));
+              }
+            } else {
+              if (A.in_vals) {
+                if (cyc < A.in_first || cyc >= A.in_first + A.in_count) atomicOr(&A.error[1], 1u);
+                bwrite(S, cdk, dk, lane, val[k] & wmask(wk));
+              } else {
+                bwrite(S, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
+              }
+            }
+          }
+        }
+        i += n - 1;
         break;
       }
       case I_MEMRD: {
         const uint64_t a = bread(S, K, ca, sa, lane);
-        const uint64_t depth = A.mem_depth[aux];
+        const uint64_t depth = mem_depth[aux];
         const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-        bwrite(S, cd, dst, lane, A.mem[(A.mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
+        bwrite(S, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
         break;
       }
       case I_STREG: {
@@ -446,9 +481,9 @@ __global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
         const uint64_t en = bread(S, K, ca, sa, lane), a = bread(S, K, cb, sb, lane);
         const uint64_t v = bread(S, K, cc, sc, lane);
         if (en) {
-          const uint64_t depth = A.mem_depth[aux];
+          const uint64_t depth = mem_depth[aux];
           const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-          A.mem[(A.mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
+          A.mem[(mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
         }
         break;
       }
@@ -488,6 +523,34 @@ __global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
   }
 }
 
+__global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
+  extern __shared__ uint64_t lds[];
+  const uint64_t cyc = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
+  batched_body(A, blockIdx.x, cyc, lds);
+}
+
+// Serving: one launch advances every resident job by one cycle.  Job j owns
+// workgroups [wg_start[j], wg_start[j + 1]); a job whose budget for this
+// quantum is spent (tick >= ticks[j]) does nothing.  All jobs share the
+// launch's LDS size (the largest job's) and 64 threads per workgroup.
+__global__ void __launch_bounds__(64) batched_multi(const BatchArgs* __restrict__ jobs,
+                                                    const uint32_t* __restrict__ wg_start,
+                                                    const uint64_t* __restrict__ cycle_base,
+                                                    const uint32_t* __restrict__ ticks, uint32_t n_jobs,
+                                                    uint32_t tick) {
+  extern __shared__ uint64_t lds[];
+  // the job of this workgroup: binary search over the prefix table
+  uint32_t lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (wg_start[mid] <= blockIdx.x) lo = mid; else hi = mid;
+  }
+  const uint32_t j = lo;
+  if (tick >= ticks[j]) return;
+  const BatchArgs A = jobs[j];
+  batched_body(A, blockIdx.x - wg_start[j], cycle_base[j] + tick, lds);
+}
+
 }  // namespace fsim
 
 // ---------------------------------------------------------------- launches
@@ -508,6 +571,15 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t
 hipError_t launch_batched(const BatchArgs& a, uint32_t grid, uint32_t threads, size_t lds_bytes,
                           hipStream_t s) {
   hipLaunchKernelGGL(batched_cycle, dim3(grid), dim3(threads), lds_bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_multi(const BatchArgs* jobs, const uint32_t* wg_start, const uint64_t* cycle_base,
+                                const uint32_t* ticks, uint32_t n_jobs, uint32_t tick, uint32_t grid,
+                                size_t lds_bytes, hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(batched_multi, dim3(grid), dim3(64), lds_bytes, s, jobs, wg_start, cycle_base, ticks,
+                     n_jobs, tick);
   return hipGetLastError();
 }
 

@@ -11,104 +11,30 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fibersim.h"
-#include "compiler.h"
-#include "kernels.h"
+#include "runtime_internal.h"
 
 using fsim::Design;
 using fsim::Status;
 
+namespace fsim {
 namespace {
 thread_local std::string g_last_error;
-
+}
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
-int fail(const Status& s) { return fail(s.code, s.msg); }
+}  // namespace fsim
 
-#define HIP_TRY(expr)                                                                    \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(FSIM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
-  } while (0)
+using fsim::fail;
+using fsim::DevBuf;
+using fsim::align256;
+using fsim::batch_args;
+using fsim::batch_grid;
+using fsim::batched_wave_bytes;
+using fsim::ensure_batched;
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// A device buffer the library owns.
-struct DevBuf {
-  void* p = nullptr;
-  size_t n = 0;
-  ~DevBuf() { if (p) (void)hipFree(p); }
-  hipError_t alloc(size_t bytes) {
-    if (p) { (void)hipFree(p); p = nullptr; }
-    n = bytes;
-    return hipMalloc(&p, bytes ? bytes : 256);
-  }
-};
-}  // namespace
-
-struct fsim_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  uint32_t n_cus = 0, lds_bytes = 0;
-  std::mutex mu;
-};
-
-struct fsim_design {
-  std::atomic<int> refs{1};
-  fsim_ctx* ctx = nullptr;          // null: compiled on the host only
-  Design d;
-  fsim_design_info info{};
-  // plain-form program on the device
-  DevBuf instr, levels, chunks, procs, consts, mem_off, mem_depth, in_width;
-  uint32_t slot_words = 0, max_proc_instr = 0, max_lvls = 0, max_chunks = 0;
-  // batched-form program, encoded on first use
-  std::mutex batch_mu;
-  bool batch_ready = false;
-  DevBuf b_instr, b_procs, b_consts;
-};
-
-struct fsim_sim {
-  fsim_design* d = nullptr;
-  uint32_t n_inst = 1;
-  bool batched = false;
-  uint32_t n_tiles = 1, n_pad = 64, tpw = 1;
-  uint64_t *stB = nullptr, *stD = nullptr;
-  uint32_t* stW = nullptr;
-  uint32_t G = 1, threads = 256, launch = FSIM_LAUNCH_PERSISTENT, graph_cycles = 64;
-  size_t lds_bytes = 0;
-  bool stage_instr = false;
-  bool poisoned = false;
-  uint64_t cycle = 0, seed = 0;
-  uint32_t epoch = 0;
-  // device memory: workspace (owned or borrowed) and its carve-up
-  DevBuf own_ws;
-  char* ws = nullptr;
-  uint64_t *state = nullptr, *outputs = nullptr, *mem = nullptr, *keys = nullptr, *cyc_dev = nullptr;
-  uint32_t *flags = nullptr, *error = nullptr;
-  // explicit inputs
-  DevBuf in_vals;
-  uint64_t in_first = 0, in_count = 0;
-  bool explicit_inputs = false;
-  // digests
-  uint64_t* dig_out = nullptr;
-  uint64_t dig_first = 0, dig_max = 0;
-  DevBuf dig_part;
-  // phase timestamps
-  uint64_t* trace = nullptr;
-  uint64_t trace_first = 0, trace_max = 0;
-  // graph mode
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  ~fsim_sim() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-  }
-};
-
-extern "C" const char* fsim_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* fsim_last_error(void) { return fsim::g_last_error.c_str(); }
 
 // ------------------------------------------------------------------ context
 extern "C" int fsim_ctx_create(int hip_device, void* hip_stream, fsim_ctx** out) {
@@ -238,11 +164,12 @@ extern "C" int fsim_design_partition(const fsim_design* dd, uint32_t* sink_to_pr
   return FSIM_OK;
 }
 
-static void design_release(fsim_design* d) {
+void fsim::design_retain(fsim_design* d) { if (d) d->refs++; }
+void fsim::design_release(fsim_design* d) {
   if (d && --d->refs == 0) delete d;
 }
 
-extern "C" void fsim_design_free(fsim_design* d) { design_release(d); }
+extern "C" void fsim_design_free(fsim_design* d) { fsim::design_release(d); }
 
 // ---------------------------------------------------------------------- sim
 namespace {
@@ -341,12 +268,15 @@ extern "C" int fsim_set_stimulus_seed(fsim_sim* s, uint64_t seed_base) {
   return FSIM_OK;
 }
 
-static int ensure_batched(fsim_design* d) {
+int fsim::ensure_batched(fsim_design* d) {
   std::lock_guard<std::mutex> g(d->batch_mu);
   if (d->batch_ready) return FSIM_OK;
   Design& D = d->d;
-  Status st = fsim::encode_batched(D, nullptr);
-  if (!st.ok()) return fail(st);
+  if (!D.batch_encoded) {
+    Status st = fsim::encode_batched(D, nullptr);
+    if (!st.ok()) return fail(st);
+  }
+  if (!d->ctx) return FSIM_OK;           // host-only design: encoded, not uploaded
   hipStream_t s = d->ctx->stream;
   int rc;
   if ((rc = upload(d->b_instr, D.batch_instr, s))) return rc;
@@ -357,7 +287,22 @@ static int ensure_batched(fsim_design* d) {
   return FSIM_OK;
 }
 
-static size_t batched_wave_bytes(const Design& D) {
+
+extern "C" int fsim_design_batched_info(fsim_design* d, uint32_t* slots_b, uint32_t* slots_w,
+                                        uint32_t* slots_d, uint64_t* n_instr, uint64_t* wave_lds_bytes) {
+  if (!d) return fail(FSIM_E_ARG, "design is NULL");
+  int rc = ensure_batched(d);
+  if (rc) return rc;
+  const Design& D = d->d;
+  if (slots_b) *slots_b = D.batch_slots[0];
+  if (slots_w) *slots_w = D.batch_slots[1];
+  if (slots_d) *slots_d = D.batch_slots[2];
+  if (n_instr) *n_instr = D.batch_instr.size();
+  if (wave_lds_bytes) *wave_lds_bytes = batched_wave_bytes(D);
+  return FSIM_OK;
+}
+
+size_t fsim::batched_wave_bytes(const Design& D) {
   return ((size_t)D.batch_slots[0] + ((size_t)D.batch_slots[1] * 64 + 1) / 2 + (size_t)D.batch_slots[2] * 64) * 8;
 }
 
@@ -485,7 +430,7 @@ extern "C" void fsim_sim_destroy(fsim_sim* s) {
   }
   fsim_design* d = s->d;
   delete s;
-  design_release(d);
+  fsim::design_release(d);
 }
 
 extern "C" int fsim_set_inputs(fsim_sim* s, uint64_t first_cycle, uint32_t n_cycles, const uint64_t* vals) {
@@ -539,7 +484,7 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   return a;
 }
 
-static fsim::BatchArgs batch_args(fsim_sim* s) {
+fsim::BatchArgs fsim::batch_args(fsim_sim* s) {
   const fsim_design* dd = s->d;
   const Design& D = dd->d;
   fsim::BatchArgs a{};
@@ -564,7 +509,7 @@ static fsim::BatchArgs batch_args(fsim_sim* s) {
   return a;
 }
 
-static uint32_t batch_grid(const fsim_sim* s) {
+uint32_t fsim::batch_grid(const fsim_sim* s) {
   return s->d->d.P * ((s->n_tiles + s->tpw - 1) / s->tpw);
 }
 

@@ -84,6 +84,7 @@ SIGNATURES = {
     "fsim_design_info_get": (_I, [_P, _P]),
     "fsim_design_partition": (_I, [_P, _P, _P, _P]),
     "fsim_design_free": (None, [_P]),
+    "fsim_design_batched_info": (_I, [_P, _P, _P, _P, _P, _P]),
     "fsim_sim_footprint": (_I, [_P, _U32, _P]),
     "fsim_sim_create": (_I, [_P, _U32, _P, C.c_size_t, _P, _P]),
     "fsim_sim_destroy": (None, [_P]),
@@ -101,7 +102,42 @@ SIGNATURES = {
     "fsim_enable_digest": (_I, [_P, _P, _U64]),
     "fsim_enable_trace": (_I, [_P, _P, _U64, _P]),
     "fsim_sim_layout": (_I, [_P, _P, _P, _P, _P]),
+    "fsim_server_create": (_I, [_P, C.c_size_t, _P, _P]),
+    "fsim_server_submit": (_I, [_P, _P, _U32, _U64, _U64, _P]),
+    "fsim_server_poll": (_I, [_P, _U64, _P]),
+    "fsim_server_wait": (_I, [_P, _U64, C.c_double]),
+    "fsim_server_result": (_I, [_P, _U64, _U32, _P, _P]),
+    "fsim_server_cancel": (_I, [_P, _U64]),
+    "fsim_server_release": (_I, [_P, _U64]),
+    "fsim_server_stats_get": (_I, [_P, _P]),
+    "fsim_server_destroy": (None, [_P]),
 }
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED, JOB_FAILED = 0, 1, 2, 3, 4
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("quantum_cycles", C.c_uint32), ("max_jobs", C.c_uint32), ("max_queue", C.c_uint32),
+                ("host_cycle_ns", C.c_uint32)]
+
+
+class JobStatus(C.Structure):
+    _fields_ = [("state", C.c_int32), ("n_instances", C.c_uint32), ("cycles_done", C.c_uint64),
+                ("n_cycles", C.c_uint64), ("device_bytes", C.c_uint64), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in ("submitted", "completed", "cancelled", "rejected", "failed",
+                                          "running", "queued", "quanta", "instance_cycles")] + \
+               [("busy_seconds", C.c_double), ("elapsed_seconds", C.c_double),
+                ("hbm_used", C.c_uint64), ("hbm_budget", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 _lib = None
 
@@ -209,6 +245,14 @@ class Design:
         i = DesignInfo()
         _check(lib().fsim_design_info_get(self._h, C.byref(i)), "fsim_design_info_get")
         return i.as_dict()
+
+    def batched_info(self) -> dict:
+        sb, sw, sd = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        ni, wb = C.c_uint64(), C.c_uint64()
+        _check(lib().fsim_design_batched_info(self._h, C.byref(sb), C.byref(sw), C.byref(sd),
+                                              C.byref(ni), C.byref(wb)), "fsim_design_batched_info")
+        return dict(slots_b=sb.value, slots_w=sw.value, slots_d=sd.value, n_instr=ni.value,
+                    wave_lds_bytes=wb.value)
 
     def partition(self):
         info = self.info()
@@ -344,3 +388,58 @@ class Sim:
         if h and _lib is not None:
             _lib.fsim_sim_destroy(h)
             self._h = None
+
+
+class Server:
+    """Continuous-batching request loop (fsim_server_*).  ctx=None gives the
+    host-only executor that advances cycle counters without simulating."""
+
+    def __init__(self, ctx, hbm_budget: int, quantum_cycles=0, max_jobs=0, max_queue=0, host_cycle_ns=0):
+        o = ServerOpts(quantum_cycles, max_jobs, max_queue, host_cycle_ns)
+        h = C.c_void_p()
+        _check(lib().fsim_server_create(ctx._h if ctx is not None else None, hbm_budget, C.byref(o),
+                                        C.byref(h)), "fsim_server_create")
+        self._h = h
+        self.ctx = ctx
+        self._designs = []
+
+    def submit(self, design: Design, n_instances: int, n_cycles: int, seed_base: int) -> int:
+        jid = C.c_uint64()
+        _check(lib().fsim_server_submit(self._h, design._h, n_instances, n_cycles, seed_base & (2**64 - 1),
+                                        C.byref(jid)), "fsim_server_submit")
+        self._designs.append(design)      # keep the Python object alive
+        return jid.value
+
+    def poll(self, job: int) -> dict:
+        st = JobStatus()
+        _check(lib().fsim_server_poll(self._h, job, C.byref(st)), "fsim_server_poll")
+        return st.as_dict()
+
+    def wait(self, job: int, timeout: float = -1.0):
+        _check(lib().fsim_server_wait(self._h, job, timeout), "fsim_server_wait")
+
+    def result(self, job: int, inst: int, design: Design):
+        regs = np.zeros(max(design.n_regs, 1), np.uint64)
+        outs = np.zeros(max(design.n_outputs, 1), np.uint64)
+        _check(lib().fsim_server_result(self._h, job, inst, _ptr(regs), _ptr(outs)), "fsim_server_result")
+        return regs[: design.n_regs], outs[: design.n_outputs]
+
+    def cancel(self, job: int):
+        _check(lib().fsim_server_cancel(self._h, job), "fsim_server_cancel")
+
+    def release(self, job: int):
+        _check(lib().fsim_server_release(self._h, job), "fsim_server_release")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().fsim_server_stats_get(self._h, C.byref(st)), "fsim_server_stats_get")
+        return st.as_dict()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.fsim_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

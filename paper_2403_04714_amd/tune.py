@@ -110,3 +110,64 @@ def tune_plain(ctx, nl, targets=(16, 32, 64, 128, 256), threads=(256, 512, 1024)
         cache[key] = best
         _save_cache(cache)
     return best, trials
+
+
+def time_batched(ctx, design, n_inst, threads, cycles, seed=0x5EED0000, reps=2):
+    """Seconds per simulated cycle of the batched form (all n_inst instances)."""
+    import torch
+    s = F.Sim(design, n_inst, launch=F.LAUNCH_GRAPH, wg_threads=threads, seed=seed)
+    s.step(min(64, cycles))
+    s.sync()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.torch_stream)
+        s.step(cycles)
+        e1.record(ctx.torch_stream)
+        e1.synchronize()
+        s.sync()
+        best = min(best, e0.elapsed_time(e1) / 1e3 / cycles)
+    del s
+    return best
+
+
+def tune_batched(ctx, nl, n_inst, targets=(256, 512, 1024, 2048), threads=(64, 128, 256),
+                 cycles=256, use_cache=True, verbose=False, designs=None):
+    """Batched-form autotuner: packing target and tiles of 64 instances per
+    workgroup.  Returns (best, trials); best has s_per_cycle for all instances."""
+    key = f"batched/{design_hash(nl)}/{n_inst}/{_device_name()}"
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return cache[key], []
+    trials, best = [], None
+    for t in targets:
+        try:
+            d = designs[t] if designs and t in designs else F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=t)
+        except F.FsimError as e:
+            if verbose:
+                print(f"tune: target {t}: {e}", flush=True)
+            continue
+        for th in threads:
+            if th > 64 * ((n_inst + 63) // 64):
+                continue
+            try:
+                spc = time_batched(ctx, d, n_inst, th, cycles)
+            except F.FsimError as e:
+                if verbose:
+                    print(f"tune: target {t} threads {th}: {e}", flush=True)
+                continue
+            rec = dict(target=t, processes=d.info()["n_processes"], threads=th, s_per_cycle=spc,
+                       inst_cycles_per_s=n_inst / spc)
+            trials.append(rec)
+            if verbose:
+                print(f"tune: {rec}", flush=True)
+            if best is None or spc < best["s_per_cycle"]:
+                best = rec
+        del d
+    if best is None:
+        raise RuntimeError("autotuner found no runnable configuration")
+    if use_cache:
+        cache = _load_cache()
+        cache[key] = best
+        _save_cache(cache)
+    return best, trials
