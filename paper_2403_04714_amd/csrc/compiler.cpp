@@ -912,6 +912,65 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
     }
     for (uint32_t i = 0; i < n_ord; ++i) { emitted[order[i]] = UINT32_MAX; slot_of[order[i]] = UINT32_MAX; kidx[order[i]] = UINT32_MAX; last_use[order[i]] = 0; }
   }
+  // ---- final form: handler kinds and LDS byte offsets
+  uint32_t max_k = 0;
+  for (const BatchProc& bp : d.batch_procs) max_k = std::max(max_k, bp.n_consts);
+  const uint32_t kbase = 16 + 8 * d.batch_slots[0];
+  const uint32_t wbase = (kbase + 8 * max_k + 15) & ~15u;
+  const uint32_t dbase = wbase + 256 * d.batch_slots[1];
+  const uint32_t end = dbase + 512 * d.batch_slots[2] + 16;     // + slack for 8-byte reads of u32 rows
+  if (end > 0xFFFF)
+    return Status::err(FSIM_E_CAPACITY, fmt("batched form: %llu bytes of live values per wave exceed the "
+                                            "16-bit offsets; use more processes", end));
+  d.batch_kbase = kbase;
+  d.batch_wave_bytes = end;
+  for (uint32_t p = 0; p < d.P; ++p) {
+    const BatchProc& bp = d.batch_procs[p];
+    for (uint32_t i = bp.instr_off; i < bp.instr_off + bp.n_instr; ++i) {
+      Instr& in = d.batch_instr[i];
+      const uint8_t cd = in.cls & 3, ca = (in.cls >> 2) & 3, cb = (in.cls >> 4) & 3, cc = (in.cls >> 6) & 3;
+      auto off = [&](uint8_t cls, uint16_t idx) -> uint16_t {
+        switch (cls) {
+          case C_B: return (uint16_t)(16 + 8 * idx);
+          case C_W: return (uint16_t)(wbase + 256 * idx);
+          case C_D: return (uint16_t)(dbase + 512 * idx);
+          default:  return (uint16_t)(kbase + 8 * idx);
+        }
+      };
+      // a constant operand of a 1-bit operator becomes the all-zeros or
+      // all-ones mask
+      auto moff = [&](uint8_t cls, uint16_t idx) -> uint16_t {
+        if (cls == C_K) return (d.batch_consts[bp.const_off + idx] & 1) ? 8 : 0;
+        return off(cls, idx);
+      };
+      const uint8_t op = in.op;
+      if (op == I_LDREG || op == I_LDIN) { in.dst = off(cd, in.dst); }
+      else if (op == I_MEMRD) { in.dst = off(cd, in.dst); in.a = off(ca, in.a); }
+      else if (op == I_STREG || op == I_STOUT) { in.a = off(ca, in.a); }
+      else if (op == I_WPORT) { in.a = off(ca, in.a); in.b = off(cb, in.b); in.c = off(cc, in.c); }
+      else {
+        const bool bk_a = ca == C_B || ca == C_K, bk_b = cb == C_B || cb == C_K, bk_c = cc == C_B || cc == C_K;
+        const bool mask_ok = cd == C_B &&
+            (((op == I_AND || op == I_OR || op == I_XOR || op == I_ADD || op == I_SUB) && bk_a && bk_b) ||
+             (op == I_NOT && bk_a) ||
+             ((op == I_EQ || op == I_LT) && ca == C_B && cb == C_B) ||
+             (op == I_MUX && ca == C_B && bk_b && bk_c));
+        if (mask_ok) {
+          in.op = op == I_AND ? K_MASK_AND : op == I_OR ? K_MASK_OR
+                : (op == I_XOR || op == I_ADD || op == I_SUB) ? K_MASK_XOR
+                : op == I_NOT ? K_MASK_NOT : op == I_EQ ? K_MASK_EQ : op == I_LT ? K_MASK_LT : K_MASK_MUX;
+          in.a = moff(ca, in.a); in.b = moff(cb, in.b); in.c = moff(cc, in.c);
+          in.dst = off(C_B, in.dst);
+        } else {
+          in.a = off(ca, in.a); in.b = off(cb, in.b); in.c = off(cc, in.c);
+          in.dst = off(cd, in.dst);
+        }
+      }
+    }
+  }
+  // one trailing instruction: the kernel fetches instruction i + 1 while it
+  // executes instruction i
+  d.batch_instr.push_back(Instr{});
   d.batch_encoded = true;
   return {};
 }

@@ -67,7 +67,21 @@ inline uint32_t make_chunk(uint32_t start, uint32_t count, uint32_t op) {
 }
 
 // Batched form: per process, one sequential stream evaluated by a wave for
-// 64 instances at a time; slots are per class.
+// 64 instances at a time; slots are per class.  After encoding, the opcode
+// byte names the handler and every operand is an LDS byte offset within the
+// wave's region:
+//   [0, 16)           two 1-bit masks: all zeros, all ones
+//   [16, kbase)       1-bit value slots (one u64 mask each)
+//   [kbase, wbase)    the process's constants (u64 each, staged per wave)
+//   [wbase, dbase)    <=32-bit value slots (64 x u32 each)
+//   [dbase, end)      <=64-bit value slots (64 x u64 each)
+// Operators on per-lane values keep their opcode (I_AND .. I_MUL, with the
+// operand classes in cls); operators whose operands and result are all 1-bit
+// become whole-mask handlers.
+enum : uint8_t {
+  K_MASK_AND = 24, K_MASK_OR = 25, K_MASK_XOR = 26, K_MASK_NOT = 27,
+  K_MASK_EQ = 28, K_MASK_LT = 29, K_MASK_MUX = 30
+};
 struct BatchProc {
   uint32_t instr_off;
   uint32_t n_instr;

@@ -338,57 +338,59 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
   return (cptr<T>)(p);
 }
 
-struct WaveSlots {
-  uint64_t* B;   // [slotsB]
-  uint32_t* W;   // [slotsW][64]
-  uint64_t* D;   // [slotsD][64]
-};
+// One operand of a per-lane operator, zero-extended to 64 bits.  `off` is a
+// byte offset into the wave's LDS region; the class picks the lane stride
+// (1-bit masks and constants: every lane reads the same word; u32 and u64
+// rows: one element per lane) and the extraction.  Rows of u32 are read as
+// two u32 words so that only 4-byte alignment is assumed.
+__device__ __forceinline__ uint64_t lread(const char* base, uint32_t cls, uint32_t off, uint32_t lane) {
+  const uint32_t stride = (0x0840u >> (cls * 4)) & 0xF;      // B 0, W 4, D 8, K 0
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(base + off + lane * stride);
+  const uint64_t v = (uint64_t)p[0] | ((uint64_t)p[1] << 32);
+  const uint32_t sh = cls == C_B ? lane : 0;
+  const uint64_t m = cls == C_B ? 1ull : cls == C_W ? 0xFFFFFFFFull : ~0ull;
+  return (v >> sh) & m;
+}
 
-__device__ __forceinline__ uint64_t bread(const WaveSlots& S, cptr<uint64_t> K, uint32_t cls, uint32_t s,
-                                          uint32_t lane) {
-  switch (cls) {
-    case C_B: return (S.B[s] >> lane) & 1;
-    case C_W: return S.W[s * 64 + lane];
-    case C_D: return S.D[s * 64 + lane];
-    default:  return K[s];
+// Store a per-lane value into a slot of class cls (never a constant).
+__device__ __forceinline__ void lwrite(char* base, uint32_t cls, uint32_t off, uint32_t lane, uint64_t v) {
+  if (cls == C_B) {
+    const uint64_t m = __ballot(v & 1);
+    if (lane == 0) *reinterpret_cast<uint64_t*>(base + off) = m;
+  } else if (cls == C_W) {
+    reinterpret_cast<uint32_t*>(base + off)[lane] = (uint32_t)v;
+  } else {
+    reinterpret_cast<uint64_t*>(base + off)[lane] = v;
   }
 }
 
-__device__ __forceinline__ void bwrite(const WaveSlots& S, uint32_t cls, uint32_t s, uint32_t lane, uint64_t v) {
-  switch (cls) {
-    case C_B: {
-      const uint64_t m = __ballot(v & 1);
-      if (lane == 0) S.B[s] = m;
-      break;
-    }
-    case C_W: S.W[s * 64 + lane] = (uint32_t)v; break;
-    default:  S.D[s * 64 + lane] = v; break;
-  }
+// one 16-byte instruction as four words (scalar loads)
+struct IWord { uint32_t x, y, z, w; };
+__device__ __forceinline__ IWord fetch(cptr<uint32_t> p, uint32_t i) {
+  return IWord{p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]};
 }
 
-// the 64-lane mask of a 1-bit operand: B slots as stored, constants by bit 0
-__device__ __forceinline__ uint64_t bmask(const WaveSlots& S, cptr<uint64_t> K, uint32_t cls, uint32_t s) {
-  return cls == C_B ? S.B[s] : ((K[s] & 1) ? ~0ull : 0ull);
+__device__ __forceinline__ uint64_t mread(const char* base, uint32_t off) {
+  return *reinterpret_cast<const uint64_t*>(base + off);
 }
 
 // One simulated cycle of one (process, tile group) work item of a batched sim.
-__device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block, uint64_t cyc, uint64_t* lds) {
+__device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block, uint64_t cyc, char* lds) {
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t p = block % A.P, grp = block / A.P;
   const uint32_t tile = grp * A.tpw + wave;
   if (tile >= A.n_tiles) return;                 // no barriers below: a wave may leave early
   const uint32_t inst = tile * 64 + lane;        // < n_pad
   const bool real = inst < A.n_inst;
-  const size_t wave_words = A.slotsB + (A.slotsW * 64 + 1) / 2 + A.slotsD * 64;
-  WaveSlots S;
-  S.B = lds + wave * wave_words;
-  S.W = reinterpret_cast<uint32_t*>(S.B + A.slotsB);
-  S.D = S.B + A.slotsB + (A.slotsW * 64 + 1) / 2;
+  char* base = lds + (size_t)wave * A.wave_bytes;
   const BatchProc bp = A.procs[p];
-  const cptr<uint32_t> prog = as_const(reinterpret_cast<const uint32_t*>(A.instr + bp.instr_off));
-  const cptr<uint64_t> K = as_const(A.consts + bp.const_off);
+  const cptr<uint32_t> prog32 = as_const(reinterpret_cast<const uint32_t*>(A.instr + bp.instr_off));
   const cptr<uint64_t> mem_off = as_const(A.mem_off);
   const cptr<uint32_t> mem_depth = as_const(A.mem_depth);
+  // the wave's region: the two constant masks, then the process's constants
+  if (lane < 2) reinterpret_cast<uint64_t*>(base)[lane] = lane ? ~0ull : 0ull;
+  for (uint32_t k = lane; k < bp.n_consts; k += 64)
+    reinterpret_cast<uint64_t*>(base + A.kbase)[k] = A.consts[bp.const_off + k];
   const uint32_t cur = cyc & 1, nxt = cur ^ 1;
   const cptr<uint64_t> stB_cur = as_const(A.stB + (size_t)cur * A.nB * A.n_tiles);
   uint64_t* stB_nxt = A.stB + (size_t)nxt * A.nB * A.n_tiles;
@@ -397,12 +399,41 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
   const uint64_t* stD_cur = A.stD + (size_t)cur * A.nD * A.n_pad;
   uint64_t* stD_nxt = A.stD + (size_t)nxt * A.nD * A.n_pad;
   uint64_t dacc = 0;
-  for (uint32_t i = 0; i < bp.n_instr; ++i) {
-    // wave-uniform instruction (scalar registers)
-    const uint32_t x = prog[4 * i], y = prog[4 * i + 1], z = prog[4 * i + 2], aux = prog[4 * i + 3];
+  IWord q = fetch(prog32, 0);
+  for (uint32_t i = 0; i < bp.n_instr;) {
+    // the next instruction is fetched before this one executes (the program
+    // ends with a pad instruction, so i + 1 is always readable)
+    const IWord qn = fetch(prog32, i + 1);
+    const uint32_t x = q.x, y = q.y, z = q.z, aux = q.w;
     const uint32_t op = x & 0xFF, w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
     const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
-    const uint32_t dst = y & 0xFFFF, sa = y >> 16, sb = z & 0xFFFF, sc = z >> 16;
+    const uint32_t dst = y & 0xFFFF, oa = y >> 16, ob = z & 0xFFFF, oc = z >> 16;
+    if (op >= I_AND && op <= I_MUL) {
+      const uint64_t a = lread(base, ca, oa, lane), b = lread(base, cb, ob, lane);
+      const uint64_t c = op == I_MUX ? lread(base, cc, oc, lane) : 0;
+      lwrite(base, cd, dst, lane, alu(op, w, a, b, c));
+      ++i;
+      q = qn;
+      continue;
+    }
+    if (op >= K_MASK_AND) {
+      // every operand and the result are 64-instance masks
+      const uint64_t ma = mread(base, oa), mb = mread(base, ob);
+      uint64_t r;
+      switch (op) {
+        case K_MASK_AND: r = ma & mb; break;
+        case K_MASK_OR:  r = ma | mb; break;
+        case K_MASK_XOR: r = ma ^ mb; break;        // also 1-bit ADD and SUB (sums mod 2)
+        case K_MASK_NOT: r = ~ma; break;
+        case K_MASK_EQ:  r = ~(ma ^ mb); break;
+        case K_MASK_LT:  r = ~ma & mb; break;
+        default:         r = (ma & mb) | (~ma & mread(base, oc)); break;   // MUX
+      }
+      if (lane == 0) *reinterpret_cast<uint64_t*>(base + dst) = r;
+      ++i;
+      q = qn;
+      continue;
+    }
     switch (op) {
       case I_LDREG:
       case I_LDIN: {
@@ -413,7 +444,7 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
 #pragma unroll
         for (uint32_t k = 0; k < 16; ++k) {
           if (k < n) {
-            const uint32_t xk = prog[4 * (i + k)], auxk = prog[4 * (i + k) + 3];
+            const uint32_t xk = prog32[4 * (i + k)], auxk = prog32[4 * (i + k) + 3];
             const uint32_t cak = (xk >> 18) & 3;
             if ((xk & 0xFF) == I_LDREG) {
               val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
@@ -430,39 +461,40 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
 #pragma unroll
         for (uint32_t k = 0; k < 16; ++k) {
           if (k < n) {
-            const uint32_t xk = prog[4 * (i + k)], yk = prog[4 * (i + k) + 1];
+            const uint32_t xk = prog32[4 * (i + k)], yk = prog32[4 * (i + k) + 1];
             const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
             const uint32_t dk = yk & 0xFFFF;
             if ((xk & 0xFF) == I_LDREG) {
               if (cak == C_B) {
-                if (cdk == C_B) { if (lane == 0) S.B[dk] = val[k]; }
-                else bwrite(S, cdk, dk, lane, (val[k] >> lane) & 1);
+                if (cdk == C_B) { if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = val[k]; }
+                else lwrite(base, cdk, dk, lane, (val[k] >> lane) & 1);
               } else {
-                bwrite(S, cdk, dk, lane, val[k] & wmask(wk));
+                lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
               }
             } else {
               if (A.in_vals) {
                 if (cyc < A.in_first || cyc >= A.in_first + A.in_count) atomicOr(&A.error[1], 1u);
-                bwrite(S, cdk, dk, lane, val[k] & wmask(wk));
+                lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
               } else {
-                bwrite(S, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
+                lwrite(base, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
               }
             }
           }
         }
-        i += n - 1;
-        break;
+        i += n;
+        q = fetch(prog32, i);
+        continue;
       }
       case I_MEMRD: {
-        const uint64_t a = bread(S, K, ca, sa, lane);
+        const uint64_t a = lread(base, ca, oa, lane);
         const uint64_t depth = mem_depth[aux];
         const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-        bwrite(S, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
+        lwrite(base, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
         break;
       }
       case I_STREG: {
         // cd: class of the register's state array, ca: class of the value
-        const uint64_t v = bread(S, K, ca, sa, lane) & wmask(w);
+        const uint64_t v = lread(base, ca, oa, lane) & wmask(w);
         if (cd == C_B) {
           const uint64_t m = __ballot(v & 1);
           if (lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile] = m;
@@ -471,15 +503,15 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
         } else {
           stD_nxt[(size_t)aux * A.n_pad + inst] = v;
         }
-        if (A.digest) dacc += hmix((uint64_t)(sb | (sc << 16)) ^ hmix(v));
+        if (A.digest) dacc += hmix((uint64_t)(ob | (oc << 16)) ^ hmix(v));
         break;
       }
       case I_STOUT:
-        A.outputs[(size_t)aux * A.n_pad + inst] = bread(S, K, ca, sa, lane) & wmask(w);
+        A.outputs[(size_t)aux * A.n_pad + inst] = lread(base, ca, oa, lane) & wmask(w);
         break;
       case I_WPORT: {
-        const uint64_t en = bread(S, K, ca, sa, lane), a = bread(S, K, cb, sb, lane);
-        const uint64_t v = bread(S, K, cc, sc, lane);
+        const uint64_t en = lread(base, ca, oa, lane), a = lread(base, cb, ob, lane);
+        const uint64_t v = lread(base, cc, oc, lane);
         if (en) {
           const uint64_t depth = mem_depth[aux];
           const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
@@ -487,35 +519,11 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
         }
         break;
       }
-      default: {
-        // 1-bit logic on whole masks when every operand and the result are 1-bit
-        const bool mask_ok = cd == C_B &&
-            ((op == I_AND || op == I_OR || op == I_XOR || op == I_ADD || op == I_SUB) &&
-                 (ca == C_B || ca == C_K) && (cb == C_B || cb == C_K) ||
-             op == I_NOT && (ca == C_B || ca == C_K) ||
-             (op == I_EQ || op == I_LT) && ca == C_B && cb == C_B ||
-             op == I_MUX && ca == C_B && (cb == C_B || cb == C_K) && (cc == C_B || cc == C_K));
-        if (mask_ok) {
-          const uint64_t ma = bmask(S, K, ca, sa), mb = bmask(S, K, cb, sb), mc = bmask(S, K, cc, sc);
-          uint64_t r;
-          switch (op) {
-            case I_AND: r = ma & mb; break;
-            case I_OR:  r = ma | mb; break;
-            case I_XOR: case I_ADD: case I_SUB: r = ma ^ mb; break;   // mod 2 sums
-            case I_NOT: r = ~ma; break;
-            case I_EQ:  r = ~(ma ^ mb); break;
-            case I_LT:  r = ~ma & mb; break;
-            default:    r = (ma & mb) | (~ma & mc); break;             // MUX
-          }
-          if (lane == 0) S.B[dst] = r;
-        } else {
-          const uint64_t a = bread(S, K, ca, sa, lane), b = bread(S, K, cb, sb, lane);
-          const uint64_t c = bread(S, K, cc, sc, lane);
-          bwrite(S, cd, dst, lane, alu(op, w, a, b, c));
-        }
+      default:
         break;
-      }
     }
+    ++i;
+    q = qn;
   }
   if (A.digest && real) {
     const uint64_t k = cyc - A.digest_first;
@@ -526,7 +534,7 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
 __global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
   extern __shared__ uint64_t lds[];
   const uint64_t cyc = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
-  batched_body(A, blockIdx.x, cyc, lds);
+  batched_body(A, blockIdx.x, cyc, reinterpret_cast<char*>(lds));
 }
 
 // Serving: one launch advances every resident job by one cycle.  Job j owns
@@ -548,7 +556,7 @@ __global__ void __launch_bounds__(64) batched_multi(const BatchArgs* __restrict_
   const uint32_t j = lo;
   if (tick >= ticks[j]) return;
   const BatchArgs A = jobs[j];
-  batched_body(A, blockIdx.x - wg_start[j], cycle_base[j] + tick, lds);
+  batched_body(A, blockIdx.x - wg_start[j], cycle_base[j] + tick, reinterpret_cast<char*>(lds));
 }
 
 }  // namespace fsim

@@ -303,7 +303,7 @@ extern "C" int fsim_design_batched_info(fsim_design* d, uint32_t* slots_b, uint3
 }
 
 size_t fsim::batched_wave_bytes(const Design& D) {
-  return ((size_t)D.batch_slots[0] + ((size_t)D.batch_slots[1] * 64 + 1) / 2 + (size_t)D.batch_slots[2] * 64) * 8;
+  return D.batch_wave_bytes;
 }
 
 static int sim_create_batched(fsim_sim* s, void* workspace, size_t ws_bytes, const fsim_sim_opts& o) {
@@ -505,7 +505,8 @@ fsim::BatchArgs fsim::batch_args(fsim_sim* s) {
   a.cycle_ptr = nullptr;
   a.P = D.P; a.n_tiles = s->n_tiles; a.tpw = s->tpw; a.n_inst = s->n_inst; a.n_pad = s->n_pad; a.I = D.I;
   a.nB = D.reg_count[0]; a.nW = D.reg_count[1]; a.nD = D.reg_count[2];
-  a.slotsB = D.batch_slots[0]; a.slotsW = D.batch_slots[1]; a.slotsD = D.batch_slots[2];
+  a.wave_bytes = D.batch_wave_bytes;
+  a.kbase = D.batch_kbase;
   return a;
 }
 
