@@ -9,7 +9,10 @@ on-device stimulus.  Compilation (fiber extraction, packing, encoding) and
 autotuning happen once, before the timed region.
 
 Prints ONE JSON line.  Also reports the roofline of the dominant kernel and
-the oracle's CPU rate on a bounded sample.
+the oracle's CPU rate on a bounded sample, and, measured in the same run at
+bounded cycle counts: the batched form (many independent stimulus instances
+per launch) on the single-core and 8-tile SoC workloads, the plain form on
+the 8-tile SoC, and a served Poisson stream of jobs with p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -52,6 +55,97 @@ def cpu_baseline(nl, seed, budget_s=12.0):
                        f"single-threaded C oracle ({dt:.1f} s)")
 
 
+def time_sim(sim, stream, cycles, warm):
+    """Seconds of GPU time for `cycles` cycles after `warm` untimed ones
+    (HIP events on the library's stream)."""
+    import torch
+    if warm:
+        sim.step(warm)
+    sim.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(cycles)
+    e1.record(stream)
+    e1.synchronize()
+    sim.sync()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def bench_batched(F, g, tune, ctx, name, n_inst, target, threads, cycles, warm, seed):
+    """Batched form: n_inst instances in one launch per cycle (hipGraph),
+    packing target fixed, threads per workgroup autotuned."""
+    nl = g.workload(name)
+    t0 = time.time()
+    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=target)
+    compile_s = time.time() - t0
+    best, _ = tune.tune_batched(ctx, nl, n_inst, targets=(target,), threads=threads, cycles=32,
+                                use_cache=False, designs={target: d})
+    sim = F.Sim(d, n_inst, launch=F.LAUNCH_GRAPH, wg_threads=best["threads"], seed=seed)
+    gpu_s = time_sim(sim, ctx.torch_stream, cycles, warm)
+    info = d.info()
+    bpc, _ = algorithmic_bytes_per_cycle(nl, info["n_live_ops"], n_inst)
+    achieved = bpc / (gpu_s / cycles) / 1e9
+    lay = sim.layout()
+    bi = d.batched_info()
+    out = {"workload": f"{nl.name} x{n_inst}", "instances": n_inst, "cycles": cycles,
+           "value": round(n_inst * cycles / gpu_s, 1), "unit": "instance-cycles/s",
+           "us_per_cycle": round(gpu_s / cycles * 1e6, 2),
+           "roofline": {"bound": "alu", "kernel": "batched_cycle", "hbm_achieved_GBs": round(achieved, 2),
+                        "hbm_frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_cycle": bpc},
+           "processes": int(info["n_processes"]), "dup_process": round(info["dup_process"], 4),
+           "workgroups": lay["workgroups"], "threads": lay["threads"],
+           "wave_lds_bytes": int(bi["wave_lds_bytes"]), "instructions": int(bi["n_instr"]),
+           "compile_s": round(compile_s, 2)}
+    del sim, d
+    return out
+
+
+def bench_plain_tuned(F, g, tune, ctx, name, targets, threads, cycles, warm, seed):
+    """Plain form, one instance, packing target and threads autotuned (graph
+    launches: beyond a hundred or so workgroups the per-cycle launch is the
+    cheaper barrier)."""
+    nl = g.workload(name)
+    t0 = time.time()
+    best, _ = tune.tune_plain(ctx, nl, targets=targets, threads=threads, launches=(F.LAUNCH_GRAPH,),
+                              cycles=500, use_cache=False)
+    tune_s = time.time() - t0
+    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=best["target"])
+    sim = F.Sim(d, 1, launch=best["launch"], wg_threads=best["threads"], seed=seed)
+    gpu_s = time_sim(sim, ctx.torch_stream, cycles, warm)
+    info = d.info()
+    lay = sim.layout()
+    out = {"workload": f"{nl.name} x1", "instances": 1, "cycles": cycles,
+           "value": round(cycles / gpu_s, 1), "unit": "instance-cycles/s",
+           "us_per_cycle": round(gpu_s / cycles * 1e6, 2), "processes": int(info["n_processes"]),
+           "workgroups": lay["workgroups"], "threads": lay["threads"],
+           "process_levels": int(info["max_process_levels"]) + 2,
+           "dup_process": round(info["dup_process"], 4), "compile_s": round(info["compile_seconds"], 2),
+           "autotune_s": round(tune_s, 1)}
+    del sim, d
+    return out
+
+
+def bench_served(F, g, ctx, n_jobs, lam, inst_hi, cyc_lo, cyc_hi):
+    """Served Poisson stream over the single-core and 8-tile SoC designs."""
+    from paper_2403_04714_amd import serve
+    designs = [F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=1024),
+               F.Design(ctx, g.workload("soc8"), pack=F.PACK_SLB, target_processes=4096)]
+    jobs = serve.draw_jobs(n_jobs, designs, inst_lo=1, inst_hi=inst_hi, cyc_lo=cyc_lo, cyc_hi=cyc_hi)
+    arr = serve.arrivals(n_jobs, lam=lam)
+    srv = F.Server(ctx, 64 << 30, quantum_cycles=256)
+    recs, summ = serve.run(srv, designs, jobs, arr, timeout_s=600)
+    st = srv.stats()
+    srv.close()
+    return {"designs": ["core (1024 processes)", "soc8 (4096 processes)"], "jobs": n_jobs,
+            "arrival_rate_per_s": lam, "instances": f"log-uniform [1, {inst_hi}]",
+            "cycles": f"log-uniform [{cyc_lo}, {cyc_hi}]",
+            "completed": summ["completed"], "p50_s": round(summ["p50_s"], 4), "p99_s": round(summ["p99_s"], 4),
+            "mean_s": round(summ["mean_s"], 4), "wall_s": round(summ["wall_s"], 3),
+            "value": round(summ["instance_cycles_per_s"], 1), "unit": "instance-cycles/s",
+            "total_work_instance_cycles": int(summ["total_work_instance_cycles"]),
+            "quanta": int(st["quanta"]), "device_busy_s": round(st["busy_seconds"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +154,8 @@ def main():
     ap.add_argument("--cycles", type=int, default=100_000, help="cycles per step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline only: skip the batched, 8-tile plain and served sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
@@ -159,6 +255,17 @@ def main():
                    "instructions_in_lds": lay["staged"]},
         "wall_s_timed": round(wall, 3),
     }
+    if not args.no_extra:
+        del sim
+        extra_t0 = time.time()
+        out["batched"] = [
+            bench_batched(F, g, tune, ctx, "core", 1024, 1024, (64, 128), 512, 64, seed),
+            bench_batched(F, g, tune, ctx, "soc8", 256, 4096, (64, 128), 256, 32, seed),
+        ]
+        out["plain_soc8"] = bench_plain_tuned(F, g, tune, ctx, "soc8", (256, 512, 1024), (256, 1024),
+                                              5000, 500, seed)
+        out["served"] = bench_served(F, g, ctx, n_jobs=24, lam=4.0, inst_hi=1024, cyc_lo=100, cyc_hi=2000)
+        out["extra_sections_s"] = round(time.time() - extra_t0, 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(nl, seed)
     print(json.dumps(out), flush=True)
