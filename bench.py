@@ -146,6 +146,39 @@ def bench_served(F, g, ctx, n_jobs, lam, inst_hi, cyc_lo, cyc_hi):
             "quanta": int(st["quanta"]), "device_busy_s": round(st["busy_seconds"], 3)}
 
 
+def study_prng(F, g, ctx, cycles=2000, warm=200):
+    """The synchronization experiment of Sec. 4.1 on this GPU: independent
+    xorshift32 fibers (no communication), a fixed number of fibers per
+    workgroup (7, 56, 448), workgroups swept from 64 upwards; each series'
+    rate is normalised to its rate at 64 workgroups.  Both barriers are
+    measured: the persistent kernel's grid barrier and per-cycle launches in
+    a hipGraph."""
+    import numpy as np
+    rows = []
+    for k in (7, 56, 448):
+        for G in (64, 128, 256, 512, 1024, 2048):
+            n = k * G
+            nl = g.prng_array(n)
+            d = F.Design(ctx, nl, partition=np.arange(n, dtype=np.uint32) // k)
+            for launch in (F.LAUNCH_PERSISTENT, F.LAUNCH_GRAPH):
+                try:
+                    sim = F.Sim(d, 1, launch=launch, wg_threads=64)
+                except F.FsimError:
+                    continue                       # not co-resident: no grid barrier possible
+                gpu_s = time_sim(sim, ctx.torch_stream, cycles, warm)
+                rows.append({"fibers_per_wg": k, "workgroups": G,
+                             "launch": "persistent" if launch == F.LAUNCH_PERSISTENT else "graph",
+                             "rate_hz": round(cycles / gpu_s, 1), "us_per_cycle": round(gpu_s / cycles * 1e6, 3)})
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+                del sim
+            del d
+    for r in rows:
+        base = [x for x in rows if x["fibers_per_wg"] == r["fibers_per_wg"] and x["launch"] == r["launch"]
+                and x["workgroups"] == 64]
+        r["normalised"] = round(r["rate_hz"] / base[0]["rate_hz"], 4) if base else None
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +187,8 @@ def main():
     ap.add_argument("--cycles", type=int, default=100_000, help="cycles per step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--study", choices=["prng"], default=None,
+                    help="run a study instead of the benchmark (prng: the barrier sweep of Sec. 4.1)")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the batched, 8-tile plain and served sections")
     args = ap.parse_args()
@@ -170,6 +205,11 @@ def main():
         B.build()
     from paper_2403_04714_amd import netgen as g
     from paper_2403_04714_amd import tune
+
+    if args.study == "prng":
+        ctx = F.Context(0)
+        print(json.dumps({"study": "prng barrier sweep (Sec. 4.1)", "rows": study_prng(F, g, ctx)}), flush=True)
+        return
 
     seed = g.STIM_SEED_BASE
     t0 = time.time()

@@ -603,16 +603,28 @@ Status encode_plain(Design& d, uint32_t max_slots) {
     pp.instr_off = (uint32_t)d.plain_instr.size();
     pp.chunk_off = (uint32_t)d.plain_chunks.size();
     pp.lvl_off = (uint32_t)d.plain_levels.size();
-    // emits one level from a list of instructions sorted by opcode
+    // emits one level from a list of instructions sorted by opcode:
+    // operators of any opcode share I_ALU chunks, other opcodes get chunks of
+    // their own
     auto emit_level = [&](const std::vector<Instr>& ins) {
       d.plain_levels.push_back((uint32_t)d.plain_chunks.size() - pp.chunk_off);
+      auto kind = [](uint8_t op) -> uint32_t { return (op >= I_AND && op <= I_MUL) ? (uint32_t)I_ALU : op; };
       size_t k = 0;
       while (k < ins.size()) {
+        const uint32_t kk = kind(ins[k].op), cap = chunk_capacity(kk);
         size_t e = k;
-        while (e < ins.size() && e - k < 64 && ins[e].op == ins[k].op) ++e;
+        while (e < ins.size() && e - k < cap && kind(ins[e].op) == kk) ++e;
         uint32_t start = (uint32_t)d.plain_instr.size() - pp.instr_off;
-        for (size_t j = k; j < e; ++j) d.plain_instr.push_back(ins[j]);
-        d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), ins[k].op));
+        // an operator chunk carries the set of its opcodes in every
+        // instruction's aux field, so the kernel evaluates only those
+        uint32_t present = 0;
+        if (kk == I_ALU)
+          for (size_t j = k; j < e; ++j) present |= 1u << ins[j].op;
+        for (size_t j = k; j < e; ++j) {
+          d.plain_instr.push_back(ins[j]);
+          if (kk == I_ALU) d.plain_instr.back().aux = present;
+        }
+        d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), kk));
         k = e;
       }
     };

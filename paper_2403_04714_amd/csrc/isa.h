@@ -20,7 +20,8 @@ enum : uint8_t {
   I_STREG = 19,    // next value of register aux <- a (masked to w)
   I_STOUT = 20,    // output aux <- a
   I_WPORT = 21,    // if a != 0: mem[aux][b mod depth] <- c (port order)
-  I_NUM = 22
+  I_NUM = 22,
+  I_ALU = 23       // plain-form chunk of operators of mixed opcodes (AND .. MUL)
 };
 
 // Slot classes of the batched form: 1-bit values are 64-lane ballot masks,
@@ -40,13 +41,16 @@ struct Instr {
 static_assert(sizeof(Instr) == 16, "Instr must be 16 bytes");
 
 // Plain form: per process, a constant prologue (run once per launch), then
-// levels 0..n_lvls-1 (leaf loads, operator levels, the store level); the
-// instructions of a level are grouped by opcode and cut into chunks of at most
-// 64, so that a wavefront always runs one opcode (scalar dispatch, no
-// divergence).  A chunk is one u32: start (16 bits, relative to the first
-// level instruction) | (count - 1) << 16 (6 bits) | opcode << 22.  After the
-// levels comes the write-port commit, run in order by one thread after every
-// read of the cycle.
+// levels 0..n_lvls-1 (leaf loads, operator levels, the store level).  The
+// instructions of a level are cut into chunks: a chunk of operators (I_ALU)
+// holds up to 64 instructions of any opcodes, one per lane, whose operands
+// are all read before any lane computes; leaf-load and store chunks hold up
+// to 256 instructions of one opcode, four per lane, all issued before the
+// first is used; memory reads come in chunks of up to 64.  A chunk is one
+// u32: start (16 bits, relative to the first level instruction) |
+// (count - 1) << 16 (8 bits) | opcode << 24.  After the levels comes the
+// write-port commit, run in order by one thread after every read of the
+// cycle.
 struct PlainProc {
   uint32_t lvl_off;    // index into the level table: n_lvls + 1 chunk indices
   uint32_t n_lvls;
@@ -63,7 +67,10 @@ struct PlainProc {
 static_assert(sizeof(PlainProc) == 48, "PlainProc must be 48 bytes");
 
 inline uint32_t make_chunk(uint32_t start, uint32_t count, uint32_t op) {
-  return start | ((count - 1) << 16) | (op << 22);
+  return start | ((count - 1) << 16) | (op << 24);
+}
+inline uint32_t chunk_capacity(uint32_t op) {
+  return (op == I_LDREG || op == I_LDIN || op == I_STREG || op == I_STOUT) ? 256 : 64;
 }
 
 // Batched form: per process, one sequential stream evaluated by a wave for

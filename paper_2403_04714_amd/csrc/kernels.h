@@ -40,6 +40,7 @@ struct PlainArgs {
   uint32_t n_cycles;
   uint32_t epoch0;            // barrier epoch before this launch
   const uint64_t* cycle_ptr;  // graph mode: absolute base cycle in device memory
+  uint32_t single_wave;       // 64-thread workgroups, staged, <= 256 chunks: flat chunk loop
 };
 
 // Batched form: one wave per (process, tile of 64 instances).  State is kept
@@ -48,6 +49,7 @@ struct PlainArgs {
 // double-buffered by cycle parity.
 struct BatchArgs {
   const Instr* instr;
+  uint64_t n_instr_total;     // instructions in the whole program array
   const BatchProc* procs;
   const uint64_t* consts;
   uint64_t* stB;              // [2][nB][n_tiles]
@@ -78,7 +80,8 @@ hipError_t launch_batched_multi(const BatchArgs* jobs, const uint32_t* wg_start,
                                 size_t lds_bytes, hipStream_t s);
 hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t lds_bytes,
                         bool persistent, hipStream_t s);
-hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged);
+hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged,
+                           bool single_wave);
 hipError_t launch_digest_reduce(const uint64_t* part, uint32_t G, uint64_t n, uint64_t* out,
                                 hipStream_t s);
 hipError_t launch_stim_keys(uint64_t* keys, uint64_t seed_base, uint32_t n_inst, uint32_t I,

@@ -57,6 +57,34 @@ __device__ __forceinline__ uint64_t alu(uint32_t op, uint32_t w, uint64_t a, uin
   return r & wmask(w);
 }
 
+// One operator per lane, opcodes differing between lanes.  `present` (wave
+// uniform) holds the opcodes that occur in the chunk: each of them is
+// evaluated for every lane and kept where it is the lane's own, so the cost
+// is a few vector instructions per opcode present, without divergent
+// branches.
+__device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uint32_t w, uint64_t a,
+                                              uint64_t b, uint64_t c) {
+  uint64_t r = 0;
+  // the empty asm keeps each test a real (scalar) branch, so opcodes absent
+  // from the chunk cost two scalar instructions instead of being computed
+#define FSIM_MIXED(OPC, EXPR) \
+  if (present & (1u << (OPC))) { asm volatile(""); r = op == (OPC) ? (uint64_t)(EXPR) : r; }
+  FSIM_MIXED(I_AND, a & b)
+  FSIM_MIXED(I_OR, a | b)
+  FSIM_MIXED(I_XOR, a ^ b)
+  FSIM_MIXED(I_NOT, ~a)
+  FSIM_MIXED(I_ADD, a + b)
+  FSIM_MIXED(I_SUB, a - b)
+  FSIM_MIXED(I_MUX, a ? b : c)
+  FSIM_MIXED(I_SHL, b >= 64 ? 0 : (a << (b & 63)))
+  FSIM_MIXED(I_SHR, b >= 64 ? 0 : (a >> (b & 63)))
+  FSIM_MIXED(I_EQ, a == b)
+  FSIM_MIXED(I_LT, a < b)
+  FSIM_MIXED(I_MUL, a * b)
+#undef FSIM_MIXED
+  return r & wmask(w);
+}
+
 static constexpr long kSpinLimit = 1l << 22;
 
 // Grid-wide barrier over G workgroups (see the file comment).  Returns false
@@ -165,91 +193,97 @@ __device__ void plain_body(const PlainArgs& A) {
       trace_row = k < A.trace_max ? A.trace + (k * gridDim.x + blockIdx.x) * A.trace_stride : nullptr;
       if (trace_row) trace_row[0] = __builtin_amdgcn_s_memrealtime();
     }
-    // this wave's first chunk of level 0 and its instruction
+    // this wave's first chunk of level 0 and its instruction, and the first
+    // chunk word of level 1 (a level always exists after the leaf level)
     uint32_t c_lo = lvl(0), c_hi = lvl(1);
     uint32_t ch_first = c_lo + wave < c_hi ? chunks[c_lo + wave] : 0;
     ch_first = __builtin_amdgcn_readfirstlane(ch_first);
     uint4 raw_first = make_uint4(0, 0, 0, 0);
-    if (c_lo + wave < c_hi && lane <= ((ch_first >> 16) & 63)) raw_first = fetch((ch_first & 0xFFFF) + lane);
+    if (c_lo + wave < c_hi && lane <= ((ch_first >> 16) & 0xFF)) raw_first = fetch((ch_first & 0xFFFF) + lane);
+    uint32_t n_lo = c_hi, n_hi = n_lvls > 1 ? lvl(2) : c_hi;
+    uint32_t ch_next = __builtin_amdgcn_readfirstlane(n_lo + wave < n_hi ? chunks[n_lo + wave] : 0);
     for (uint32_t L = 0; L < n_lvls; ++L) {
-      // the next level's first chunk word for this wave, issued early
-      const uint32_t n_lo = c_hi, n_hi = L + 1 < n_lvls ? lvl(L + 2) : c_hi;
+      // Prefetch, issued with this level's operand reads so that the
+      // latencies overlap: the next level's first instruction for this wave
+      // and the first chunk word two levels ahead.  Instructions and chunk
+      // words never change during the launch.
       const bool have_next = n_lo + wave < n_hi;
-      uint32_t ch_next = have_next ? chunks[n_lo + wave] : 0;
+      uint4 raw_next = make_uint4(0, 0, 0, 0);
+      if (have_next && lane <= ((ch_next >> 16) & 0xFF)) raw_next = fetch((ch_next & 0xFFFF) + lane);
+      const uint32_t m_lo = n_hi, m_hi = L + 2 < n_lvls ? lvl(L + 3) : n_hi;
+      const uint32_t ch_after = m_lo + wave < m_hi ? chunks[m_lo + wave] : 0;
       bool first = true;
       for (uint32_t c = c_lo + wave; c < c_hi; c += nwaves) {
         uint32_t ch = first ? ch_first : __builtin_amdgcn_readfirstlane(chunks[c]);
-        const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 63) + 1, op = ch >> 22;
-        if (lane < cnt) {
-          const Dec in = decode(first ? raw_first : fetch(start + lane));
-          const uint32_t w = in.w;
-          switch (op) {          // op is wave-uniform: scalar branches only
-            case I_LDREG:
-              slot[in.dst] = cur[in.aux] & wmask(w);
-              break;
-            case I_LDIN: {
-              uint64_t v;
-              if (A.in_vals) {
-                if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v = 0; }
-                else v = A.in_vals[(cyc - A.in_first) * A.I + in.aux];
+        const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 0xFF) + 1, op = ch >> 24;
+        if (op == I_ALU) {
+          // operators of mixed opcodes: every operand is read before any lane
+          // computes, so the level costs one LDS round trip; the opcode
+          // switch then runs on registers only
+          if (lane < cnt) {
+            const Dec in = decode(first ? raw_first : fetch(start + lane));
+            uint64_t a = slot[in.a], b = slot[in.b], cc = slot[in.c];
+            asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
+            const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
+            slot[in.dst] = alu_mixed(present, in.op, in.w, a, b, cc);
+          }
+        } else if (op == I_LDREG || op == I_LDIN || op == I_STREG || op == I_STOUT) {
+          // up to four instructions per lane; all loads are issued before the
+          // first result is used
+          Dec in[4];
+          uint64_t v[4];
+#pragma unroll
+          for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t e = lane + 64 * q;
+            if (e < cnt) {
+              in[q] = decode(q == 0 && first ? raw_first : fetch(start + e));
+              if (op == I_LDREG) {
+                v[q] = cur[in[q].aux];
+              } else if (op == I_LDIN) {
+                if (A.in_vals) {
+                  if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v[q] = 0; }
+                  else v[q] = A.in_vals[(cyc - A.in_first) * A.I + in[q].aux];
+                } else {
+                  v[q] = hmix(A.in_keys[in[q].aux] ^ cyc);
+                }
               } else {
-                v = hmix(A.in_keys[in.aux] ^ cyc);
+                v[q] = slot[in[q].a];
               }
-              slot[in.dst] = v & wmask(w);   // LDIN widths fold in the port width
-              break;
             }
-            case I_MEMRD: {
-              const uint64_t a = slot[in.a];
-              const uint64_t depth = A.mem_depth[in.aux];
-              const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-              slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(w);
-              break;
+          }
+#pragma unroll
+          for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t e = lane + 64 * q;
+            if (e < cnt) {
+              const uint64_t x = v[q] & wmask(in[q].w);   // LDIN widths fold in the port width
+              if (op == I_LDREG || op == I_LDIN) {
+                slot[in[q].dst] = x;
+              } else if (op == I_STREG) {
+                nxt[in[q].aux] = x;
+                if (A.digest_part) dacc += hmix((uint64_t)in[q].aux ^ hmix(x));
+              } else {
+                A.outputs[in[q].aux] = x;
+              }
             }
-            case I_AND: slot[in.dst] = (slot[in.a] & slot[in.b]) & wmask(w); break;
-            case I_OR:  slot[in.dst] = (slot[in.a] | slot[in.b]) & wmask(w); break;
-            case I_XOR: slot[in.dst] = (slot[in.a] ^ slot[in.b]) & wmask(w); break;
-            case I_NOT: slot[in.dst] = ~slot[in.a] & wmask(w); break;
-            case I_ADD: slot[in.dst] = (slot[in.a] + slot[in.b]) & wmask(w); break;
-            case I_SUB: slot[in.dst] = (slot[in.a] - slot[in.b]) & wmask(w); break;
-            case I_MUX: {
-              const uint64_t s = slot[in.a], a = slot[in.b], b = slot[in.c];
-              slot[in.dst] = (s ? a : b) & wmask(w);
-              break;
-            }
-            case I_SHL: {
-              const uint64_t a = slot[in.a], b = slot[in.b];
-              slot[in.dst] = (b >= 64 ? 0 : (a << b)) & wmask(w);   // the hardware takes
-              break;                                                 // amounts mod 64
-            }
-            case I_SHR: {
-              const uint64_t a = slot[in.a], b = slot[in.b];
-              slot[in.dst] = (b >= 64 ? 0 : (a >> b)) & wmask(w);
-              break;
-            }
-            case I_EQ: slot[in.dst] = (slot[in.a] == slot[in.b]) ? 1 : 0; break;
-            case I_LT: slot[in.dst] = (slot[in.a] < slot[in.b]) ? 1 : 0; break;
-            case I_MUL: slot[in.dst] = (slot[in.a] * slot[in.b]) & wmask(w); break;
-            case I_STREG: {
-              const uint64_t v = slot[in.a] & wmask(w);
-              nxt[in.aux] = v;
-              if (A.digest_part) dacc += hmix((uint64_t)in.aux ^ hmix(v));
-              break;
-            }
-            case I_STOUT:
-              A.outputs[in.aux] = slot[in.a] & wmask(w);
-              break;
-            default:
-              break;
+          }
+        } else if (op == I_MEMRD) {
+          if (lane < cnt) {
+            const Dec in = decode(first ? raw_first : fetch(start + lane));
+            const uint64_t a = slot[in.a];
+            const uint64_t depth = A.mem_depth[in.aux];
+            const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
+            slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
           }
         }
         first = false;
       }
-      // the next level's first instruction for this wave, before the barrier
-      ch_next = __builtin_amdgcn_readfirstlane(ch_next);
-      if (have_next && lane <= ((ch_next >> 16) & 63)) raw_first = fetch((ch_next & 0xFFFF) + lane);
       ch_first = ch_next;
+      raw_first = raw_next;
+      ch_next = __builtin_amdgcn_readfirstlane(ch_after);
       c_lo = n_lo;
       c_hi = n_hi;
+      n_lo = m_lo;
+      n_hi = m_hi;
       if (one_wave) asm volatile("" ::: "memory");
       else __syncthreads();
       if (trace_row && L + 2 < A.trace_stride) trace_row[L + 1] = __builtin_amdgcn_s_memrealtime();
@@ -289,6 +323,173 @@ __device__ void plain_body(const PlainArgs& A) {
     if (trace_row) trace_row[A.trace_stride - 1] = __builtin_amdgcn_s_memrealtime();
   }
 }
+
+// Single-wave processes (64 threads): LDS operations of one wave complete in
+// order, so the levels need no barrier and the chunks of all levels run as
+// one flat sequence.  The chunk words sit in four registers (lane k of word q
+// holds chunk 64 q + k, read with v_readlane) and the first instruction of
+// the next chunk is fetched while the current chunk runs.
+template <bool PERSISTENT>
+__device__ void plain_wave_body(const PlainArgs& A) {
+  extern __shared__ uint64_t lds[];
+  __shared__ int abort_flag;
+  const uint32_t lane = threadIdx.x;
+  const PlainProc pp = A.procs[blockIdx.x];
+  uint64_t* slot = lds;
+  const uint32_t n_all = pp.n_instr + pp.n_wp;
+  const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
+  uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
+  for (uint32_t i = lane; i < n_all; i += 64) Is[i] = Ig[i];
+  for (uint32_t i = lane; i < pp.n_consts; i += 64) {
+    const Instr in = A.instr[pp.const_off + i];
+    slot[in.dst] = A.consts[in.aux];
+  }
+  const uint32_t n_ch = pp.n_chunks;
+  uint32_t cw[4];
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q)
+    cw[q] = lane + 64 * q < n_ch ? A.chunks[pp.chunk_off + lane + 64 * q] : 0;
+  // level starts, for the phase timestamps only
+  const uint32_t n_lvls = pp.n_lvls;
+  const uint32_t lv_lo = lane <= n_lvls ? A.levels[pp.lvl_off + lane] : 0;
+  if (lane == 0) abort_flag = 0;
+  __syncthreads();
+  auto chunk_word = [&](uint32_t c) -> uint32_t {
+    const uint32_t q = c >> 6;
+    const uint32_t v = q == 0 ? cw[0] : q == 1 ? cw[1] : q == 2 ? cw[2] : cw[3];
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(c & 63));
+  };
+  const uint64_t cyc0 = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
+  uint64_t* trace_row = nullptr;
+  for (uint32_t t = 0; t < A.n_cycles; ++t) {
+    const uint64_t cyc = cyc0 + t;
+    const uint64_t* cur = A.state + (cyc & 1) * A.R;
+    uint64_t* nxt = A.state + ((cyc + 1) & 1) * A.R;
+    uint64_t dacc = 0;
+    if (A.trace) {
+      const uint64_t k = cyc - A.trace_first;
+      trace_row = k < A.trace_max ? A.trace + (k * gridDim.x + blockIdx.x) * A.trace_stride : nullptr;
+      if (trace_row && lane == 0) trace_row[0] = __builtin_amdgcn_s_memrealtime();
+    }
+    // the first instruction of chunk c for this lane, zero on lanes past the
+    // chunk's end (their operand reads then hit slot 0, harmlessly); the
+    // load is unconditional (clamped index) so that it stays in the same
+    // basic block as the operand reads it overlaps
+    auto first_instr = [&](uint32_t chw) -> uint4 {
+      const uint32_t m = (chw >> 16) & 0xFF;
+      return Is[(chw & 0xFFFF) + (lane < m ? lane : m)];
+    };
+    uint32_t ch = n_ch ? chunk_word(0) : 0;
+    uint4 raw = first_instr(ch);
+    if (!(n_ch && lane <= ((ch >> 16) & 0xFF))) raw = make_uint4(0, 0, 0, 0);
+    uint32_t L_next = 1;   // next level whose end is timestamped
+    for (uint32_t c = 0; c < n_ch; ++c) {
+      const uint32_t chn = c + 1 < n_ch ? chunk_word(c + 1) : 0;
+      const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 0xFF) + 1, op = ch >> 24;
+      uint4 rawn;
+      if (op == I_ALU) {
+        // operand reads of this chunk, then the next chunk's first
+        // instruction; only the operands are waited for before computing
+        const Dec in = decode(raw);
+        uint64_t a = slot[in.a], b = slot[in.b], cc = slot[in.c];
+        rawn = first_instr(chn);
+        asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
+        const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
+        const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
+        if (lane < cnt) slot[in.dst] = r;
+      } else if (op == I_MEMRD) {
+        rawn = first_instr(chn);
+        if (lane < cnt) {
+          const Dec in = decode(raw);
+          const uint64_t a = slot[in.a];
+          const uint64_t depth = A.mem_depth[in.aux];
+          const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
+          slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
+        }
+      } else {
+        rawn = first_instr(chn);
+        // leaf loads and sink stores, up to four per lane, loads all issued
+        // before the first is used
+        Dec in[4];
+        uint64_t v[4];
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+          const uint32_t e = lane + 64 * q;
+          if (e < cnt) {
+            in[q] = decode(q == 0 ? raw : Is[start + e]);
+            if (op == I_LDREG) {
+              v[q] = cur[in[q].aux];
+            } else if (op == I_LDIN) {
+              if (A.in_vals) {
+                if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v[q] = 0; }
+                else v[q] = A.in_vals[(cyc - A.in_first) * A.I + in[q].aux];
+              } else {
+                v[q] = hmix(A.in_keys[in[q].aux] ^ cyc);
+              }
+            } else {
+              v[q] = slot[in[q].a];
+            }
+          }
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+          const uint32_t e = lane + 64 * q;
+          if (e < cnt) {
+            const uint64_t x = v[q] & wmask(in[q].w);
+            if (op == I_LDREG || op == I_LDIN) {
+              slot[in[q].dst] = x;
+            } else if (op == I_STREG) {
+              nxt[in[q].aux] = x;
+              if (A.digest_part) dacc += hmix((uint64_t)in[q].aux ^ hmix(x));
+            } else {
+              A.outputs[in[q].aux] = x;
+            }
+          }
+        }
+      }
+      if (!(c + 1 < n_ch && lane <= ((chn >> 16) & 0xFF))) rawn = make_uint4(0, 0, 0, 0);
+      ch = chn;
+      raw = rawn;
+      if (trace_row) {
+        // stamp the end of every level that ends with this chunk (levels
+        // beyond the 63rd are not stamped)
+        while (L_next < 64 && L_next <= n_lvls &&
+               c + 1 >= (uint32_t)__builtin_amdgcn_readlane((int)lv_lo, (int)L_next)) {
+          if (lane == 0 && L_next + 1 < A.trace_stride) trace_row[L_next] = __builtin_amdgcn_s_memrealtime();
+          ++L_next;
+        }
+      }
+    }
+    if (lane == 0) {
+      for (uint32_t k = 0; k < pp.n_wp; ++k) {
+        const Dec in = decode(Is[pp.n_instr + k]);
+        if (slot[in.a] != 0) {
+          const uint32_t m = in.aux;
+          const uint64_t depth = A.mem_depth[m], av = slot[in.b];
+          const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
+          A.mem[A.mem_off[m] + addr] = slot[in.c] & wmask(in.w);
+        }
+      }
+    }
+    if (A.digest_part) {
+      for (int off = 32; off > 0; off >>= 1) dacc += __shfl_xor(dacc, off);
+      const uint64_t k = cyc - A.digest_first;
+      if (lane == 0 && k < A.digest_max) A.digest_part[k * gridDim.x + blockIdx.x] = dacc;
+    }
+    if (trace_row && lane == 0) trace_row[A.trace_stride - 2] = __builtin_amdgcn_s_memrealtime();
+    if (PERSISTENT) {
+      if (gridDim.x > 1) {
+        if (!grid_barrier(A.flags, A.error, gridDim.x, A.epoch0 + t + 1, &abort_flag)) return;
+      } else {
+        asm volatile("" ::: "memory");
+      }
+    }
+    if (trace_row && lane == 0) trace_row[A.trace_stride - 1] = __builtin_amdgcn_s_memrealtime();
+  }
+}
+
+__global__ void __launch_bounds__(64) plain_wave_persistent(PlainArgs A) { plain_wave_body<true>(A); }
+__global__ void __launch_bounds__(64) plain_wave_cycle(PlainArgs A) { plain_wave_body<false>(A); }
 
 __global__ void __launch_bounds__(1024) plain_persistent(PlainArgs A) { plain_body<true, true>(A); }
 __global__ void __launch_bounds__(1024) plain_cycle(PlainArgs A) { plain_body<false, true>(A); }
@@ -364,10 +565,16 @@ __device__ __forceinline__ void lwrite(char* base, uint32_t cls, uint32_t off, u
   }
 }
 
-// one 16-byte instruction as four words (scalar loads)
+// The instruction stream reaches the wave in blocks of 64 instructions: lane
+// k holds instruction k of the block in four registers (one vector load per
+// block, issued a whole block ahead), and the wave-uniform instruction is
+// taken out with v_readlane.  Streaming the program through the scalar data
+// cache instead costs a cache miss every few instructions once several
+// waves per CU run different processes.
 struct IWord { uint32_t x, y, z, w; };
-__device__ __forceinline__ IWord fetch(cptr<uint32_t> p, uint32_t i) {
-  return IWord{p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]};
+__device__ __forceinline__ IWord lane_word(const uint4& b, uint32_t l) {
+  return IWord{(uint32_t)__builtin_amdgcn_readlane((int)b.x, (int)l), (uint32_t)__builtin_amdgcn_readlane((int)b.y, (int)l),
+               (uint32_t)__builtin_amdgcn_readlane((int)b.z, (int)l), (uint32_t)__builtin_amdgcn_readlane((int)b.w, (int)l)};
 }
 
 __device__ __forceinline__ uint64_t mread(const char* base, uint32_t off) {
@@ -384,7 +591,13 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
   const bool real = inst < A.n_inst;
   char* base = lds + (size_t)wave * A.wave_bytes;
   const BatchProc bp = A.procs[p];
-  const cptr<uint32_t> prog32 = as_const(reinterpret_cast<const uint32_t*>(A.instr + bp.instr_off));
+  const uint4* prog = reinterpret_cast<const uint4*>(A.instr);
+  // block b of this process: instructions instr_off + 64 b .. + 63, zero past
+  // the end of the program array
+  auto load_blk = [&](uint32_t b) -> uint4 {
+    const uint64_t j = (uint64_t)bp.instr_off + 64ull * b + lane;
+    return j < A.n_instr_total ? prog[j] : make_uint4(0, 0, 0, 0);
+  };
   const cptr<uint64_t> mem_off = as_const(A.mem_off);
   const cptr<uint32_t> mem_depth = as_const(A.mem_depth);
   // the wave's region: the two constant masks, then the process's constants
@@ -399,11 +612,18 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
   const uint64_t* stD_cur = A.stD + (size_t)cur * A.nD * A.n_pad;
   uint64_t* stD_nxt = A.stD + (size_t)nxt * A.nD * A.n_pad;
   uint64_t dacc = 0;
-  IWord q = fetch(prog32, 0);
+  uint32_t blk = 0;
+  uint4 bc = load_blk(0), bn = load_blk(1);
+  // instruction j of the process, j in the current or the next block
+  auto instr = [&](uint32_t j) -> IWord { return lane_word((j >> 6) == blk ? bc : bn, j & 63); };
   for (uint32_t i = 0; i < bp.n_instr;) {
-    // the next instruction is fetched before this one executes (the program
-    // ends with a pad instruction, so i + 1 is always readable)
-    const IWord qn = fetch(prog32, i + 1);
+    // a step advances i by at most 16, so it crosses at most one block
+    if ((i >> 6) != blk) {
+      bc = bn;
+      ++blk;
+      bn = load_blk(blk + 1);
+    }
+    const IWord q = lane_word(bc, i & 63);
     const uint32_t x = q.x, y = q.y, z = q.z, aux = q.w;
     const uint32_t op = x & 0xFF, w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
     const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
@@ -413,7 +633,6 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
       const uint64_t c = op == I_MUX ? lread(base, cc, oc, lane) : 0;
       lwrite(base, cd, dst, lane, alu(op, w, a, b, c));
       ++i;
-      q = qn;
       continue;
     }
     if (op >= K_MASK_AND) {
@@ -431,7 +650,6 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
       }
       if (lane == 0) *reinterpret_cast<uint64_t*>(base + dst) = r;
       ++i;
-      q = qn;
       continue;
     }
     switch (op) {
@@ -444,7 +662,8 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
 #pragma unroll
         for (uint32_t k = 0; k < 16; ++k) {
           if (k < n) {
-            const uint32_t xk = prog32[4 * (i + k)], auxk = prog32[4 * (i + k) + 3];
+            const IWord qk = instr(i + k);
+            const uint32_t xk = qk.x, auxk = qk.w;
             const uint32_t cak = (xk >> 18) & 3;
             if ((xk & 0xFF) == I_LDREG) {
               val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
@@ -461,7 +680,8 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
 #pragma unroll
         for (uint32_t k = 0; k < 16; ++k) {
           if (k < n) {
-            const uint32_t xk = prog32[4 * (i + k)], yk = prog32[4 * (i + k) + 1];
+            const IWord qk = instr(i + k);
+            const uint32_t xk = qk.x, yk = qk.y;
             const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
             const uint32_t dk = yk & 0xFFFF;
             if ((xk & 0xFF) == I_LDREG) {
@@ -482,7 +702,6 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
           }
         }
         i += n;
-        q = fetch(prog32, i);
         continue;
       }
       case I_MEMRD: {
@@ -523,7 +742,6 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
         break;
     }
     ++i;
-    q = qn;
   }
   if (A.digest && real) {
     const uint64_t k = cyc - A.digest_first;
@@ -566,6 +784,15 @@ namespace fsim {
 
 hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t lds_bytes,
                         bool persistent, hipStream_t s) {
+  if (a.single_wave) {
+    if (persistent) {
+      void* args[] = {const_cast<PlainArgs*>(&a)};
+      return hipLaunchCooperativeKernel((const void*)plain_wave_persistent, dim3(G), dim3(64), args,
+                                        (unsigned)lds_bytes, s);
+    }
+    hipLaunchKernelGGL(plain_wave_cycle, dim3(G), dim3(64), lds_bytes, s, a);
+    return hipGetLastError();
+  }
   if (persistent) {
     void* args[] = {const_cast<PlainArgs*>(&a)};
     return hipLaunchCooperativeKernel(a.stage_instr ? (const void*)plain_persistent : (const void*)plain_persistent_g,
@@ -591,7 +818,10 @@ hipError_t launch_batched_multi(const BatchArgs* jobs, const uint32_t* wg_start,
   return hipGetLastError();
 }
 
-hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged) {
+hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged,
+                           bool single_wave) {
+  if (single_wave)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, plain_wave_persistent, 64, lds_bytes);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, staged ? plain_persistent : plain_persistent_g,
                                                       (int)threads, lds_bytes);
 }

@@ -65,7 +65,7 @@ extern "C" int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_byt
   if (lds_bytes) *lds_bytes = ctx->lds_bytes;
   if (max_coresident_wgs) {
     int b = 0;
-    HIP_TRY(fsim::plain_occupancy(&b, 256, 0, true));
+    HIP_TRY(fsim::plain_occupancy(&b, 256, 0, true, false));
     *max_coresident_wgs = (uint32_t)b * ctx->n_cus;
   }
   return FSIM_OK;
@@ -391,9 +391,11 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
   }
   if (lds > lds_limit) return fail(FSIM_E_CAPACITY, "process does not fit in LDS");
   s->lds_bytes = lds;
+  // one wave per process: the flat chunk loop (chunk words held in registers)
+  s->single_wave = s->threads == 64 && s->stage_instr && d->max_chunks <= 256;
   if (s->launch == FSIM_LAUNCH_PERSISTENT) {
     int b = 0;
-    HIP_TRY(fsim::plain_occupancy(&b, s->threads, lds, s->stage_instr));
+    HIP_TRY(fsim::plain_occupancy(&b, s->threads, lds, s->stage_instr, s->single_wave));
     if ((uint64_t)b * d->ctx->n_cus < s->G)
       return fail(FSIM_E_CAPACITY, "persistent launch: " + std::to_string(s->G) +
                                        " workgroups are not co-resident; use fewer processes");
@@ -480,6 +482,7 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   a.slot_words = dd->slot_words;
   a.instr_words = dd->max_proc_instr;
   a.chunk_words = dd->max_chunks;
+  a.single_wave = s->single_wave ? 1 : 0;
   a.cycle_ptr = nullptr;
   return a;
 }
@@ -489,6 +492,7 @@ fsim::BatchArgs fsim::batch_args(fsim_sim* s) {
   const Design& D = dd->d;
   fsim::BatchArgs a{};
   a.instr = (const fsim::Instr*)dd->b_instr.p;
+  a.n_instr_total = D.batch_instr.size();
   a.procs = (const fsim::BatchProc*)dd->b_procs.p;
   a.consts = (const uint64_t*)dd->b_consts.p;
   a.stB = s->stB; a.stW = s->stW; a.stD = s->stD;

@@ -76,6 +76,7 @@ struct fsim_sim {
   uint32_t G = 1, threads = 256, launch = FSIM_LAUNCH_PERSISTENT, graph_cycles = 64;
   size_t lds_bytes = 0;
   bool stage_instr = false;
+  bool single_wave = false;    // plain form: the flat one-wave kernel
   bool poisoned = false;
   uint64_t cycle = 0, seed = 0;
   uint32_t epoch = 0;

@@ -624,6 +624,37 @@ def xorshift32(seed=2463534242) -> Netlist:
     return b.build(name="xorshift32")
 
 
+def prng_array(n, seed=0x5EED) -> Netlist:
+    """n independent xorshift32 generators (three shifts and three XORs each,
+    the synchronization experiment of Parendi Sec. 4.1): every register is a
+    fiber on its own and no fiber reads another's state.  Built directly as
+    arrays (n reaches a million)."""
+    n_nodes = 3 + 7 * n
+    op = np.empty(n_nodes, np.uint8)
+    arg = np.full((n_nodes, 3), NONE, np.uint32)
+    imm = np.zeros(n_nodes, np.uint64)
+    op[:3] = OPS["CONST"]
+    imm[:3] = (13, 17, 5)
+    base = 3 + 7 * np.arange(n, dtype=np.int64)
+    op[base] = OPS["REG"]
+    imm[base] = np.arange(n, dtype=np.uint64)
+    for k, (o, a0, a1) in enumerate([("SHL", 0, None), ("XOR", 0, 1), ("SHR", 2, None),
+                                      ("XOR", 2, 3), ("SHL", 4, None), ("XOR", 4, 5)], start=1):
+        op[base + k] = OPS[o]
+        arg[base + k, 0] = base + a0
+        # shift amounts are the shared constants 13, 17, 5
+        arg[base + k, 1] = (base + a1) if a1 is not None else {1: 0, 3: 1, 5: 2}[k]
+    rng = np.random.default_rng(seed)
+    init = rng.integers(1, 2**32, n, dtype=np.uint64)
+    return Netlist(
+        op=op, width=np.full(n_nodes, 32, np.uint8), arg=arg, imm=imm,
+        reg_width=np.full(n, 32, np.uint8), reg_init=init, reg_next=(base + 6).astype(np.uint32),
+        in_width=np.zeros(0, np.uint8), out_node=np.zeros(0, np.uint32),
+        mem_depth=np.zeros(0, np.uint32), mem_width=np.zeros(0, np.uint8), mem_init=np.zeros(0, np.uint64),
+        wp_mem=np.zeros(0, np.uint32), wp_en=np.zeros(0, np.uint32), wp_addr=np.zeros(0, np.uint32),
+        wp_data=np.zeros(0, np.uint32), name=f"prng{n}", meta=dict(seed=seed))
+
+
 def swap_pair(w=16, a0=0x1234, b0=0xBEEF) -> Netlist:
     b = Builder()
     ra, rb_ = b.add_reg(w, a0), b.add_reg(w, b0)

@@ -76,10 +76,10 @@ def edge_cases():
     return b.build("edge_cases")
 
 
-def check_plain(F, ctx, nl, pack, cycles):
-    print(f"case {nl.name}: plain pack={pack} cycles={cycles}", flush=True)
+def check_plain(F, ctx, nl, pack, cycles, threads=0):
+    print(f"case {nl.name}: plain pack={pack} threads={threads} cycles={cycles}", flush=True)
     d = F.Design(ctx, nl, pack=pack)
-    s = F.Sim(d, 1, seed=SEED)
+    s = F.Sim(d, 1, seed=SEED, wg_threads=threads)
     s.enable_digest(cycles)
     s.step(cycles)
     ref = O.Sim(nl, seed=SEED)
@@ -110,8 +110,9 @@ def check_batched(F, ctx, nl, n_inst, cycles):
 
 @pytest.mark.parametrize("make", [no_operators, edge_cases])
 @pytest.mark.parametrize("pack", [0, 1, 2])
-def test_plain_degenerate(F, ctx, make, pack):
-    check_plain(F, ctx, make(), pack, 257)
+@pytest.mark.parametrize("threads", [64, 256])
+def test_plain_degenerate(F, ctx, make, pack, threads):
+    check_plain(F, ctx, make(), pack, 257, threads)
 
 
 @pytest.mark.parametrize("make", [no_operators, edge_cases])

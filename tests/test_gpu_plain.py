@@ -84,9 +84,17 @@ def small_core(seed=5):
     return g.gen_core(seed, p)
 
 
-@pytest.mark.parametrize("target", [4, 24, 200])
-def test_small_core_with_memories(F, ctx, target):
-    run_both(F, ctx, small_core(), 400, 0, target)
+@pytest.mark.parametrize("target,threads", [(4, 0), (24, 0), (200, 0), (24, 64), (200, 64)])
+def test_small_core_with_memories(F, ctx, target, threads):
+    """threads 64: one wave per process, the flat chunk loop."""
+    run_both(F, ctx, small_core(), 400, 0, target, threads=threads)
+
+
+@pytest.mark.parametrize("launch", [1, 3])
+def test_single_wave_launch_modes(F, ctx, launch):
+    """The one-wave kernel under the grid barrier and under graph launches,
+    with steps that cut graphs and persistent launches unevenly."""
+    run_both(F, ctx, g.gen_tiny(6), 700, 0, 9, launch=launch, threads=64, chunks=(1, 64, 129, None))
 
 
 def test_core_full_size_2000_cycles(F, ctx):
@@ -94,6 +102,12 @@ def test_core_full_size_2000_cycles(F, ctx):
     4096 x 64 memories), one fiber per register merged to 256 processes;
     2,000 cycles compared per cycle (the oracle needs ~6 ms per cycle)."""
     run_both(F, ctx, g.workload("core"), 2000, 0, 256)
+
+
+def test_core_full_size_single_wave(F, ctx):
+    """The single-core workload at 1024 one-wave processes (the flat chunk
+    loop), 1,000 cycles compared per cycle."""
+    run_both(F, ctx, g.workload("core"), 1000, 0, 1024, launch=3, threads=64)
 
 
 def _pairs_inputs(n=4):

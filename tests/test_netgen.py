@@ -57,3 +57,22 @@ def test_soc_replicates_core():
     assert soc.n_mems == 4 * core.n_mems and soc.n_inputs == 4 * core.n_inputs
     sim = O.Sim(soc, seed=1)      # valid: acyclic, indices in range
     sim.step(20)
+
+
+def test_prng_array_is_independent_xorshift32():
+    """Each register of the PRNG array follows Marsaglia's xorshift32
+    recurrence on its own (the synchronization experiment of Sec. 4.1)."""
+    from oracle import oracle as O
+    nl = g.prng_array(37, seed=3)
+    assert nl.n_comb_ops() == 6 * 37
+    ref = O.Sim(nl, seed=1)
+    ref.step(11)
+    def xs(v):
+        v ^= (v << 13) & 0xFFFFFFFF
+        v ^= v >> 17
+        v ^= (v << 5) & 0xFFFFFFFF
+        return v
+    x = [int(v) for v in nl.reg_init]
+    for _ in range(11):
+        x = [xs(v) for v in x]
+    assert [int(v) for v in ref.regs()] == x
