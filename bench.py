@@ -125,6 +125,64 @@ def bench_plain_tuned(F, g, tune, ctx, name, targets, threads, cycles, warm, see
     return out
 
 
+def barrier_estimate(F, sim, cycles=24):
+    """Per-cycle cost outside the slowest workgroup's compute, from the phase
+    timestamps: cycle period minus the slowest workgroup's compute span
+    (start to commit).  In graph mode this is the launch gap; in persistent
+    mode the grid barrier."""
+    import numpy as np
+    sim.enable_trace(cycles)
+    sim.step(cycles)
+    tr = sim.trace().astype(np.int64)
+    stride = tr.shape[2]
+    period = np.diff(tr[:, :, 0].min(axis=1)) * 10 / 1000
+    comp = (tr[:, :, stride - 2] - tr[:, :, 0]).max(axis=1) * 10 / 1000
+    return {"period_us": round(float(np.median(period)), 3),
+            "slowest_compute_us": round(float(np.median(comp[1:])), 3),
+            "barrier_us": round(float(np.median(period) - np.median(comp[1:])), 3)}
+
+
+def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=8192, cycles=200):
+    """The 48-tile SoC: compile statistics (duplication overhead), the plain
+    form at one instance and the batched form at 64 instances."""
+    nl = g.workload("soc48")
+    out = {"workload": nl.name, "registers": int(nl.n_regs), "word_ops": int(nl.n_comb_ops()),
+           "memories": int(nl.n_mems), "plain": [], "batched": None}
+    designs = {}
+    for target, threads in plain_cfgs:
+        if target not in designs:
+            designs[target] = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=target)
+        d = designs[target]
+        info = d.info()
+        sim = F.Sim(d, 1, launch=F.LAUNCH_GRAPH, wg_threads=threads, seed=seed)
+        gpu_s = time_sim(sim, ctx.torch_stream, cycles, 20)
+        rec = {"processes": int(info["n_processes"]), "threads": threads,
+               "value": round(cycles / gpu_s, 1), "unit": "instance-cycles/s",
+               "us_per_cycle": round(gpu_s / cycles * 1e6, 2), "compile_s": round(info["compile_seconds"], 1),
+               "dup_fiber": round(info["dup_fiber"], 4), "dup_process": round(info["dup_process"], 4),
+               "duplicated_ops": int(round((info["dup_process"] - 1) * info["n_live_ops"])),
+               "process_levels": int(info["max_process_levels"]) + 2}
+        rec.update(barrier_estimate(F, sim))
+        out["plain"].append(rec)
+        print(json.dumps({"soc48_plain": rec}), file=sys.stderr, flush=True)
+        del sim
+    if batched_target not in designs:
+        designs[batched_target] = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=batched_target)
+    d = designs[batched_target]
+    sim = F.Sim(d, 64, launch=F.LAUNCH_GRAPH, seed=seed)
+    bc = max(8, cycles // 10)
+    gpu_s = time_sim(sim, ctx.torch_stream, bc, 4)
+    info = d.info()
+    bpc, _ = algorithmic_bytes_per_cycle(nl, info["n_live_ops"], 64)
+    out["batched"] = {"instances": 64, "processes": int(info["n_processes"]), "cycles": bc,
+                      "value": round(64 * bc / gpu_s, 1), "unit": "instance-cycles/s",
+                      "us_per_cycle": round(gpu_s / bc * 1e6, 1),
+                      "hbm_achieved_GBs": round(bpc / (gpu_s / bc) / 1e9, 2),
+                      "wave_lds_bytes": int(d.batched_info()["wave_lds_bytes"])}
+    print(json.dumps({"soc48_batched": out["batched"]}), file=sys.stderr, flush=True)
+    return out
+
+
 def bench_served(F, g, ctx, n_jobs, lam, inst_hi, cyc_lo, cyc_hi):
     """Served Poisson stream over the single-core and 8-tile SoC designs."""
     from paper_2403_04714_amd import serve
@@ -187,6 +245,10 @@ def main():
     ap.add_argument("--cycles", type=int, default=100_000, help="cycles per step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
+    ap.add_argument("--soc48", action="store_true",
+                    help="also measure the 48-tile SoC (compiling it takes about a minute)")
+    ap.add_argument("--soc48-plain", default="8192:64",
+                    help="plain configurations for --soc48, target:threads[,target:threads...]")
     ap.add_argument("--study", choices=["prng"], default=None,
                     help="run a study instead of the benchmark (prng: the barrier sweep of Sec. 4.1)")
     ap.add_argument("--no-extra", action="store_true",
@@ -306,6 +368,9 @@ def main():
                                               5000, 500, seed)
         out["served"] = bench_served(F, g, ctx, n_jobs=24, lam=4.0, inst_hi=1024, cyc_lo=100, cyc_hi=2000)
         out["extra_sections_s"] = round(time.time() - extra_t0, 1)
+    if args.soc48:
+        cfgs = tuple(tuple(int(v) for v in c.split(":")) for c in args.soc48_plain.split(","))
+        out["soc48"] = bench_soc48(F, g, ctx, seed, plain_cfgs=cfgs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(nl, seed)
     print(json.dumps(out), flush=True)

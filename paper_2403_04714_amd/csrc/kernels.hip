@@ -339,7 +339,21 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
   uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
-  for (uint32_t i = lane; i < n_all; i += 64) Is[i] = Ig[i];
+  // staging, eight loads in flight per lane (one memory latency per 512
+  // instructions; the per-cycle launch modes stage on every launch)
+  for (uint32_t base = 0; base < n_all; base += 512) {
+    uint4 t[8];
+#pragma unroll
+    for (uint32_t q = 0; q < 8; ++q) {
+      const uint32_t i = base + lane + 64 * q;
+      if (i < n_all) t[q] = Ig[i];
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < 8; ++q) {
+      const uint32_t i = base + lane + 64 * q;
+      if (i < n_all) Is[i] = t[q];
+    }
+  }
   for (uint32_t i = lane; i < pp.n_consts; i += 64) {
     const Instr in = A.instr[pp.const_off + i];
     slot[in.dst] = A.consts[in.aux];
@@ -359,6 +373,14 @@ __device__ void plain_wave_body(const PlainArgs& A) {
     const uint32_t v = q == 0 ? cw[0] : q == 1 ? cw[1] : q == 2 ? cw[2] : cw[3];
     return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(c & 63));
   };
+  // the first instruction of a chunk for this lane; lanes past the chunk's
+  // end get its last instruction (valid slots to read, their results are
+  // not stored).  No condition: the load stays in the basic block of the
+  // operand reads it overlaps.  For "no chunk" (word 0) it reads entry 0.
+  auto first_instr = [&](uint32_t chw) -> uint4 {
+    const uint32_t m = (chw >> 16) & 0xFF;
+    return Is[(chw & 0xFFFF) + (lane < m ? lane : m)];
+  };
   const uint64_t cyc0 = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
   uint64_t* trace_row = nullptr;
   for (uint32_t t = 0; t < A.n_cycles; ++t) {
@@ -371,34 +393,44 @@ __device__ void plain_wave_body(const PlainArgs& A) {
       trace_row = k < A.trace_max ? A.trace + (k * gridDim.x + blockIdx.x) * A.trace_stride : nullptr;
       if (trace_row && lane == 0) trace_row[0] = __builtin_amdgcn_s_memrealtime();
     }
-    // the first instruction of chunk c for this lane, zero on lanes past the
-    // chunk's end (their operand reads then hit slot 0, harmlessly); the
-    // load is unconditional (clamped index) so that it stays in the same
-    // basic block as the operand reads it overlaps
-    auto first_instr = [&](uint32_t chw) -> uint4 {
-      const uint32_t m = (chw >> 16) & 0xFF;
-      return Is[(chw & 0xFFFF) + (lane < m ? lane : m)];
+    uint32_t L_next = 1;   // next level whose end is timestamped
+    auto stamp = [&](uint32_t done) {
+      // stamp the end of every level that ends before chunk `done` (levels
+      // beyond the 63rd are not stamped)
+      while (L_next < 64 && L_next <= n_lvls &&
+             done >= (uint32_t)__builtin_amdgcn_readlane((int)lv_lo, (int)L_next)) {
+        if (lane == 0 && L_next + 1 < A.trace_stride) trace_row[L_next] = __builtin_amdgcn_s_memrealtime();
+        ++L_next;
+      }
     };
+    uint32_t c = 0;
     uint32_t ch = n_ch ? chunk_word(0) : 0;
     uint4 raw = first_instr(ch);
-    if (!(n_ch && lane <= ((ch >> 16) & 0xFF))) raw = make_uint4(0, 0, 0, 0);
-    uint32_t L_next = 1;   // next level whose end is timestamped
-    for (uint32_t c = 0; c < n_ch; ++c) {
-      const uint32_t chn = c + 1 < n_ch ? chunk_word(c + 1) : 0;
+    while (c < n_ch) {
+      if ((ch >> 24) == I_ALU) {
+        // a run of operator chunks: operand reads, then the next chunk's
+        // first instruction; only the operands are waited for
+        do {
+          const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
+          const uint32_t chn = c + 1 < n_ch ? chunk_word(c + 1) : 0;
+          const Dec in = decode(raw);
+          uint64_t a = slot[in.a], b = slot[in.b], cc = slot[in.c];
+          const uint4 rn = first_instr(chn);
+          asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
+          const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
+          const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
+          if (lane < cnt) slot[in.dst] = r;
+          ++c;
+          ch = chn;
+          raw = rn;
+          if (trace_row) stamp(c);
+        } while (c < n_ch && (ch >> 24) == I_ALU);
+        continue;
+      }
       const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 0xFF) + 1, op = ch >> 24;
-      uint4 rawn;
-      if (op == I_ALU) {
-        // operand reads of this chunk, then the next chunk's first
-        // instruction; only the operands are waited for before computing
-        const Dec in = decode(raw);
-        uint64_t a = slot[in.a], b = slot[in.b], cc = slot[in.c];
-        rawn = first_instr(chn);
-        asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
-        const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
-        const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
-        if (lane < cnt) slot[in.dst] = r;
-      } else if (op == I_MEMRD) {
-        rawn = first_instr(chn);
+      const uint32_t chn = c + 1 < n_ch ? chunk_word(c + 1) : 0;
+      const uint4 rn = first_instr(chn);
+      if (op == I_MEMRD) {
         if (lane < cnt) {
           const Dec in = decode(raw);
           const uint64_t a = slot[in.a];
@@ -407,7 +439,6 @@ __device__ void plain_wave_body(const PlainArgs& A) {
           slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
         }
       } else {
-        rawn = first_instr(chn);
         // leaf loads and sink stores, up to four per lane, loads all issued
         // before the first is used
         Dec in[4];
@@ -447,18 +478,10 @@ __device__ void plain_wave_body(const PlainArgs& A) {
           }
         }
       }
-      if (!(c + 1 < n_ch && lane <= ((chn >> 16) & 0xFF))) rawn = make_uint4(0, 0, 0, 0);
+      ++c;
       ch = chn;
-      raw = rawn;
-      if (trace_row) {
-        // stamp the end of every level that ends with this chunk (levels
-        // beyond the 63rd are not stamped)
-        while (L_next < 64 && L_next <= n_lvls &&
-               c + 1 >= (uint32_t)__builtin_amdgcn_readlane((int)lv_lo, (int)L_next)) {
-          if (lane == 0 && L_next + 1 < A.trace_stride) trace_row[L_next] = __builtin_amdgcn_s_memrealtime();
-          ++L_next;
-        }
-      }
+      raw = rn;
+      if (trace_row) stamp(c);
     }
     if (lane == 0) {
       for (uint32_t k = 0; k < pp.n_wp; ++k) {

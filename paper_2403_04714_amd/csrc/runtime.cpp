@@ -97,7 +97,10 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   const uint32_t lds = ctx ? ctx->lds_bytes : kDefaultLds;
   const uint32_t max_slots = (lds - kStaticLds) / 8;
   const uint32_t default_target = ctx ? ctx->n_cus : 256;
-  const uint32_t default_nodes = std::min<uint32_t>(max_slots / 2, 0xFFFE);
+  // default node cap of a process: its slots (8 B per node) and its staged
+  // instructions (16 B each, about 1.25 per node counting the stores) fit in
+  // LDS together, so every process runs from LDS-staged instructions
+  const uint32_t default_nodes = std::min<uint32_t>((lds - kStaticLds) / 28, 0xFFFE);
   s = fsim::partition_design(d, part, o, default_target, default_nodes);
   if (!s.ok()) return fail(s);
   s = fsim::encode_plain(d, std::min<uint32_t>(max_slots, 0xFFFE));
