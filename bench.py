@@ -39,6 +39,31 @@ def algorithmic_bytes_per_cycle(nl, n_live_ops, n_instances=1):
     return per_inst * n_instances + 8 * n_live_ops, state_bytes
 
 
+def kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2403_04714_amd", "csrc", "kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def measured_traffic(kernel, workload, processes, threads):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters over a
+    device copy of known size), or None when there is no summary for this
+    configuration or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    try:
+        with open(path) as f:
+            line = next(l for l in f if l.startswith("traffic_json: "))
+        rec = json.loads(line[len("traffic_json: "):])
+    except (OSError, StopIteration, ValueError):
+        return None
+    if (rec.get("kernel_source") != kernel_source_hash() or rec.get("processes") != processes
+            or rec.get("threads") != threads):
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def cpu_baseline(nl, seed, budget_s=12.0):
     """The oracle as it stands, single thread, on a bounded prefix."""
     from oracle import oracle as orc
@@ -247,8 +272,17 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--soc48", action="store_true",
                     help="also measure the 48-tile SoC (compiling it takes about a minute)")
-    ap.add_argument("--soc48-plain", default="8192:64",
+    ap.add_argument("--soc48-plain", default="8192:64,16384:64",
                     help="plain configurations for --soc48, target:threads[,target:threads...]")
+    ap.add_argument("--plain-config", default=None,
+                    help="target:threads:launch for the headline plain run, skipping the autotuner "
+                         "(launch 1 persistent, 3 graph); used for profiling runs")
+    ap.add_argument("--profile-run", choices=["batched-core", "plain-core", "plain-prng"], default=None,
+                    help="a short fixed run for hardware counters (per-cycle launches): batched "
+                         "single-core x256 on 1024 processes, plain single-core on 2048 one-wave "
+                         "processes, or 64 one-wave processes of 7 independent PRNG fibers")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a device copy of known size (the reference for HBM byte counters)")
     ap.add_argument("--study", choices=["prng"], default=None,
                     help="run a study instead of the benchmark (prng: the barrier sweep of Sec. 4.1)")
     ap.add_argument("--no-extra", action="store_true",
@@ -268,6 +302,32 @@ def main():
     from paper_2403_04714_amd import netgen as g
     from paper_2403_04714_amd import tune
 
+    if args.profile_run:
+        ctx = F.Context(0)
+        if args.profile_run == "batched-core":
+            d = F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=1024)
+            sim = F.Sim(d, 256, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
+        elif args.profile_run == "plain-core":
+            d = F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=2048)
+            sim = F.Sim(d, 1, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
+        else:
+            import numpy as np
+            d = F.Design(ctx, g.prng_array(7 * 64), partition=np.arange(7 * 64, dtype=np.uint32) // 7)
+            sim = F.Sim(d, 1, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
+        sim.step(32)
+        sim.sync()
+        print(json.dumps({"profile_run": args.profile_run, "layout": sim.layout(),
+                          "processes": d.info()["n_processes"], "cycles": 32}), flush=True)
+        return
+    if args.copy_calibration:
+        n = 512 << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": n, "bytes_written": n, "launches": 3}}), flush=True)
+        return
     if args.study == "prng":
         ctx = F.Context(0)
         print(json.dumps({"study": "prng barrier sweep (Sec. 4.1)", "rows": study_prng(F, g, ctx)}), flush=True)
@@ -279,9 +339,12 @@ def main():
     gen_s = time.time() - t0
     ctx = F.Context(0)
     t0 = time.time()
-    best, _ = tune.tune_plain(ctx, nl, targets=(128, 256, 512), threads=(64, 256),
-                              launches=(F.LAUNCH_PERSISTENT, F.LAUNCH_GRAPH), cycles=2000,
-                              use_cache=not args.retune)
+    if args.plain_config:
+        tgt, thr, la = (int(v) for v in args.plain_config.split(":"))
+        best = {"target": tgt, "threads": thr, "launch": la}
+    else:
+        best, _ = tune.tune_plain(ctx, nl, targets=(512, 1024, 2048, 4096), threads=(64, 256),
+                                  launches=(F.LAUNCH_GRAPH,), cycles=2000, use_cache=not args.retune)
     tune_s = time.time() - t0
     d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=best["target"])
     info = d.info()
@@ -308,15 +371,17 @@ def main():
     ms_per_step = gpu_s * 1e3 / args.steps
 
     bpc, state_bytes = algorithmic_bytes_per_cycle(nl, info["n_live_ops"])
+    one_wave = lay["threads"] == 64 and lay["staged"]
     if best["launch"] == F.LAUNCH_PERSISTENT:
-        kernel = "plain_persistent"
+        kernel = "plain_wave_persistent" if one_wave else "plain_persistent"
         cycles_per_launch = min(args.cycles, 1 << 20)
         launch_s = gpu_s / args.steps * cycles_per_launch / args.cycles
     else:
-        kernel = "plain_cycle"
+        kernel = "plain_wave_cycle" if one_wave else "plain_cycle"
         cycles_per_launch = 1
         launch_s = gpu_s / total_cycles       # upper bound: includes the graph's launch gaps
     achieved = bpc * cycles_per_launch / launch_s / 1e9
+    traffic = measured_traffic(kernel, "core", info["n_processes"], lay["threads"])
     out = {
         "metric": "simulated cycles/s x instances",
         "value": round(value, 1),
@@ -337,7 +402,7 @@ def main():
                    "stimulus_seed": seed},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": None,
+                     "traffic": traffic,
                      "bytes_per_cycle": bpc, "cycles_per_launch": cycles_per_launch,
                      "launch_ms": round(launch_s * 1e3, 4),
                      "note": "latency-bound: levels x per-level latency + barrier; see latency"},
@@ -364,7 +429,7 @@ def main():
             bench_batched(F, g, tune, ctx, "core", 1024, 1024, (64, 128), 512, 64, seed),
             bench_batched(F, g, tune, ctx, "soc8", 256, 4096, (64, 128), 256, 32, seed),
         ]
-        out["plain_soc8"] = bench_plain_tuned(F, g, tune, ctx, "soc8", (256, 512, 1024), (256, 1024),
+        out["plain_soc8"] = bench_plain_tuned(F, g, tune, ctx, "soc8", (1024, 2048, 4096), (64, 256),
                                               5000, 500, seed)
         out["served"] = bench_served(F, g, ctx, n_jobs=24, lam=4.0, inst_hi=1024, cyc_lo=100, cyc_hi=2000)
         out["extra_sections_s"] = round(time.time() - extra_t0, 1)

@@ -486,11 +486,18 @@ Status partition_design(Design& d, const fsim_partition* part, const fsim_compil
         uint64_t lo = std::max<uint64_t>(straggler, (total3 + target - 1) / target), hi = 0;
         bool found = false;
         const double grow = P3 > 20000 ? 1.04 : 1.1;
+        // a larger bound that no longer lowers the process count means the
+        // node cap, not the bound, is what stops the merge: three such trials
+        // in a row end the search (the final unbounded trial decides)
+        uint32_t prev_alive = UINT32_MAX, stalled = 0;
         for (uint64_t B = lo; B <= total3; B = std::max<uint64_t>(B + 1, (uint64_t)(B * grow))) {
           SlbResult t = slb_merge(d, n3, c3, s3, readers3, B, target, max_nodes);
           phase("stage 4 trial");
           if (t.n_alive <= target) { hi = B; best = std::move(t); found = true; break; }
           lo = B + 1;
+          stalled = t.n_alive >= prev_alive ? stalled + 1 : 0;
+          prev_alive = std::min(prev_alive, t.n_alive);
+          if (stalled >= 3) break;
           if (B == total3) break;
           if (B * grow >= total3) B = total3 - 1;
         }

@@ -128,6 +128,9 @@ struct Dec {
   uint32_t op, w, dst, a, b, c, aux;
 };
 
+// one 16-byte instruction as four plain words
+struct IWord { uint32_t x, y, z, w; };
+
 // The 16-byte instruction is read with one 128-bit load and decoded from
 // registers: x = op | w << 8 | cls << 16 | flags << 24, y = dst | a << 16,
 // z = b | c << 16, w = aux.
@@ -341,17 +344,21 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
   // staging, eight loads in flight per lane (one memory latency per 512
   // instructions; the per-cycle launch modes stage on every launch)
+  // (plain 16-byte words, not uint4: an array of the vector type is kept in
+  // scratch memory by the compiler)
+  const IWord* Igw = reinterpret_cast<const IWord*>(Ig);
+  IWord* Isw = reinterpret_cast<IWord*>(Is);
   for (uint32_t base = 0; base < n_all; base += 512) {
-    uint4 t[8];
+    IWord t[8];
 #pragma unroll
     for (uint32_t q = 0; q < 8; ++q) {
       const uint32_t i = base + lane + 64 * q;
-      if (i < n_all) t[q] = Ig[i];
+      t[q] = i < n_all ? Igw[i] : IWord{0, 0, 0, 0};
     }
 #pragma unroll
     for (uint32_t q = 0; q < 8; ++q) {
       const uint32_t i = base + lane + 64 * q;
-      if (i < n_all) Is[i] = t[q];
+      if (i < n_all) Isw[i] = t[q];
     }
   }
   for (uint32_t i = lane; i < pp.n_consts; i += 64) {
@@ -594,7 +601,6 @@ __device__ __forceinline__ void lwrite(char* base, uint32_t cls, uint32_t off, u
 // taken out with v_readlane.  Streaming the program through the scalar data
 // cache instead costs a cache miss every few instructions once several
 // waves per CU run different processes.
-struct IWord { uint32_t x, y, z, w; };
 __device__ __forceinline__ IWord lane_word(const uint4& b, uint32_t l) {
   return IWord{(uint32_t)__builtin_amdgcn_readlane((int)b.x, (int)l), (uint32_t)__builtin_amdgcn_readlane((int)b.y, (int)l),
                (uint32_t)__builtin_amdgcn_readlane((int)b.z, (int)l), (uint32_t)__builtin_amdgcn_readlane((int)b.w, (int)l)};

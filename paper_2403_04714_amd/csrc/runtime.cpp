@@ -102,6 +102,11 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   // LDS together, so every process runs from LDS-staged instructions
   const uint32_t default_nodes = std::min<uint32_t>((lds - kStaticLds) / 28, 0xFFFE);
   s = fsim::partition_design(d, part, o, default_target, default_nodes);
+  if (s.code == FSIM_E_CAPACITY && o.max_process_nodes == 0 && !part) {
+    // too few processes for that cap: allow processes whose instructions
+    // are read from global memory instead (slots alone must fit)
+    s = fsim::partition_design(d, part, o, default_target, std::min<uint32_t>(max_slots / 2, 0xFFFE));
+  }
   if (!s.ok()) return fail(s);
   s = fsim::encode_plain(d, std::min<uint32_t>(max_slots, 0xFFFE));
   if (!s.ok()) return fail(s);

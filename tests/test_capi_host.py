@@ -230,3 +230,26 @@ def test_capacity_limit_respected():
     with pytest.raises(F.FsimError) as e:
         host_design(nl, pack=F.PACK_SLB, target_processes=1, max_process_nodes=50)
     assert e.value.code == F.E_CAPACITY
+
+
+# every packing the GPU tests ask for compiles on the host (so that a GPU run
+# never spends its time on a design that cannot be built)
+@pytest.mark.parametrize("make,pack,target", [
+    ("tiny0", 2, 0), ("tiny1", 1, 0), ("tiny1", 0, 8), ("tiny1", 0, 33), ("tiny2", 0, 16),
+    ("tiny3", 0, 5), ("tiny4", 0, 12), ("tiny6", 0, 9),
+    ("small_core", 0, 4), ("small_core", 0, 24), ("small_core", 0, 200),
+    ("core", 0, 256), ("core", 0, 1024), ("core", 0, 2048),
+])
+def test_gpu_test_designs_compile(make, pack, target):
+    from paper_2403_04714_amd import fibersim as F
+    if make.startswith("tiny"):
+        nl = g.gen_tiny(int(make[4:]))
+    elif make == "small_core":
+        p = g.CoreParams(n_regs_1=1400, n_regs_32=300, n_regs_64=300, target_ops=20000,
+                         mem_depth=256, reg_locality=96)
+        nl = g.gen_core(5, p)
+    else:
+        nl = g.workload(make)
+    d = F.Design(None, nl, pack=pack, target_processes=target)
+    assert d.info()["n_processes"] >= 1
+    d.batched_info()
