@@ -40,10 +40,14 @@ def algorithmic_bytes_per_cycle(nl, n_live_ops, n_instances=1):
 
 
 def kernel_source_hash():
+    """Hash of the plain-form device code (the kernel file and the helpers it
+    shares with the batched form)."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2403_04714_amd", "csrc", "kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+    h = hashlib.sha1()
+    for name in ("kernels_plain.hip", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2403_04714_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
 
 
 def measured_traffic(kernel, workload, processes, threads):

@@ -1,0 +1,132 @@
+// device_common.h -- device helpers shared by the plain and the batched
+// kernels of libfibersim: the stimulus hash, width masks, the operator
+// evaluation, the grid barrier and the instruction decoding.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "isa.h"
+#include "kernels.h"
+
+namespace fsim {
+
+// SplitMix64 output function: the first output of a SplitMix64 generator whose
+// state is x (Steele, Lea and Flood, OOPSLA 2014; published constants).
+__device__ __forceinline__ uint64_t hmix(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t wmask(uint32_t w) { return ~0ull >> (64u - w); }
+
+// One combinational operator on zero-extended operands, masked to w.
+__device__ __forceinline__ uint64_t alu(uint32_t op, uint32_t w, uint64_t a, uint64_t b, uint64_t c) {
+  uint64_t r;
+  switch (op) {
+    case I_AND: r = a & b; break;
+    case I_OR:  r = a | b; break;
+    case I_XOR: r = a ^ b; break;
+    case I_NOT: r = ~a; break;
+    case I_ADD: r = a + b; break;
+    case I_SUB: r = a - b; break;
+    case I_MUX: r = a ? b : c; break;
+    case I_SHL: r = b >= 64 ? 0 : (a << b); break;   // explicit: the hardware
+    case I_SHR: r = b >= 64 ? 0 : (a >> b); break;   // takes amounts mod 64
+    case I_EQ:  r = a == b; break;
+    case I_LT:  r = a < b; break;
+    case I_MUL: r = a * b; break;
+    default:    r = 0; break;
+  }
+  return r & wmask(w);
+}
+
+// One operator per lane, opcodes differing between lanes.  `present` (wave
+// uniform) holds the opcodes that occur in the chunk: each of them is
+// evaluated for every lane and kept where it is the lane's own, so the cost
+// is a few vector instructions per opcode present, without divergent
+// branches.
+__device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uint32_t w, uint64_t a,
+                                              uint64_t b, uint64_t c) {
+  uint64_t r = 0;
+  // the empty asm keeps each test a real (scalar) branch, so opcodes absent
+  // from the chunk cost two scalar instructions instead of being computed
+#define FSIM_MIXED(OPC, EXPR) \
+  if (present & (1u << (OPC))) { asm volatile(""); r = op == (OPC) ? (uint64_t)(EXPR) : r; }
+  FSIM_MIXED(I_AND, a & b)
+  FSIM_MIXED(I_OR, a | b)
+  FSIM_MIXED(I_XOR, a ^ b)
+  FSIM_MIXED(I_NOT, ~a)
+  FSIM_MIXED(I_ADD, a + b)
+  FSIM_MIXED(I_SUB, a - b)
+  FSIM_MIXED(I_MUX, a ? b : c)
+  FSIM_MIXED(I_SHL, b >= 64 ? 0 : (a << (b & 63)))
+  FSIM_MIXED(I_SHR, b >= 64 ? 0 : (a >> (b & 63)))
+  FSIM_MIXED(I_EQ, a == b)
+  FSIM_MIXED(I_LT, a < b)
+  FSIM_MIXED(I_MUL, a * b)
+#undef FSIM_MIXED
+  return r & wmask(w);
+}
+
+static constexpr long kSpinLimit = 1l << 22;
+
+// Grid-wide barrier over G workgroups (see the file comment).  Returns false
+// if the poll exceeded its bound or another workgroup already gave up; the
+// caller then leaves its cycle loop so that every wave exits.
+__device__ __forceinline__ bool grid_barrier(uint32_t* flags, uint32_t* error, uint32_t G,
+                                             uint32_t epoch, int* lds_abort) {
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    long spins = 0;
+    bool ok = true;
+    for (;;) {
+      bool mine = true;
+      for (uint32_t g = threadIdx.x; g < G; g += 64) {
+        uint32_t v = __hip_atomic_load(&flags[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int32_t)(v - epoch) < 0) mine = false;
+      }
+      if (__all(mine)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if ((++spins & 1023) == 0) {
+        if (__hip_atomic_load(&error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = false; break; }
+        if (spins > kSpinLimit) {
+          if (threadIdx.x == 0) atomicOr(&error[0], 1u);
+          ok = false;
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) *lds_abort = ok ? 0 : 1;
+  }
+  __syncthreads();
+  return *lds_abort == 0;
+}
+
+struct Dec {
+  uint32_t op, w, dst, a, b, c, aux;
+};
+
+// one 16-byte instruction as four plain words
+struct IWord { uint32_t x, y, z, w; };
+
+// The 16-byte instruction is read with one 128-bit load and decoded from
+// registers: x = op | w << 8 | cls << 16 | flags << 24, y = dst | a << 16,
+// z = b | c << 16, w = aux.
+__device__ __forceinline__ Dec decode(uint4 r) {
+  Dec d;
+  d.op = r.x & 0xFF; d.w = (r.x >> 8) & 0xFF;
+  d.dst = r.y & 0xFFFF; d.a = r.y >> 16;
+  d.b = r.z & 0xFFFF; d.c = r.z >> 16;
+  d.aux = r.w;
+  return d;
+}
+
+}  // namespace fsim

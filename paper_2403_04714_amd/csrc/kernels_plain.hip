@@ -1,4 +1,4 @@
-// kernels.hip -- gfx950 device code of libfibersim.
+// kernels_plain.hip -- gfx950 device code of libfibersim: the plain form.
 //
 // Plain form (one instance): a workgroup runs one process (a set of fibers,
 // Parendi Sec. 3.2).  Per simulated cycle it evaluates the process level by
@@ -20,128 +20,9 @@
 
 #include <cstdint>
 
-#include "isa.h"
-#include "kernels.h"
+#include "device_common.h"
 
 namespace fsim {
-
-// SplitMix64 output function: the first output of a SplitMix64 generator whose
-// state is x (Steele, Lea and Flood, OOPSLA 2014; published constants).
-__device__ __forceinline__ uint64_t hmix(uint64_t x) {
-  uint64_t z = x + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ uint64_t wmask(uint32_t w) { return ~0ull >> (64u - w); }
-
-// One combinational operator on zero-extended operands, masked to w.
-__device__ __forceinline__ uint64_t alu(uint32_t op, uint32_t w, uint64_t a, uint64_t b, uint64_t c) {
-  uint64_t r;
-  switch (op) {
-    case I_AND: r = a & b; break;
-    case I_OR:  r = a | b; break;
-    case I_XOR: r = a ^ b; break;
-    case I_NOT: r = ~a; break;
-    case I_ADD: r = a + b; break;
-    case I_SUB: r = a - b; break;
-    case I_MUX: r = a ? b : c; break;
-    case I_SHL: r = b >= 64 ? 0 : (a << b); break;   // explicit: the hardware
-    case I_SHR: r = b >= 64 ? 0 : (a >> b); break;   // takes amounts mod 64
-    case I_EQ:  r = a == b; break;
-    case I_LT:  r = a < b; break;
-    case I_MUL: r = a * b; break;
-    default:    r = 0; break;
-  }
-  return r & wmask(w);
-}
-
-// One operator per lane, opcodes differing between lanes.  `present` (wave
-// uniform) holds the opcodes that occur in the chunk: each of them is
-// evaluated for every lane and kept where it is the lane's own, so the cost
-// is a few vector instructions per opcode present, without divergent
-// branches.
-__device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uint32_t w, uint64_t a,
-                                              uint64_t b, uint64_t c) {
-  uint64_t r = 0;
-  // the empty asm keeps each test a real (scalar) branch, so opcodes absent
-  // from the chunk cost two scalar instructions instead of being computed
-#define FSIM_MIXED(OPC, EXPR) \
-  if (present & (1u << (OPC))) { asm volatile(""); r = op == (OPC) ? (uint64_t)(EXPR) : r; }
-  FSIM_MIXED(I_AND, a & b)
-  FSIM_MIXED(I_OR, a | b)
-  FSIM_MIXED(I_XOR, a ^ b)
-  FSIM_MIXED(I_NOT, ~a)
-  FSIM_MIXED(I_ADD, a + b)
-  FSIM_MIXED(I_SUB, a - b)
-  FSIM_MIXED(I_MUX, a ? b : c)
-  FSIM_MIXED(I_SHL, b >= 64 ? 0 : (a << (b & 63)))
-  FSIM_MIXED(I_SHR, b >= 64 ? 0 : (a >> (b & 63)))
-  FSIM_MIXED(I_EQ, a == b)
-  FSIM_MIXED(I_LT, a < b)
-  FSIM_MIXED(I_MUL, a * b)
-#undef FSIM_MIXED
-  return r & wmask(w);
-}
-
-static constexpr long kSpinLimit = 1l << 22;
-
-// Grid-wide barrier over G workgroups (see the file comment).  Returns false
-// if the poll exceeded its bound or another workgroup already gave up; the
-// caller then leaves its cycle loop so that every wave exits.
-__device__ __forceinline__ bool grid_barrier(uint32_t* flags, uint32_t* error, uint32_t G,
-                                             uint32_t epoch, int* lds_abort) {
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    if (threadIdx.x == 0) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    long spins = 0;
-    bool ok = true;
-    for (;;) {
-      bool mine = true;
-      for (uint32_t g = threadIdx.x; g < G; g += 64) {
-        uint32_t v = __hip_atomic_load(&flags[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((int32_t)(v - epoch) < 0) mine = false;
-      }
-      if (__all(mine)) break;
-      __builtin_amdgcn_s_sleep(1);
-      if ((++spins & 1023) == 0) {
-        if (__hip_atomic_load(&error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = false; break; }
-        if (spins > kSpinLimit) {
-          if (threadIdx.x == 0) atomicOr(&error[0], 1u);
-          ok = false;
-          break;
-        }
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (threadIdx.x == 0) *lds_abort = ok ? 0 : 1;
-  }
-  __syncthreads();
-  return *lds_abort == 0;
-}
-
-struct Dec {
-  uint32_t op, w, dst, a, b, c, aux;
-};
-
-// one 16-byte instruction as four plain words
-struct IWord { uint32_t x, y, z, w; };
-
-// The 16-byte instruction is read with one 128-bit load and decoded from
-// registers: x = op | w << 8 | cls << 16 | flags << 24, y = dst | a << 16,
-// z = b | c << 16, w = aux.
-__device__ __forceinline__ Dec decode(uint4 r) {
-  Dec d;
-  d.op = r.x & 0xFF; d.w = (r.x >> 8) & 0xFF;
-  d.dst = r.y & 0xFFFF; d.a = r.y >> 16;
-  d.b = r.z & 0xFFFF; d.c = r.z >> 16;
-  d.aux = r.w;
-  return d;
-}
 
 template <bool PERSISTENT, bool STAGED>
 __device__ void plain_body(const PlainArgs& A) {
@@ -547,265 +428,6 @@ __global__ void stim_keys(uint64_t* keys, uint64_t seed_base, uint32_t n_inst, u
   keys[k] = hmix(hmix(seed_base + i) ^ (uint64_t)p);
 }
 
-
-// ------------------------------------------------------------ batched form
-//
-// A wave evaluates one process for 64 instances (one lane per instance,
-// Sec. 6.4's many-independent-tests scenario).  The instruction stream is
-// wave-uniform, so it is fetched with scalar loads and dispatched with scalar
-// branches.  Values live in LDS slots per class: a 1-bit value is one 64-lane
-// ballot mask, a narrow value one u32 per lane, a wide value one u64 per lane.
-// Operators whose operands and result are all 1-bit work on the masks
-// directly.
-
-// Read-only for the whole launch (program, constant pool, memory tables, the
-// current half of the state): reading through the constant address space lets
-// the compiler use scalar loads for wave-uniform addresses instead of a vector
-// load plus a wait for every interpreted instruction.
-template <class T>
-using cptr = const __attribute__((address_space(4))) T*;
-template <class T>
-__device__ __forceinline__ cptr<T> as_const(const T* p) {
-  return (cptr<T>)(p);
-}
-
-// One operand of a per-lane operator, zero-extended to 64 bits.  `off` is a
-// byte offset into the wave's LDS region; the class picks the lane stride
-// (1-bit masks and constants: every lane reads the same word; u32 and u64
-// rows: one element per lane) and the extraction.  Rows of u32 are read as
-// two u32 words so that only 4-byte alignment is assumed.
-__device__ __forceinline__ uint64_t lread(const char* base, uint32_t cls, uint32_t off, uint32_t lane) {
-  const uint32_t stride = (0x0840u >> (cls * 4)) & 0xF;      // B 0, W 4, D 8, K 0
-  const uint32_t* p = reinterpret_cast<const uint32_t*>(base + off + lane * stride);
-  const uint64_t v = (uint64_t)p[0] | ((uint64_t)p[1] << 32);
-  const uint32_t sh = cls == C_B ? lane : 0;
-  const uint64_t m = cls == C_B ? 1ull : cls == C_W ? 0xFFFFFFFFull : ~0ull;
-  return (v >> sh) & m;
-}
-
-// Store a per-lane value into a slot of class cls (never a constant).
-__device__ __forceinline__ void lwrite(char* base, uint32_t cls, uint32_t off, uint32_t lane, uint64_t v) {
-  if (cls == C_B) {
-    const uint64_t m = __ballot(v & 1);
-    if (lane == 0) *reinterpret_cast<uint64_t*>(base + off) = m;
-  } else if (cls == C_W) {
-    reinterpret_cast<uint32_t*>(base + off)[lane] = (uint32_t)v;
-  } else {
-    reinterpret_cast<uint64_t*>(base + off)[lane] = v;
-  }
-}
-
-// The instruction stream reaches the wave in blocks of 64 instructions: lane
-// k holds instruction k of the block in four registers (one vector load per
-// block, issued a whole block ahead), and the wave-uniform instruction is
-// taken out with v_readlane.  Streaming the program through the scalar data
-// cache instead costs a cache miss every few instructions once several
-// waves per CU run different processes.
-__device__ __forceinline__ IWord lane_word(const uint4& b, uint32_t l) {
-  return IWord{(uint32_t)__builtin_amdgcn_readlane((int)b.x, (int)l), (uint32_t)__builtin_amdgcn_readlane((int)b.y, (int)l),
-               (uint32_t)__builtin_amdgcn_readlane((int)b.z, (int)l), (uint32_t)__builtin_amdgcn_readlane((int)b.w, (int)l)};
-}
-
-__device__ __forceinline__ uint64_t mread(const char* base, uint32_t off) {
-  return *reinterpret_cast<const uint64_t*>(base + off);
-}
-
-// One simulated cycle of one (process, tile group) work item of a batched sim.
-__device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block, uint64_t cyc, char* lds) {
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t p = block % A.P, grp = block / A.P;
-  const uint32_t tile = grp * A.tpw + wave;
-  if (tile >= A.n_tiles) return;                 // no barriers below: a wave may leave early
-  const uint32_t inst = tile * 64 + lane;        // < n_pad
-  const bool real = inst < A.n_inst;
-  char* base = lds + (size_t)wave * A.wave_bytes;
-  const BatchProc bp = A.procs[p];
-  const uint4* prog = reinterpret_cast<const uint4*>(A.instr);
-  // block b of this process: instructions instr_off + 64 b .. + 63, zero past
-  // the end of the program array
-  auto load_blk = [&](uint32_t b) -> uint4 {
-    const uint64_t j = (uint64_t)bp.instr_off + 64ull * b + lane;
-    return j < A.n_instr_total ? prog[j] : make_uint4(0, 0, 0, 0);
-  };
-  const cptr<uint64_t> mem_off = as_const(A.mem_off);
-  const cptr<uint32_t> mem_depth = as_const(A.mem_depth);
-  // the wave's region: the two constant masks, then the process's constants
-  if (lane < 2) reinterpret_cast<uint64_t*>(base)[lane] = lane ? ~0ull : 0ull;
-  for (uint32_t k = lane; k < bp.n_consts; k += 64)
-    reinterpret_cast<uint64_t*>(base + A.kbase)[k] = A.consts[bp.const_off + k];
-  const uint32_t cur = cyc & 1, nxt = cur ^ 1;
-  const cptr<uint64_t> stB_cur = as_const(A.stB + (size_t)cur * A.nB * A.n_tiles);
-  uint64_t* stB_nxt = A.stB + (size_t)nxt * A.nB * A.n_tiles;
-  const uint32_t* stW_cur = A.stW + (size_t)cur * A.nW * A.n_pad;
-  uint32_t* stW_nxt = A.stW + (size_t)nxt * A.nW * A.n_pad;
-  const uint64_t* stD_cur = A.stD + (size_t)cur * A.nD * A.n_pad;
-  uint64_t* stD_nxt = A.stD + (size_t)nxt * A.nD * A.n_pad;
-  uint64_t dacc = 0;
-  uint32_t blk = 0;
-  uint4 bc = load_blk(0), bn = load_blk(1);
-  // instruction j of the process, j in the current or the next block
-  auto instr = [&](uint32_t j) -> IWord { return lane_word((j >> 6) == blk ? bc : bn, j & 63); };
-  for (uint32_t i = 0; i < bp.n_instr;) {
-    // a step advances i by at most 16, so it crosses at most one block
-    if ((i >> 6) != blk) {
-      bc = bn;
-      ++blk;
-      bn = load_blk(blk + 1);
-    }
-    const IWord q = lane_word(bc, i & 63);
-    const uint32_t x = q.x, y = q.y, z = q.z, aux = q.w;
-    const uint32_t op = x & 0xFF, w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
-    const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
-    const uint32_t dst = y & 0xFFFF, oa = y >> 16, ob = z & 0xFFFF, oc = z >> 16;
-    if (op >= I_AND && op <= I_MUL) {
-      const uint64_t a = lread(base, ca, oa, lane), b = lread(base, cb, ob, lane);
-      const uint64_t c = op == I_MUX ? lread(base, cc, oc, lane) : 0;
-      lwrite(base, cd, dst, lane, alu(op, w, a, b, c));
-      ++i;
-      continue;
-    }
-    if (op >= K_MASK_AND) {
-      // every operand and the result are 64-instance masks
-      const uint64_t ma = mread(base, oa), mb = mread(base, ob);
-      uint64_t r;
-      switch (op) {
-        case K_MASK_AND: r = ma & mb; break;
-        case K_MASK_OR:  r = ma | mb; break;
-        case K_MASK_XOR: r = ma ^ mb; break;        // also 1-bit ADD and SUB (sums mod 2)
-        case K_MASK_NOT: r = ~ma; break;
-        case K_MASK_EQ:  r = ~(ma ^ mb); break;
-        case K_MASK_LT:  r = ~ma & mb; break;
-        default:         r = (ma & mb) | (~ma & mread(base, oc)); break;   // MUX
-      }
-      if (lane == 0) *reinterpret_cast<uint64_t*>(base + dst) = r;
-      ++i;
-      continue;
-    }
-    switch (op) {
-      case I_LDREG:
-      case I_LDIN: {
-        // a run of up to 16 leaf loads (length in flags): every load is issued
-        // before any result is used, so the run costs one memory latency
-        const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
-        uint64_t val[16];
-#pragma unroll
-        for (uint32_t k = 0; k < 16; ++k) {
-          if (k < n) {
-            const IWord qk = instr(i + k);
-            const uint32_t xk = qk.x, auxk = qk.w;
-            const uint32_t cak = (xk >> 18) & 3;
-            if ((xk & 0xFF) == I_LDREG) {
-              val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
-                     : cak == C_W ? (uint64_t)stW_cur[(size_t)auxk * A.n_pad + inst]
-                                  : stD_cur[(size_t)auxk * A.n_pad + inst];
-            } else if (A.in_vals) {
-              val[k] = (real && cyc >= A.in_first && cyc < A.in_first + A.in_count)
-                           ? A.in_vals[((cyc - A.in_first) * A.I + auxk) * A.n_inst + inst] : 0;
-            } else {
-              val[k] = A.keys[(size_t)auxk * A.n_pad + inst];
-            }
-          }
-        }
-#pragma unroll
-        for (uint32_t k = 0; k < 16; ++k) {
-          if (k < n) {
-            const IWord qk = instr(i + k);
-            const uint32_t xk = qk.x, yk = qk.y;
-            const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
-            const uint32_t dk = yk & 0xFFFF;
-            if ((xk & 0xFF) == I_LDREG) {
-              if (cak == C_B) {
-                if (cdk == C_B) { if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = val[k]; }
-                else lwrite(base, cdk, dk, lane, (val[k] >> lane) & 1);
-              } else {
-                lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
-              }
-            } else {
-              if (A.in_vals) {
-                if (cyc < A.in_first || cyc >= A.in_first + A.in_count) atomicOr(&A.error[1], 1u);
-                lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
-              } else {
-                lwrite(base, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
-              }
-            }
-          }
-        }
-        i += n;
-        continue;
-      }
-      case I_MEMRD: {
-        const uint64_t a = lread(base, ca, oa, lane);
-        const uint64_t depth = mem_depth[aux];
-        const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-        lwrite(base, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
-        break;
-      }
-      case I_STREG: {
-        // cd: class of the register's state array, ca: class of the value
-        const uint64_t v = lread(base, ca, oa, lane) & wmask(w);
-        if (cd == C_B) {
-          const uint64_t m = __ballot(v & 1);
-          if (lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile] = m;
-        } else if (cd == C_W) {
-          stW_nxt[(size_t)aux * A.n_pad + inst] = (uint32_t)v;
-        } else {
-          stD_nxt[(size_t)aux * A.n_pad + inst] = v;
-        }
-        if (A.digest) dacc += hmix((uint64_t)(ob | (oc << 16)) ^ hmix(v));
-        break;
-      }
-      case I_STOUT:
-        A.outputs[(size_t)aux * A.n_pad + inst] = lread(base, ca, oa, lane) & wmask(w);
-        break;
-      case I_WPORT: {
-        const uint64_t en = lread(base, ca, oa, lane), a = lread(base, cb, ob, lane);
-        const uint64_t v = lread(base, cc, oc, lane);
-        if (en) {
-          const uint64_t depth = mem_depth[aux];
-          const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-          A.mem[(mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
-        }
-        break;
-      }
-      default:
-        break;
-    }
-    ++i;
-  }
-  if (A.digest && real) {
-    const uint64_t k = cyc - A.digest_first;
-    if (k < A.digest_max) atomicAdd((unsigned long long*)&A.digest[k * A.n_inst + inst], (unsigned long long)dacc);
-  }
-}
-
-__global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
-  extern __shared__ uint64_t lds[];
-  const uint64_t cyc = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
-  batched_body(A, blockIdx.x, cyc, reinterpret_cast<char*>(lds));
-}
-
-// Serving: one launch advances every resident job by one cycle.  Job j owns
-// workgroups [wg_start[j], wg_start[j + 1]); a job whose budget for this
-// quantum is spent (tick >= ticks[j]) does nothing.  All jobs share the
-// launch's LDS size (the largest job's) and 64 threads per workgroup.
-__global__ void __launch_bounds__(64) batched_multi(const BatchArgs* __restrict__ jobs,
-                                                    const uint32_t* __restrict__ wg_start,
-                                                    const uint64_t* __restrict__ cycle_base,
-                                                    const uint32_t* __restrict__ ticks, uint32_t n_jobs,
-                                                    uint32_t tick) {
-  extern __shared__ uint64_t lds[];
-  // the job of this workgroup: binary search over the prefix table
-  uint32_t lo = 0, hi = n_jobs;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) / 2;
-    if (wg_start[mid] <= blockIdx.x) lo = mid; else hi = mid;
-  }
-  const uint32_t j = lo;
-  if (tick >= ticks[j]) return;
-  const BatchArgs A = jobs[j];
-  batched_body(A, blockIdx.x - wg_start[j], cycle_base[j] + tick, reinterpret_cast<char*>(lds));
-}
-
 }  // namespace fsim
 
 // ---------------------------------------------------------------- launches
@@ -829,21 +451,6 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t
   }
   if (a.stage_instr) hipLaunchKernelGGL(plain_cycle, dim3(G), dim3(threads), lds_bytes, s, a);
   else hipLaunchKernelGGL(plain_cycle_g, dim3(G), dim3(threads), lds_bytes, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_batched(const BatchArgs& a, uint32_t grid, uint32_t threads, size_t lds_bytes,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(batched_cycle, dim3(grid), dim3(threads), lds_bytes, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_batched_multi(const BatchArgs* jobs, const uint32_t* wg_start, const uint64_t* cycle_base,
-                                const uint32_t* ticks, uint32_t n_jobs, uint32_t tick, uint32_t grid,
-                                size_t lds_bytes, hipStream_t s) {
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(batched_multi, dim3(grid), dim3(64), lds_bytes, s, jobs, wg_start, cycle_base, ticks,
-                     n_jobs, tick);
   return hipGetLastError();
 }
 
