@@ -100,15 +100,19 @@ def time_sim(sim, stream, cycles, warm):
     return e0.elapsed_time(e1) / 1e3
 
 
-def bench_batched(F, g, tune, ctx, name, n_inst, target, threads, cycles, warm, seed):
+def bench_batched(F, g, tune, ctx, name, n_inst, targets, threads, cycles, warm, seed):
     """Batched form: n_inst instances in one launch per cycle (hipGraph),
-    packing target fixed, threads per workgroup autotuned."""
+    packing target and threads per workgroup autotuned."""
     nl = g.workload(name)
     t0 = time.time()
-    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=target)
+    designs = {t: F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=t) for t in targets}
     compile_s = time.time() - t0
-    best, _ = tune.tune_batched(ctx, nl, n_inst, targets=(target,), threads=threads, cycles=32,
-                                use_cache=False, designs={target: d})
+    best, _ = tune.tune_batched(ctx, nl, n_inst, targets=targets, threads=threads, cycles=32,
+                                use_cache=False, designs=designs)
+    d = designs[best["target"]]
+    for t in targets:
+        if t != best["target"]:
+            del designs[t]
     sim = F.Sim(d, n_inst, launch=F.LAUNCH_GRAPH, wg_threads=best["threads"], seed=seed)
     gpu_s = time_sim(sim, ctx.torch_stream, cycles, warm)
     info = d.info()
@@ -171,7 +175,7 @@ def barrier_estimate(F, sim, cycles=24):
             "barrier_us": round(float(np.median(period) - np.median(comp[1:])), 3)}
 
 
-def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=8192, cycles=200):
+def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=32768, cycles=200):
     """The 48-tile SoC: compile statistics (duplication overhead), the plain
     form at one instance and the batched form at 64 instances."""
     nl = g.workload("soc48")
@@ -215,15 +219,15 @@ def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=8192, 
 def bench_served(F, g, ctx, n_jobs, lam, inst_hi, cyc_lo, cyc_hi):
     """Served Poisson stream over the single-core and 8-tile SoC designs."""
     from paper_2403_04714_amd import serve
-    designs = [F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=1024),
-               F.Design(ctx, g.workload("soc8"), pack=F.PACK_SLB, target_processes=4096)]
+    designs = [F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=4096),
+               F.Design(ctx, g.workload("soc8"), pack=F.PACK_SLB, target_processes=16384)]
     jobs = serve.draw_jobs(n_jobs, designs, inst_lo=1, inst_hi=inst_hi, cyc_lo=cyc_lo, cyc_hi=cyc_hi)
     arr = serve.arrivals(n_jobs, lam=lam)
     srv = F.Server(ctx, 64 << 30, quantum_cycles=256)
     recs, summ = serve.run(srv, designs, jobs, arr, timeout_s=600)
     st = srv.stats()
     srv.close()
-    return {"designs": ["core (1024 processes)", "soc8 (4096 processes)"], "jobs": n_jobs,
+    return {"designs": ["core (4096 processes)", "soc8 (16384 processes)"], "jobs": n_jobs,
             "arrival_rate_per_s": lam, "instances": f"log-uniform [1, {inst_hi}]",
             "cycles": f"log-uniform [{cyc_lo}, {cyc_hi}]",
             "completed": summ["completed"], "p50_s": round(summ["p50_s"], 4), "p99_s": round(summ["p99_s"], 4),
@@ -430,8 +434,8 @@ def main():
         del sim
         extra_t0 = time.time()
         out["batched"] = [
-            bench_batched(F, g, tune, ctx, "core", 1024, 1024, (64, 128), 512, 64, seed),
-            bench_batched(F, g, tune, ctx, "soc8", 256, 4096, (64, 128), 256, 32, seed),
+            bench_batched(F, g, tune, ctx, "core", 1024, (2048, 4096, 8192), (64, 128), 512, 64, seed),
+            bench_batched(F, g, tune, ctx, "soc8", 256, (16384, 32768), (64, 128), 256, 32, seed),
         ]
         out["plain_soc8"] = bench_plain_tuned(F, g, tune, ctx, "soc8", (1024, 2048, 4096), (64, 256),
                                               5000, 500, seed)
