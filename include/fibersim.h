@@ -155,7 +155,10 @@ int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_bytes,
 /* Validate (Sec. 5.3: comb loops rejected), extract fibers by reverse crawl
  * (Sec. 5.1), pack them into processes (Sec. 5.1, or the given partition),
  * levelize and encode, and upload the program.  partition and opts may be
- * NULL. */
+ * NULL.  A process of more than 8191 live nodes does not fit the plain
+ * form's operand encoding: the design still loads (the batched form has no
+ * such limit), a plain sim of it fails with FSIM_E_CAPACITY, and
+ * FSIM_FORM_AUTO then picks the batched form for one instance too. */
 int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl,
                      const fsim_partition* partition,
                      const fsim_compile_opts* opts, fsim_design** out);

@@ -590,7 +590,8 @@ Status encode_plain(Design& d, uint32_t max_slots) {
   for (uint32_t p = 0; p < d.P; ++p) {
     const uint32_t lo = d.proc_off[p], hi = d.proc_off[p + 1];
     const uint32_t n = hi - lo;
-    if (n > max_slots || n > 0xFFFE)
+    // operands are LDS byte offsets in 16 bits: at most 8191 slots
+    if (n > max_slots || n > 8191)
       return Status::err(FSIM_E_CAPACITY,
                          fmt("process %llu needs %llu value slots; use more processes", p, n));
     for (uint32_t i = lo; i < hi; ++i) slot[d.proc_nodes[i]] = i - lo;
@@ -602,7 +603,7 @@ Status encode_plain(Design& d, uint32_t max_slots) {
       uint32_t x = d.proc_nodes[i];
       if (d.op[x] != FSIM_OP_CONST) continue;
       uint64_t v = d.imm[x] & (~0ull >> (64 - d.width[x]));
-      d.plain_instr.push_back(make(I_LDCONST, d.width[x], (uint16_t)slot[x], 0, 0, 0,
+      d.plain_instr.push_back(make(I_LDCONST, d.width[x], (uint16_t)(8 * slot[x]), 0, 0, 0,
                                    (uint32_t)d.consts.size()));
       d.consts.push_back(v);
     }
@@ -642,10 +643,10 @@ Status encode_plain(Design& d, uint32_t max_slots) {
     while (i < hi && d.level[d.proc_nodes[i]] == 0) {
       uint32_t x = d.proc_nodes[i++];
       if (d.op[x] == FSIM_OP_REG)
-        ins.push_back(make(I_LDREG, d.width[x], (uint16_t)slot[x], 0, 0, 0, (uint32_t)d.imm[x]));
+        ins.push_back(make(I_LDREG, d.width[x], (uint16_t)(8 * slot[x]), 0, 0, 0, (uint32_t)d.imm[x]));
       else if (d.op[x] == FSIM_OP_INPUT)   // the width folds in the port's own width
         ins.push_back(make(I_LDIN, std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]),
-                           (uint16_t)slot[x], 0, 0, 0, (uint32_t)d.imm[x]));
+                           (uint16_t)(8 * slot[x]), 0, 0, 0, (uint32_t)d.imm[x]));
     }
     std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
     emit_level(ins);
@@ -659,12 +660,12 @@ Status encode_plain(Design& d, uint32_t max_slots) {
       for (uint32_t x : lvl_nodes) {
         uint8_t op = d.op[x];
         const uint32_t* a = &d.arg[3ull * x];
-        uint16_t sa = (uint16_t)slot[a[0]];
-        auto s = [&](int k) -> uint16_t { return k < arity(op) ? (uint16_t)slot[a[k]] : sa; };
+        uint16_t sa = (uint16_t)(8 * slot[a[0]]);
+        auto s = [&](int k) -> uint16_t { return k < arity(op) ? (uint16_t)(8 * slot[a[k]]) : sa; };
         if (op == FSIM_OP_MEMRD)
-          ins.push_back(make(I_MEMRD, d.width[x], (uint16_t)slot[x], sa, sa, sa, (uint32_t)d.imm[x]));
+          ins.push_back(make(I_MEMRD, d.width[x], (uint16_t)(8 * slot[x]), sa, sa, sa, (uint32_t)d.imm[x]));
         else
-          ins.push_back(make(op, d.width[x], (uint16_t)slot[x], sa, s(1), s(2), 0));
+          ins.push_back(make(op, d.width[x], (uint16_t)(8 * slot[x]), sa, s(1), s(2), 0));
       }
       std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
       emit_level(ins);
@@ -675,10 +676,10 @@ Status encode_plain(Design& d, uint32_t max_slots) {
     for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
       uint32_t s = d.psinks[k];
       if (s < d.R)
-        ins.push_back(make(I_STREG, d.reg_width[s], 0, (uint16_t)slot[d.reg_next[s]], 0, 0, s));
+        ins.push_back(make(I_STREG, d.reg_width[s], 0, (uint16_t)(8 * slot[d.reg_next[s]]), 0, 0, s));
       else if (s >= d.R + d.W) {
         uint32_t o = s - d.R - d.W;
-        ins.push_back(make(I_STOUT, d.width[d.out_node[o]], 0, (uint16_t)slot[d.out_node[o]], 0, 0, o));
+        ins.push_back(make(I_STOUT, d.width[d.out_node[o]], 0, (uint16_t)(8 * slot[d.out_node[o]]), 0, 0, o));
       }
     }
     std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
@@ -695,8 +696,8 @@ Status encode_plain(Design& d, uint32_t max_slots) {
       uint32_t s = d.psinks[k];
       if (s >= d.R && s < d.R + d.W) {
         uint32_t q = s - d.R;
-        d.plain_instr.push_back(make(I_WPORT, d.mem_width[d.wp_mem[q]], 0, (uint16_t)slot[d.wp_en[q]],
-                                     (uint16_t)slot[d.wp_addr[q]], (uint16_t)slot[d.wp_data[q]], d.wp_mem[q]));
+        d.plain_instr.push_back(make(I_WPORT, d.mem_width[d.wp_mem[q]], 0, (uint16_t)(8 * slot[d.wp_en[q]]),
+                                     (uint16_t)(8 * slot[d.wp_addr[q]]), (uint16_t)(8 * slot[d.wp_data[q]]), d.wp_mem[q]));
       }
     }
     pp.n_wp = (uint32_t)d.plain_instr.size() - pp.instr_off - pp.n_instr;

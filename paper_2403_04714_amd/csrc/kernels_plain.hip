@@ -32,7 +32,9 @@ __device__ void plain_body(const PlainArgs& A) {
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
   const uint32_t lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
   const PlainProc pp = A.procs[blockIdx.x];
-  uint64_t* slot = lds;
+  // value slots: instruction operands are byte offsets into the slot area
+  char* const slot_base = reinterpret_cast<char*>(lds);
+  auto at = [slot_base](uint32_t off) -> uint64_t& { return *reinterpret_cast<uint64_t*>(slot_base + off); };
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
   uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
@@ -44,7 +46,7 @@ __device__ void plain_body(const PlainArgs& A) {
   for (uint32_t L = tid; L <= pp.n_lvls; L += nthr) lvs[L] = A.levels[pp.lvl_off + L];
   for (uint32_t i = tid; i < pp.n_consts; i += nthr) {
     const Instr in = A.instr[pp.const_off + i];
-    slot[in.dst] = A.consts[in.aux];
+    at(in.dst) = A.consts[in.aux];
   }
   if (tid == 0) abort_flag = 0;
   __syncthreads();
@@ -106,10 +108,10 @@ __device__ void plain_body(const PlainArgs& A) {
           // switch then runs on registers only
           if (lane < cnt) {
             const Dec in = decode(first ? raw_first : fetch(start + lane));
-            uint64_t a = slot[in.a], b = slot[in.b], cc = slot[in.c];
+            uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
             asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
             const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
-            slot[in.dst] = alu_mixed(present, in.op, in.w, a, b, cc);
+            at(in.dst) = alu_mixed(present, in.op, in.w, a, b, cc);
           }
         } else if (op == I_LDREG || op == I_LDIN || op == I_STREG || op == I_STOUT) {
           // up to four instructions per lane; all loads are issued before the
@@ -131,7 +133,7 @@ __device__ void plain_body(const PlainArgs& A) {
                   v[q] = hmix(A.in_keys[in[q].aux] ^ cyc);
                 }
               } else {
-                v[q] = slot[in[q].a];
+                v[q] = at(in[q].a);
               }
             }
           }
@@ -141,7 +143,7 @@ __device__ void plain_body(const PlainArgs& A) {
             if (e < cnt) {
               const uint64_t x = v[q] & wmask(in[q].w);   // LDIN widths fold in the port width
               if (op == I_LDREG || op == I_LDIN) {
-                slot[in[q].dst] = x;
+                at(in[q].dst) = x;
               } else if (op == I_STREG) {
                 nxt[in[q].aux] = x;
                 if (A.digest_part) dacc += hmix((uint64_t)in[q].aux ^ hmix(x));
@@ -153,10 +155,10 @@ __device__ void plain_body(const PlainArgs& A) {
         } else if (op == I_MEMRD) {
           if (lane < cnt) {
             const Dec in = decode(first ? raw_first : fetch(start + lane));
-            const uint64_t a = slot[in.a];
+            const uint64_t a = at(in.a);
             const uint64_t depth = A.mem_depth[in.aux];
             const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-            slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
+            at(in.dst) = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
           }
         }
         first = false;
@@ -176,11 +178,11 @@ __device__ void plain_body(const PlainArgs& A) {
     if (tid == 0) {
       for (uint32_t k = 0; k < pp.n_wp; ++k) {
         const Dec in = decode(fetch(pp.n_instr + k));
-        if (slot[in.a] != 0) {
+        if (at(in.a) != 0) {
           const uint32_t m = in.aux;
-          const uint64_t depth = A.mem_depth[m], av = slot[in.b];
+          const uint64_t depth = A.mem_depth[m], av = at(in.b);
           const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
-          A.mem[A.mem_off[m] + addr] = slot[in.c] & wmask(in.w);
+          A.mem[A.mem_off[m] + addr] = at(in.c) & wmask(in.w);
         }
       }
     }
@@ -219,7 +221,9 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   __shared__ int abort_flag;
   const uint32_t lane = threadIdx.x;
   const PlainProc pp = A.procs[blockIdx.x];
-  uint64_t* slot = lds;
+  // value slots: instruction operands are byte offsets into the slot area
+  char* const slot_base = reinterpret_cast<char*>(lds);
+  auto at = [slot_base](uint32_t off) -> uint64_t& { return *reinterpret_cast<uint64_t*>(slot_base + off); };
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
   uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
@@ -244,7 +248,7 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   }
   for (uint32_t i = lane; i < pp.n_consts; i += 64) {
     const Instr in = A.instr[pp.const_off + i];
-    slot[in.dst] = A.consts[in.aux];
+    at(in.dst) = A.consts[in.aux];
   }
   const uint32_t n_ch = pp.n_chunks;
   uint32_t cw[4];
@@ -256,11 +260,6 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   const uint32_t lv_lo = lane <= n_lvls ? A.levels[pp.lvl_off + lane] : 0;
   if (lane == 0) abort_flag = 0;
   __syncthreads();
-  auto chunk_word = [&](uint32_t c) -> uint32_t {
-    const uint32_t q = c >> 6;
-    const uint32_t v = q == 0 ? cw[0] : q == 1 ? cw[1] : q == 2 ? cw[2] : cw[3];
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(c & 63));
-  };
   // the first instruction of a chunk for this lane; lanes past the chunk's
   // end get its last instruction (valid slots to read, their results are
   // not stored).  No condition: the load stays in the basic block of the
@@ -291,8 +290,19 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         ++L_next;
       }
     };
-    uint32_t c = 0;
-    uint32_t ch = n_ch ? chunk_word(0) : 0;
+    uint32_t c = 0, c_base = 0;
+    uint32_t cr[4] = {cw[0], cw[1], cw[2], cw[3]};
+    auto rotate = [&]() {      // c has reached c_base + 64
+      cr[0] = cr[1];
+      cr[1] = cr[2];
+      cr[2] = cr[3];
+      c_base += 64;
+    };
+    auto word = [&](uint32_t cc) -> uint32_t {
+      const uint32_t v = cc - c_base < 64 ? cr[0] : cr[1];
+      return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(cc & 63));
+    };
+    uint32_t ch = n_ch ? word(0) : 0;
     uint4 raw = first_instr(ch);
     while (c < n_ch) {
       if ((ch >> 24) == I_ALU) {
@@ -300,31 +310,32 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         // first instruction; only the operands are waited for
         do {
           const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
-          const uint32_t chn = c + 1 < n_ch ? chunk_word(c + 1) : 0;
+          const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
           const Dec in = decode(raw);
-          uint64_t a = slot[in.a], b = slot[in.b], cc = slot[in.c];
+          uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
           const uint4 rn = first_instr(chn);
           asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
           const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
           const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
-          if (lane < cnt) slot[in.dst] = r;
+          if (lane < cnt) at(in.dst) = r;
           ++c;
           ch = chn;
           raw = rn;
+          if (c - c_base == 64) rotate();
           if (trace_row) stamp(c);
         } while (c < n_ch && (ch >> 24) == I_ALU);
         continue;
       }
       const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 0xFF) + 1, op = ch >> 24;
-      const uint32_t chn = c + 1 < n_ch ? chunk_word(c + 1) : 0;
+      const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
       const uint4 rn = first_instr(chn);
       if (op == I_MEMRD) {
         if (lane < cnt) {
           const Dec in = decode(raw);
-          const uint64_t a = slot[in.a];
+          const uint64_t a = at(in.a);
           const uint64_t depth = A.mem_depth[in.aux];
           const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-          slot[in.dst] = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
+          at(in.dst) = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
         }
       } else {
         // leaf loads and sink stores, up to four per lane, loads all issued
@@ -346,7 +357,7 @@ __device__ void plain_wave_body(const PlainArgs& A) {
                 v[q] = hmix(A.in_keys[in[q].aux] ^ cyc);
               }
             } else {
-              v[q] = slot[in[q].a];
+              v[q] = at(in[q].a);
             }
           }
         }
@@ -356,7 +367,7 @@ __device__ void plain_wave_body(const PlainArgs& A) {
           if (e < cnt) {
             const uint64_t x = v[q] & wmask(in[q].w);
             if (op == I_LDREG || op == I_LDIN) {
-              slot[in[q].dst] = x;
+              at(in[q].dst) = x;
             } else if (op == I_STREG) {
               nxt[in[q].aux] = x;
               if (A.digest_part) dacc += hmix((uint64_t)in[q].aux ^ hmix(x));
@@ -369,16 +380,17 @@ __device__ void plain_wave_body(const PlainArgs& A) {
       ++c;
       ch = chn;
       raw = rn;
+      if (c - c_base == 64) rotate();
       if (trace_row) stamp(c);
     }
     if (lane == 0) {
       for (uint32_t k = 0; k < pp.n_wp; ++k) {
         const Dec in = decode(Is[pp.n_instr + k]);
-        if (slot[in.a] != 0) {
+        if (at(in.a) != 0) {
           const uint32_t m = in.aux;
-          const uint64_t depth = A.mem_depth[m], av = slot[in.b];
+          const uint64_t depth = A.mem_depth[m], av = at(in.b);
           const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
-          A.mem[A.mem_off[m] + addr] = slot[in.c] & wmask(in.w);
+          A.mem[A.mem_off[m] + addr] = at(in.c) & wmask(in.w);
         }
       }
     }

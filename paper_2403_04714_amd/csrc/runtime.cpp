@@ -104,12 +104,25 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   s = fsim::partition_design(d, part, o, default_target, default_nodes);
   if (s.code == FSIM_E_CAPACITY && o.max_process_nodes == 0 && !part) {
     // too few processes for that cap: allow processes whose instructions
-    // are read from global memory instead (slots alone must fit)
-    s = fsim::partition_design(d, part, o, default_target, std::min<uint32_t>(max_slots / 2, 0xFFFE));
+    // are read from global memory instead (slots alone must fit) ...
+    s = fsim::partition_design(d, part, o, default_target, std::min<uint32_t>(max_slots / 2, 8191));
+    // ... or, failing that, processes only the batched form can run
+    if (s.code == FSIM_E_CAPACITY)
+      s = fsim::partition_design(d, part, o, default_target, 1u << 30);
   }
   if (!s.ok()) return fail(s);
   s = fsim::encode_plain(d, std::min<uint32_t>(max_slots, 0xFFFE));
-  if (!s.ok()) return fail(s);
+  if (s.code == FSIM_E_CAPACITY) {
+    // the design still loads: the batched form has no such limit, and a
+    // plain sim asked for later reports this error
+    dz->plain_ok = false;
+    dz->plain_error = "plain form: " + s.msg;
+    d.plain_procs.clear(); d.plain_levels.clear(); d.plain_chunks.clear(); d.plain_instr.clear();
+    d.consts.clear();
+    d.plain_max_slots = d.plain_max_instr = d.plain_max_chunks = d.max_plain_lvls = 0;
+  } else if (!s.ok()) {
+    return fail(s);
+  }
   // per-process spans, for the LDS layout
   dz->max_proc_instr = d.plain_max_instr;
   dz->max_lvls = d.max_plain_lvls;
@@ -367,7 +380,9 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
   auto s = std::make_unique<fsim_sim>();
   s->d = d;
   s->n_inst = n_instances;
-  s->batched = o.form == FSIM_FORM_BATCHED || (o.form == FSIM_FORM_AUTO && n_instances > 1);
+  s->batched = o.form == FSIM_FORM_BATCHED ||
+               (o.form == FSIM_FORM_AUTO && (n_instances > 1 || !d->plain_ok));
+  if (!s->batched && !d->plain_ok) return fail(FSIM_E_CAPACITY, d->plain_error);
   if (!s->batched && n_instances != 1) return fail(FSIM_E_ARG, "the plain form runs exactly one instance");
   if (s->batched) {
     int rc = sim_create_batched(s.get(), workspace, ws_bytes, o);

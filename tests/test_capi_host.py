@@ -237,7 +237,7 @@ def test_capacity_limit_respected():
 @pytest.mark.parametrize("make,pack,target", [
     ("tiny0", 2, 0), ("tiny1", 1, 0), ("tiny1", 0, 8), ("tiny1", 0, 33), ("tiny2", 0, 16),
     ("tiny3", 0, 5), ("tiny4", 0, 12), ("tiny6", 0, 9),
-    ("small_core", 0, 4), ("small_core", 0, 24), ("small_core", 0, 200),
+    ("small_core", 0, 4), ("small_core", 0, 6), ("small_core", 0, 24), ("small_core", 0, 200),
     ("core", 0, 256), ("core", 0, 1024), ("core", 0, 2048),
 ])
 def test_gpu_test_designs_compile(make, pack, target):

@@ -84,10 +84,28 @@ def small_core(seed=5):
     return g.gen_core(seed, p)
 
 
-@pytest.mark.parametrize("target,threads", [(4, 0), (24, 0), (200, 0), (24, 64), (200, 64)])
+@pytest.mark.parametrize("target,threads", [(6, 0), (24, 0), (200, 0), (24, 64), (200, 64)])
 def test_small_core_with_memories(F, ctx, target, threads):
     """threads 64: one wave per process, the flat chunk loop."""
     run_both(F, ctx, small_core(), 400, 0, target, threads=threads)
+
+
+def test_oversized_processes_fall_back_to_batched(F, ctx):
+    """Four processes of the small core exceed the plain form's 8191-node
+    limit: the design loads, a plain sim is refused with FSIM_E_CAPACITY,
+    and the automatic form runs one instance in the batched form, which
+    matches the oracle."""
+    nl = small_core()
+    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=4)
+    with pytest.raises(F.FsimError) as e:
+        F.Sim(d, 1, form=F.FORM_PLAIN)
+    assert e.value.code == F.E_CAPACITY
+    s = F.Sim(d, 1, seed=SEED)
+    s.enable_digest(50)
+    s.step(50)
+    ref = O.Sim(nl, seed=SEED)
+    assert np.array_equal(s.digests()[:, 0], ref.step(50, digests=True))
+    assert np.array_equal(s.regs(), ref.regs())
 
 
 @pytest.mark.parametrize("launch", [1, 3])
