@@ -40,6 +40,10 @@ static void phase(const char* what) {
   t0 = t;
 }
 
+// leaf loads the batched kernel issues back to back before waiting: more
+// hide more memory latency, fewer keep fewer values live (LDS per wave)
+static constexpr uint32_t kLeafRun = 4;
+
 static inline int arity(uint8_t op) {
   switch (op) {
     case FSIM_OP_CONST: case FSIM_OP_INPUT: case FSIM_OP_REG: return 0;
@@ -782,7 +786,7 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
     // kernel then issues a group's loads back to back and waits once, instead
     // of one full memory latency per leaf.
     {
-      const size_t kGroup = 16;
+      const size_t kGroup = kLeafRun;
       std::vector<uint32_t> out, leaves, rest;
       out.reserve(order.size());
       auto flush = [&]() {
@@ -790,12 +794,22 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
         out.insert(out.end(), rest.begin(), rest.end());
         leaves.clear(); rest.clear();
       };
+      // within a group, inputs first, then registers by state class, so that
+      // register loads of one class form runs
+      auto leaf_key = [&](uint32_t x) -> uint32_t {
+        return d.op[x] == FSIM_OP_INPUT ? 0u : 1u + class_of_width(d.reg_width[d.imm[x]]);
+      };
+      auto flush_sorted = [&]() {
+        std::stable_sort(leaves.begin(), leaves.end(),
+                         [&](uint32_t a, uint32_t b) { return leaf_key(a) < leaf_key(b); });
+        flush();
+      };
       for (uint32_t x : order) {
         const bool leaf = d.op[x] == FSIM_OP_REG || d.op[x] == FSIM_OP_INPUT;
-        if (leaf && leaves.size() == kGroup) flush();
+        if (leaf && leaves.size() == kGroup) flush_sorted();
         (leaf ? leaves : rest).push_back(x);
       }
-      flush();
+      flush_sorted();
       order.swap(out);
       for (uint32_t i = 0; i < (uint32_t)order.size(); ++i) emitted[order[i]] = i;
     }
@@ -913,14 +927,30 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
     }
     bp.n_instr = (uint32_t)d.batch_instr.size() - bp.instr_off;
     bp.n_consts = (uint32_t)d.batch_consts.size() - bp.const_off;
-    // runs of consecutive leaf loads (at most 16): the first carries the run
-    // length in flags, the kernel executes the run as one group
+    // runs of consecutive leaf loads (at most kLeafRun, never crossing a block of
+    // 64 instructions): the first carries the run length in flags, the
+    // kernel executes the run as one group.  A run of register loads of one
+    // class whose slot class and width match the register's gets its own
+    // opcode (K_LDREG_*), executed without per-load class tests.
     for (uint32_t i = bp.instr_off; i < bp.instr_off + bp.n_instr;) {
       auto is_leaf = [&](uint32_t j) { return d.batch_instr[j].op == I_LDREG || d.batch_instr[j].op == I_LDIN; };
+      auto fast_kind = [&](uint32_t j) -> uint32_t {   // 0: not a plain same-class register load
+        const Instr& in = d.batch_instr[j];
+        if (in.op != I_LDREG) return 0;
+        const uint32_t r = in.b | ((uint32_t)in.c << 16);
+        const uint8_t cd = in.cls & 3, ca = (in.cls >> 2) & 3;
+        if (cd != ca || in.w != d.reg_width[r]) return 0;
+        return K_LDREG_B + ca;
+      };
       if (!is_leaf(i)) { ++i; continue; }
-      uint32_t j = i;
-      while (j < bp.instr_off + bp.n_instr && j - i < 16 && is_leaf(j)) ++j;
+      const uint32_t fk = fast_kind(i);
+      uint32_t j = i + 1;
+      while (j < bp.instr_off + bp.n_instr && j - i < kLeafRun && is_leaf(j) && (j - bp.instr_off) % 64 != 0 &&
+             fast_kind(j) == fk)
+        ++j;
       d.batch_instr[i].flags = (uint8_t)(j - i);
+      if (fk)
+        for (uint32_t k = i; k < j; ++k) d.batch_instr[k].op = (uint8_t)fk;
       i = j;
     }
     for (int k = 0; k < 3; ++k) {
@@ -964,7 +994,7 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
         return off(cls, idx);
       };
       const uint8_t op = in.op;
-      if (op == I_LDREG || op == I_LDIN) { in.dst = off(cd, in.dst); }
+      if (op == I_LDREG || op == I_LDIN || (op >= K_LDREG_B && op <= K_LDREG_D)) { in.dst = off(cd, in.dst); }
       else if (op == I_MEMRD) { in.dst = off(cd, in.dst); in.a = off(ca, in.a); }
       else if (op == I_STREG || op == I_STOUT) { in.a = off(ca, in.a); }
       else if (op == I_WPORT) { in.a = off(ca, in.a); in.b = off(cb, in.b); in.c = off(cc, in.c); }

@@ -87,7 +87,11 @@ inline uint32_t chunk_capacity(uint32_t op) {
 // become whole-mask handlers.
 enum : uint8_t {
   K_MASK_AND = 24, K_MASK_OR = 25, K_MASK_XOR = 26, K_MASK_NOT = 27,
-  K_MASK_EQ = 28, K_MASK_LT = 29, K_MASK_MUX = 30
+  K_MASK_EQ = 28, K_MASK_LT = 29, K_MASK_MUX = 30,
+  // a run of register loads of one class whose slot class and width match
+  // the register's (run length in flags, never crossing a 64-instruction
+  // block of the process's stream)
+  K_LDREG_B = 40, K_LDREG_W = 41, K_LDREG_D = 42
 };
 struct BatchProc {
   uint32_t instr_off;

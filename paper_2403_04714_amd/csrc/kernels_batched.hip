@@ -9,6 +9,9 @@
 
 namespace fsim {
 
+// longest run of leaf loads the encoder emits (issued back to back)
+static constexpr uint32_t kLeafRun = 4;
+
 // ------------------------------------------------------------ batched form
 //
 // A wave evaluates one process for 64 instances (one lane per instance,
@@ -116,6 +119,33 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
     const IWord q = lane_word(bc, i & 63);
     const uint32_t x = q.x, y = q.y, z = q.z, aux = q.w;
     const uint32_t op = x & 0xFF, w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
+    if (op >= K_LDREG_B) {
+      // a run of same-class register loads inside the current block: the
+      // register index (aux) and the slot offset (dst) of each load come
+      // straight from the block registers; loads first, then the stores
+      const uint32_t n = (x >> 24) & 0xFF;
+      uint64_t v[kLeafRun];
+#pragma unroll
+      for (uint32_t k = 0; k < kLeafRun; ++k) {
+        if (k < n) {
+          const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)bc.w, (int)((i + k) & 63));
+          if (op == K_LDREG_D) v[k] = (stD_cur + (size_t)r * A.n_pad)[inst];
+          else if (op == K_LDREG_W) v[k] = (stW_cur + (size_t)r * A.n_pad)[inst];
+          else v[k] = stB_cur[(size_t)r * A.n_tiles + tile];
+        }
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kLeafRun; ++k) {
+        if (k < n) {
+          const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)bc.y, (int)((i + k) & 63)) & 0xFFFF;
+          if (op == K_LDREG_D) *reinterpret_cast<uint64_t*>(base + o + 8 * lane) = v[k];
+          else if (op == K_LDREG_W) *reinterpret_cast<uint32_t*>(base + o + 4 * lane) = (uint32_t)v[k];
+          else if (lane == 0) *reinterpret_cast<uint64_t*>(base + o) = v[k];
+        }
+      }
+      i += n;
+      continue;
+    }
     const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
     const uint32_t dst = y & 0xFFFF, oa = y >> 16, ob = z & 0xFFFF, oc = z >> 16;
     if (op >= I_AND && op <= I_MUL) {
@@ -125,7 +155,7 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
       ++i;
       continue;
     }
-    if (op >= K_MASK_AND) {
+    if (op >= K_MASK_AND && op <= K_MASK_MUX) {
       // every operand and the result are 64-instance masks
       const uint64_t ma = mread(base, oa), mb = mread(base, ob);
       uint64_t r;
@@ -145,12 +175,12 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
     switch (op) {
       case I_LDREG:
       case I_LDIN: {
-        // a run of up to 16 leaf loads (length in flags): every load is issued
+        // a run of up to kLeafRun leaf loads (length in flags): every load is issued
         // before any result is used, so the run costs one memory latency
         const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
-        uint64_t val[16];
+        uint64_t val[kLeafRun];
 #pragma unroll
-        for (uint32_t k = 0; k < 16; ++k) {
+        for (uint32_t k = 0; k < kLeafRun; ++k) {
           if (k < n) {
             const IWord qk = instr(i + k);
             const uint32_t xk = qk.x, auxk = qk.w;
@@ -168,7 +198,7 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
           }
         }
 #pragma unroll
-        for (uint32_t k = 0; k < 16; ++k) {
+        for (uint32_t k = 0; k < kLeafRun; ++k) {
           if (k < n) {
             const IWord qk = instr(i + k);
             const uint32_t xk = qk.x, yk = qk.y;
