@@ -42,7 +42,7 @@ static void phase(const char* what) {
 
 // leaf loads the batched kernel issues back to back before waiting: more
 // hide more memory latency, fewer keep fewer values live (LDS per wave)
-static constexpr uint32_t kLeafRun = 4;
+static constexpr uint32_t kLeafRun = 2;
 
 static inline int arity(uint8_t op) {
   switch (op) {

@@ -10,7 +10,7 @@
 namespace fsim {
 
 // longest run of leaf loads the encoder emits (issued back to back)
-static constexpr uint32_t kLeafRun = 4;
+static constexpr uint32_t kLeafRun = 2;
 
 // ------------------------------------------------------------ batched form
 //
