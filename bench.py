@@ -143,7 +143,8 @@ def bench_plain_tuned(F, g, tune, ctx, name, targets, threads, cycles, warm, see
                               cycles=500, use_cache=False)
     tune_s = time.time() - t0
     d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=best["target"])
-    sim = F.Sim(d, 1, launch=best["launch"], wg_threads=best["threads"], seed=seed)
+    sim = F.Sim(d, 1, launch=best["launch"], wg_threads=best["threads"], seed=seed,
+                stage=best.get("stage", F.STAGE_AUTO))
     gpu_s = time_sim(sim, ctx.torch_stream, cycles, warm)
     info = d.info()
     lay = sim.layout()
@@ -182,14 +183,17 @@ def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=32768,
     out = {"workload": nl.name, "registers": int(nl.n_regs), "word_ops": int(nl.n_comb_ops()),
            "memories": int(nl.n_mems), "plain": [], "batched": None}
     designs = {}
-    for target, threads in plain_cfgs:
+    for cfg in plain_cfgs:
+        target, threads = cfg[0], cfg[1]
+        stage = cfg[2] if len(cfg) > 2 else F.STAGE_AUTO
         if target not in designs:
             designs[target] = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=target)
         d = designs[target]
         info = d.info()
-        sim = F.Sim(d, 1, launch=F.LAUNCH_GRAPH, wg_threads=threads, seed=seed)
+        sim = F.Sim(d, 1, launch=F.LAUNCH_GRAPH, wg_threads=threads, seed=seed, stage=stage)
         gpu_s = time_sim(sim, ctx.torch_stream, cycles, 20)
         rec = {"processes": int(info["n_processes"]), "threads": threads,
+               "instructions_in_lds": bool(sim.layout()["staged"]),
                "value": round(cycles / gpu_s, 1), "unit": "instance-cycles/s",
                "us_per_cycle": round(gpu_s / cycles * 1e6, 2), "compile_s": round(info["compile_seconds"], 1),
                "dup_fiber": round(info["dup_fiber"], 4), "dup_process": round(info["dup_process"], 4),
@@ -280,11 +284,13 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--soc48", action="store_true",
                     help="also measure the 48-tile SoC (compiling it takes about a minute)")
-    ap.add_argument("--soc48-plain", default="8192:64,16384:64",
-                    help="plain configurations for --soc48, target:threads[,target:threads...]")
+    ap.add_argument("--soc48-plain", default="8192:64:2,16384:64:2,16384:64:1",
+                    help="plain configurations for --soc48, target:threads[:stage][,...] "
+                         "(stage 1: instructions in LDS, 2: from global memory)")
     ap.add_argument("--plain-config", default=None,
-                    help="target:threads:launch for the headline plain run, skipping the autotuner "
-                         "(launch 1 persistent, 3 graph); used for profiling runs")
+                    help="target:threads:launch[:stage] for the headline plain run, skipping the "
+                         "autotuner (launch 1 persistent, 3 graph; stage 1 LDS, 2 global); used for "
+                         "profiling runs")
     ap.add_argument("--profile-run", choices=["batched-core", "plain-core", "plain-prng"], default=None,
                     help="a short fixed run for hardware counters (per-cycle launches): batched "
                          "single-core x256 on 1024 processes, plain single-core on 2048 one-wave "
@@ -348,15 +354,17 @@ def main():
     ctx = F.Context(0)
     t0 = time.time()
     if args.plain_config:
-        tgt, thr, la = (int(v) for v in args.plain_config.split(":"))
-        best = {"target": tgt, "threads": thr, "launch": la}
+        vals = [int(v) for v in args.plain_config.split(":")]
+        best = {"target": vals[0], "threads": vals[1], "launch": vals[2],
+                "stage": vals[3] if len(vals) > 3 else F.STAGE_AUTO}
     else:
         best, _ = tune.tune_plain(ctx, nl, targets=(512, 1024, 2048, 4096), threads=(64, 256),
                                   launches=(F.LAUNCH_GRAPH,), cycles=2000, use_cache=not args.retune)
     tune_s = time.time() - t0
     d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=best["target"])
     info = d.info()
-    sim = F.Sim(d, 1, launch=best["launch"], wg_threads=best["threads"], seed=seed)
+    sim = F.Sim(d, 1, launch=best["launch"], wg_threads=best["threads"], seed=seed,
+                stage=best.get("stage", F.STAGE_AUTO))
     lay = sim.layout()
     stream = ctx.torch_stream
     for _ in range(args.warmup):
@@ -379,13 +387,14 @@ def main():
     ms_per_step = gpu_s * 1e3 / args.steps
 
     bpc, state_bytes = algorithmic_bytes_per_cycle(nl, info["n_live_ops"])
-    one_wave = lay["threads"] == 64 and lay["staged"]
+    one_wave = lay["threads"] == 64
+    suffix = "" if lay["staged"] else "_g"
     if best["launch"] == F.LAUNCH_PERSISTENT:
-        kernel = "plain_wave_persistent" if one_wave else "plain_persistent"
+        kernel = ("plain_wave_persistent" if one_wave else "plain_persistent") + suffix
         cycles_per_launch = min(args.cycles, 1 << 20)
         launch_s = gpu_s / args.steps * cycles_per_launch / args.cycles
     else:
-        kernel = "plain_wave_cycle" if one_wave else "plain_cycle"
+        kernel = ("plain_wave_cycle" if one_wave else "plain_cycle") + suffix
         cycles_per_launch = 1
         launch_s = gpu_s / total_cycles       # upper bound: includes the graph's launch gaps
     achieved = bpc * cycles_per_launch / launch_s / 1e9

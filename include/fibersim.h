@@ -191,6 +191,13 @@ int fsim_design_batched_info(fsim_design* d, uint32_t* slots_b, uint32_t* slots_
 #define FSIM_FORM_BATCHED  1   /* one lane per instance, even for one        */
 #define FSIM_FORM_PLAIN    2   /* level-parallel workgroups (one instance)   */
 
+/* Where a plain-form workgroup reads its process's instructions from. */
+#define FSIM_STAGE_AUTO    0   /* LDS copy when it fits beside the slots     */
+#define FSIM_STAGE_LDS     1   /* copied into LDS at launch (error if too big)*/
+#define FSIM_STAGE_GLOBAL  2   /* read from global memory, prefetched; LDS
+                                  then holds only the value slots, so more
+                                  workgroups are resident at once            */
+
 typedef struct fsim_sim_opts {
   uint32_t launch;          /* FSIM_LAUNCH_*; the batched form always ends a
                                cycle at a kernel boundary (PER_CYCLE/GRAPH)  */
@@ -200,6 +207,7 @@ typedef struct fsim_sim_opts {
   uint32_t grid;            /* workgroups of the persistent kernel, 0 = auto*/
   uint32_t graph_cycles;    /* cycles per captured graph (GRAPH mode)       */
   uint32_t form;            /* FSIM_FORM_*                                  */
+  uint32_t stage;           /* plain form: FSIM_STAGE_*                     */
 } fsim_sim_opts;
 
 /* Device bytes a sim needs for n_instances (state x2, memories, outputs,

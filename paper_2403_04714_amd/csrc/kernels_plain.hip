@@ -215,7 +215,12 @@ __device__ void plain_body(const PlainArgs& A) {
 // one flat sequence.  The chunk words sit in four registers (lane k of word q
 // holds chunk 64 q + k, read with v_readlane) and the first instruction of
 // the next chunk is fetched while the current chunk runs.
-template <bool PERSISTENT>
+// STAGED: the process's instructions are copied into LDS at launch and read
+// from there.  Otherwise they are read from global memory, the first
+// instruction of each chunk two chunks ahead, and the workgroup's LDS holds
+// only the value slots, so that many more workgroups are resident at once
+// (large designs) and nothing is copied per launch.
+template <bool PERSISTENT, bool STAGED>
 __device__ void plain_wave_body(const PlainArgs& A) {
   extern __shared__ uint64_t lds[];
   __shared__ int abort_flag;
@@ -226,14 +231,15 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   auto at = [slot_base](uint32_t off) -> uint64_t& { return *reinterpret_cast<uint64_t*>(slot_base + off); };
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
-  uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
+  // instruction i of the process (LDS copy or global memory)
+  const uint4* const Is = STAGED ? reinterpret_cast<const uint4*>(lds + A.slot_words) : Ig;
   // staging, eight loads in flight per lane (one memory latency per 512
   // instructions; the per-cycle launch modes stage on every launch)
   // (plain 16-byte words, not uint4: an array of the vector type is kept in
   // scratch memory by the compiler)
   const IWord* Igw = reinterpret_cast<const IWord*>(Ig);
-  IWord* Isw = reinterpret_cast<IWord*>(Is);
-  for (uint32_t base = 0; base < n_all; base += 512) {
+  IWord* Isw = reinterpret_cast<IWord*>(lds + A.slot_words);
+  for (uint32_t base = 0; STAGED && base < n_all; base += 512) {
     IWord t[8];
 #pragma unroll
     for (uint32_t q = 0; q < 8; ++q) {
@@ -304,6 +310,10 @@ __device__ void plain_wave_body(const PlainArgs& A) {
     };
     uint32_t ch = n_ch ? word(0) : 0;
     uint4 raw = first_instr(ch);
+    // unstaged: the first instruction of chunk c + 1 is already in flight
+    // while chunk c runs, and chunk c + 2's is issued
+    uint4 raw1 = make_uint4(0, 0, 0, 0);
+    if (!STAGED) raw1 = first_instr(n_ch > 1 ? word(1) : 0);
     while (c < n_ch) {
       if ((ch >> 24) == I_ALU) {
         // a run of operator chunks: operand reads, then the next chunk's
@@ -313,7 +323,13 @@ __device__ void plain_wave_body(const PlainArgs& A) {
           const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
           const Dec in = decode(raw);
           uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
-          const uint4 rn = first_instr(chn);
+          uint4 rn;
+          if (STAGED) {
+            rn = first_instr(chn);
+          } else {
+            rn = raw1;
+            raw1 = first_instr(c + 2 < n_ch ? word(c + 2) : 0);
+          }
           asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
           const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
           const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
@@ -328,7 +344,13 @@ __device__ void plain_wave_body(const PlainArgs& A) {
       }
       const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 0xFF) + 1, op = ch >> 24;
       const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
-      const uint4 rn = first_instr(chn);
+      uint4 rn;
+      if (STAGED) {
+        rn = first_instr(chn);
+      } else {
+        rn = raw1;
+        raw1 = first_instr(c + 2 < n_ch ? word(c + 2) : 0);
+      }
       if (op == I_MEMRD) {
         if (lane < cnt) {
           const Dec in = decode(raw);
@@ -411,8 +433,10 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   }
 }
 
-__global__ void __launch_bounds__(64) plain_wave_persistent(PlainArgs A) { plain_wave_body<true>(A); }
-__global__ void __launch_bounds__(64) plain_wave_cycle(PlainArgs A) { plain_wave_body<false>(A); }
+__global__ void __launch_bounds__(64) plain_wave_persistent(PlainArgs A) { plain_wave_body<true, true>(A); }
+__global__ void __launch_bounds__(64) plain_wave_cycle(PlainArgs A) { plain_wave_body<false, true>(A); }
+__global__ void __launch_bounds__(64) plain_wave_persistent_g(PlainArgs A) { plain_wave_body<true, false>(A); }
+__global__ void __launch_bounds__(64) plain_wave_cycle_g(PlainArgs A) { plain_wave_body<false, false>(A); }
 
 __global__ void __launch_bounds__(1024) plain_persistent(PlainArgs A) { plain_body<true, true>(A); }
 __global__ void __launch_bounds__(1024) plain_cycle(PlainArgs A) { plain_body<false, true>(A); }
@@ -450,10 +474,12 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t
   if (a.single_wave) {
     if (persistent) {
       void* args[] = {const_cast<PlainArgs*>(&a)};
-      return hipLaunchCooperativeKernel((const void*)plain_wave_persistent, dim3(G), dim3(64), args,
-                                        (unsigned)lds_bytes, s);
+      return hipLaunchCooperativeKernel(a.stage_instr ? (const void*)plain_wave_persistent
+                                                      : (const void*)plain_wave_persistent_g,
+                                        dim3(G), dim3(64), args, (unsigned)lds_bytes, s);
     }
-    hipLaunchKernelGGL(plain_wave_cycle, dim3(G), dim3(64), lds_bytes, s, a);
+    if (a.stage_instr) hipLaunchKernelGGL(plain_wave_cycle, dim3(G), dim3(64), lds_bytes, s, a);
+    else hipLaunchKernelGGL(plain_wave_cycle_g, dim3(G), dim3(64), lds_bytes, s, a);
     return hipGetLastError();
   }
   if (persistent) {
@@ -469,7 +495,9 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t
 hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged,
                            bool single_wave) {
   if (single_wave)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, plain_wave_persistent, 64, lds_bytes);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
+                                                        staged ? plain_wave_persistent : plain_wave_persistent_g,
+                                                        64, lds_bytes);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, staged ? plain_persistent : plain_persistent_g,
                                                       (int)threads, lds_bytes);
 }

@@ -407,15 +407,22 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
   const size_t lds_limit = d->ctx->lds_bytes - kStaticLds;
   // slots, then (when they fit) the process's instructions, then the level table
   const size_t lvl_bytes = ((size_t)d->max_lvls + 1) * 4 + (size_t)d->max_chunks * 4;
+  if (o.stage > FSIM_STAGE_GLOBAL) return fail(FSIM_E_ARG, "unknown stage mode");
   size_t lds = (size_t)d->slot_words * 8 + lvl_bytes;
-  if (lds + (size_t)d->max_proc_instr * sizeof(fsim::Instr) <= lds_limit) {
+  const bool fits = lds + (size_t)d->max_proc_instr * sizeof(fsim::Instr) <= lds_limit;
+  if (o.stage == FSIM_STAGE_LDS && !fits)
+    return fail(FSIM_E_CAPACITY, "plain form: a process's instructions do not fit in LDS beside its slots");
+  if (fits && o.stage != FSIM_STAGE_GLOBAL) {
     s->stage_instr = true;
     lds += (size_t)d->max_proc_instr * sizeof(fsim::Instr);
   }
   if (lds > lds_limit) return fail(FSIM_E_CAPACITY, "process does not fit in LDS");
+  // one wave per process: the flat chunk loop (chunk words held in registers);
+  // its LDS holds the slots and, when staged, the instructions
+  s->single_wave = s->threads == 64 && d->max_chunks <= 256;
+  if (s->single_wave)
+    lds = (size_t)d->slot_words * 8 + (s->stage_instr ? (size_t)d->max_proc_instr * sizeof(fsim::Instr) : 0);
   s->lds_bytes = lds;
-  // one wave per process: the flat chunk loop (chunk words held in registers)
-  s->single_wave = s->threads == 64 && s->stage_instr && d->max_chunks <= 256;
   if (s->launch == FSIM_LAUNCH_PERSISTENT) {
     int b = 0;
     HIP_TRY(fsim::plain_occupancy(&b, s->threads, lds, s->stage_instr, s->single_wave));

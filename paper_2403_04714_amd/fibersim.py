@@ -21,6 +21,7 @@ E_ARG, E_NETLIST, E_COMB_LOOP, E_UNSUPPORTED, E_CAPACITY, E_DEVICE, E_STATE, E_B
 PACK_SLB, PACK_FIBERS, PACK_SINGLE = 0, 1, 2
 LAUNCH_AUTO, LAUNCH_PERSISTENT, LAUNCH_PER_CYCLE, LAUNCH_GRAPH = 0, 1, 2, 3
 FORM_AUTO, FORM_BATCHED, FORM_PLAIN = 0, 1, 2
+STAGE_AUTO, STAGE_LDS, STAGE_GLOBAL = 0, 1, 2
 
 
 class FsimError(RuntimeError):
@@ -70,7 +71,7 @@ class DesignInfo(C.Structure):
 
 class SimOpts(C.Structure):
     _fields_ = [("launch", C.c_uint32), ("wg_threads", C.c_uint32), ("grid", C.c_uint32),
-                ("graph_cycles", C.c_uint32), ("form", C.c_uint32)]
+                ("graph_cycles", C.c_uint32), ("form", C.c_uint32), ("stage", C.c_uint32)]
 
 
 # every symbol include/fibersim.h declares, with its signature
@@ -276,7 +277,7 @@ class Sim:
 
     def __init__(self, design: Design, n_instances: int = 1, launch=LAUNCH_AUTO,
                  wg_threads=0, grid=0, graph_cycles=0, seed=None, use_torch_workspace=True,
-                 form=FORM_AUTO):
+                 form=FORM_AUTO, stage=STAGE_AUTO):
         import torch
         self.design = design
         self.n_instances = n_instances
@@ -289,7 +290,7 @@ class Sim:
             base = self._ws.data_ptr()
             ws_ptr = (base + 255) // 256 * 256
             ws_bytes = fp.value
-        o = SimOpts(launch, wg_threads, grid, graph_cycles, form)
+        o = SimOpts(launch, wg_threads, grid, graph_cycles, form, stage)
         h = C.c_void_p()
         _check(lib().fsim_sim_create(design._h, n_instances, ws_ptr, ws_bytes, C.byref(o), C.byref(h)),
                "fsim_sim_create")

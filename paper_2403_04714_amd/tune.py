@@ -51,10 +51,10 @@ def _save_cache(c):
     os.replace(tmp, CACHE)
 
 
-def time_plain(ctx, design, launch, threads, cycles, seed=0x5EED0000, reps=2):
+def time_plain(ctx, design, launch, threads, cycles, seed=0x5EED0000, reps=2, stage=F.STAGE_AUTO):
     """Seconds per simulated cycle (best of reps), torch events on ctx's stream."""
     import torch
-    s = F.Sim(design, 1, launch=launch, wg_threads=threads, seed=seed)
+    s = F.Sim(design, 1, launch=launch, wg_threads=threads, seed=seed, stage=stage)
     s.step(min(200, cycles))
     s.sync()
     best = float("inf")
@@ -88,14 +88,16 @@ def tune_plain(ctx, nl, targets=(16, 32, 64, 128, 256), threads=(256, 512, 1024)
                 print(f"tune: target {t}: {e}", flush=True)
             continue
         for th in threads:
-            for la in launches:
+            # one-wave processes: instructions staged in LDS or read from global memory
+            stages = (F.STAGE_LDS, F.STAGE_GLOBAL) if th == 64 else (F.STAGE_AUTO,)
+            for la, st in [(la, st) for la in launches for st in stages]:
                 try:
-                    spc = time_plain(ctx, d, la, th, cycles)
+                    spc = time_plain(ctx, d, la, th, cycles, stage=st)
                 except F.FsimError as e:
                     if verbose:
-                        print(f"tune: target {t} threads {th} launch {la}: {e}", flush=True)
+                        print(f"tune: target {t} threads {th} launch {la} stage {st}: {e}", flush=True)
                     continue
-                rec = dict(target=t, processes=d.info()["n_processes"], threads=th, launch=la,
+                rec = dict(target=t, processes=d.info()["n_processes"], threads=th, launch=la, stage=st,
                            s_per_cycle=spc)
                 trials.append(rec)
                 if verbose:

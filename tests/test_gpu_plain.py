@@ -31,11 +31,12 @@ def say(*a):
     print(*a, flush=True)
 
 
-def run_both(F, ctx, nl, cycles, pack, target=0, launch=None, threads=0, seed=SEED, chunks=(None,)):
+def run_both(F, ctx, nl, cycles, pack, target=0, launch=None, threads=0, seed=SEED, chunks=(None,), stage=0):
     launch = F.LAUNCH_PERSISTENT if launch is None else launch
-    say(f"case {nl.name}: pack={pack} target={target} launch={launch} threads={threads} cycles={cycles}")
+    say(f"case {nl.name}: pack={pack} target={target} launch={launch} threads={threads} stage={stage} "
+        f"cycles={cycles}")
     d = F.Design(ctx, nl, pack=pack, target_processes=target)
-    s = F.Sim(d, 1, launch=launch, wg_threads=threads, seed=seed)
+    s = F.Sim(d, 1, launch=launch, wg_threads=threads, seed=seed, stage=stage)
     s.enable_digest(cycles)
     done = 0
     for c in chunks:
@@ -122,10 +123,23 @@ def test_core_full_size_2000_cycles(F, ctx):
     run_both(F, ctx, g.workload("core"), 2000, 0, 256)
 
 
+@pytest.mark.parametrize("launch", [1, 2, 3])
+def test_single_wave_instructions_from_global(F, ctx, launch):
+    """The one-wave kernel reading its instructions from global memory (two
+    chunks ahead) instead of an LDS copy."""
+    run_both(F, ctx, g.gen_tiny(7), 600, 0, 9, launch=launch, threads=64, chunks=(1, 130, None), stage=2)
+
+
+@pytest.mark.parametrize("target", [24, 200])
+def test_small_core_instructions_from_global(F, ctx, target):
+    run_both(F, ctx, small_core(), 300, 0, target, launch=3, threads=64, stage=2)
+
+
 def test_core_full_size_single_wave(F, ctx):
     """The single-core workload at 1024 one-wave processes (the flat chunk
     loop), 1,000 cycles compared per cycle."""
     run_both(F, ctx, g.workload("core"), 1000, 0, 1024, launch=3, threads=64)
+    run_both(F, ctx, g.workload("core"), 500, 0, 2048, launch=3, threads=64, stage=2)
 
 
 def _pairs_inputs(n=4):
