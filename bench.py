@@ -274,6 +274,74 @@ def study_prng(F, g, ctx, cycles=2000, warm=200):
     return rows
 
 
+def trace_split(sim, cycles=24):
+    """Phase timestamps of `cycles` cycles: cycle period, slowest and median
+    workgroup compute span (start to commit) and the level-0 span (register
+    gathers), medians over cycles, in us."""
+    import numpy as np
+    sim.enable_trace(cycles)
+    sim.step(cycles)
+    tr = sim.trace().astype(np.int64)
+    stride = tr.shape[2]
+    period = np.diff(tr[:, :, 0].min(axis=1)) * 10 / 1000
+    comp = (tr[:, :, stride - 2] - tr[:, :, 0]) * 10 / 1000
+    lvl0 = (tr[:, :, 1] - tr[:, :, 0]) * 10 / 1000
+    return {"period_us": round(float(np.median(period)), 3),
+            "compute_max_us": round(float(np.median(comp[1:].max(axis=1))), 3),
+            "compute_median_us": round(float(np.median(comp[1:])), 3),
+            "gather_us": round(float(np.median(lvl0[1:])), 3)}
+
+
+def study_scaling(F, g, tune, ctx, seed):
+    """The scaling study of Sec. 6.3 on this GPU.  Strong scaling: the
+    single-core design at a growing number of one-wave processes, split into
+    compute (slowest workgroup), register gathers (the exchange: level 0) and
+    the rest of the cycle (launch gap, i.e. synchronization).  Weak scaling:
+    meshes of 1 to 48 core tiles at a fixed number of processes per tile."""
+    strong = []
+    nl = g.workload("core")
+    for P in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=P)
+        info = d.info()
+        best = None
+        for st in (F.STAGE_LDS, F.STAGE_GLOBAL):
+            try:
+                sim = F.Sim(d, 1, launch=F.LAUNCH_GRAPH, wg_threads=64, seed=seed, stage=st)
+            except F.FsimError:
+                continue
+            us = time_sim(sim, ctx.torch_stream, 2000, 200) / 2000 * 1e6
+            if best is None or us < best[0]:
+                best = (us, st, sim)
+            else:
+                del sim
+        us, st, sim = best
+        rec = {"processes": int(info["n_processes"]), "us_per_cycle": round(us, 2),
+               "rate_khz": round(1e3 / us, 2), "instructions_in_lds": st == F.STAGE_LDS,
+               "dup_process": round(info["dup_process"], 4), "max_process_cost": int(info["max_process_cost"])}
+        rec.update(trace_split(sim))
+        strong.append(rec)
+        print(json.dumps({"strong": rec}), file=sys.stderr, flush=True)
+        del sim, d
+    weak = []
+    core = g.gen_core(seed=1)
+    for rows, cols in ((1, 1), (1, 2), (2, 2), (2, 4), (4, 4), (8, 6)):
+        nlw = g.gen_soc(rows, cols, core, mesh_seed=2) if rows * cols > 1 else core
+        t0 = time.time()
+        d = F.Design(ctx, nlw, pack=F.PACK_SLB, target_processes=512 * rows * cols)
+        compile_s = time.time() - t0
+        info = d.info()
+        sim = F.Sim(d, 1, launch=F.LAUNCH_GRAPH, wg_threads=64, seed=seed, stage=F.STAGE_GLOBAL)
+        us = time_sim(sim, ctx.torch_stream, 500, 50) / 500 * 1e6
+        rec = {"tiles": rows * cols, "word_ops": int(nlw.n_comb_ops()), "processes": int(info["n_processes"]),
+               "us_per_cycle": round(us, 2), "rate_khz": round(1e3 / us, 2),
+               "dup_process": round(info["dup_process"], 4), "compile_s": round(compile_s, 1)}
+        rec.update(trace_split(sim))
+        weak.append(rec)
+        print(json.dumps({"weak": rec}), file=sys.stderr, flush=True)
+        del sim, d
+    return {"strong": strong, "weak": weak}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,8 +365,9 @@ def main():
                          "processes, or 64 one-wave processes of 7 independent PRNG fibers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of known size (the reference for HBM byte counters)")
-    ap.add_argument("--study", choices=["prng"], default=None,
-                    help="run a study instead of the benchmark (prng: the barrier sweep of Sec. 4.1)")
+    ap.add_argument("--study", choices=["prng", "scaling"], default=None,
+                    help="run a study instead of the benchmark (prng: the barrier sweep of Sec. 4.1; "
+                         "scaling: strong and weak scaling of Sec. 6.3)")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the batched, 8-tile plain and served sections")
     args = ap.parse_args()
@@ -345,6 +414,11 @@ def main():
     if args.study == "prng":
         ctx = F.Context(0)
         print(json.dumps({"study": "prng barrier sweep (Sec. 4.1)", "rows": study_prng(F, g, ctx)}), flush=True)
+        return
+    if args.study == "scaling":
+        ctx = F.Context(0)
+        print(json.dumps({"study": "scaling (Sec. 6.3)",
+                          **study_scaling(F, g, tune, ctx, g.STIM_SEED_BASE)}), flush=True)
         return
 
     seed = g.STIM_SEED_BASE

@@ -361,25 +361,27 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         }
       } else {
         // leaf loads and sink stores, up to four per lane, loads all issued
-        // before the first is used
-        Dec in[4];
+        // before the first is used (the raw instructions are kept, not their
+        // decoded fields, to spare registers)
+        uint4 rq[4];
         uint64_t v[4];
 #pragma unroll
         for (uint32_t q = 0; q < 4; ++q) {
           const uint32_t e = lane + 64 * q;
           if (e < cnt) {
-            in[q] = decode(q == 0 ? raw : Is[start + e]);
+            rq[q] = q == 0 ? raw : Is[start + e];
+            const Dec in = decode(rq[q]);
             if (op == I_LDREG) {
-              v[q] = cur[in[q].aux];
+              v[q] = cur[in.aux];
             } else if (op == I_LDIN) {
               if (A.in_vals) {
                 if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v[q] = 0; }
-                else v[q] = A.in_vals[(cyc - A.in_first) * A.I + in[q].aux];
+                else v[q] = A.in_vals[(cyc - A.in_first) * A.I + in.aux];
               } else {
-                v[q] = hmix(A.in_keys[in[q].aux] ^ cyc);
+                v[q] = hmix(A.in_keys[in.aux] ^ cyc);
               }
             } else {
-              v[q] = at(in[q].a);
+              v[q] = at(in.a);
             }
           }
         }
@@ -387,14 +389,15 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         for (uint32_t q = 0; q < 4; ++q) {
           const uint32_t e = lane + 64 * q;
           if (e < cnt) {
-            const uint64_t x = v[q] & wmask(in[q].w);
+            const Dec in = decode(rq[q]);
+            const uint64_t x = v[q] & wmask(in.w);
             if (op == I_LDREG || op == I_LDIN) {
-              at(in[q].dst) = x;
+              at(in.dst) = x;
             } else if (op == I_STREG) {
-              nxt[in[q].aux] = x;
-              if (A.digest_part) dacc += hmix((uint64_t)in[q].aux ^ hmix(x));
+              nxt[in.aux] = x;
+              if (A.digest_part) dacc += hmix((uint64_t)in.aux ^ hmix(x));
             } else {
-              A.outputs[in[q].aux] = x;
+              A.outputs[in.aux] = x;
             }
           }
         }
