@@ -241,6 +241,34 @@ def bench_served(F, g, ctx, n_jobs, lam, inst_hi, cyc_lo, cyc_hi):
             "quanta": int(st["quanta"]), "device_busy_s": round(st["busy_seconds"], 3)}
 
 
+def study_serving(F, g, ctx, n_jobs=24, lams=(1.0, 2.0, 4.0, 8.0, 16.0, 64.0)):
+    """The serving mix swept over the mean arrival rate: p50/p99 of (done -
+    arrival) and aggregate instance-cycles/s per rate, one fresh server per
+    rate over the same compiled designs and the same job draw."""
+    from paper_2403_04714_amd import serve
+    designs = [F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=4096),
+               F.Design(ctx, g.workload("soc8"), pack=F.PACK_SLB, target_processes=16384)]
+    jobs = serve.draw_jobs(n_jobs, designs, inst_lo=1, inst_hi=1024, cyc_lo=100, cyc_hi=2000)
+    work = sum(j["instances"] * j["cycles"] for j in jobs)
+    rows = []
+    for lam in lams:
+        srv = F.Server(ctx, 64 << 30, quantum_cycles=256)
+        recs, summ = serve.run(srv, designs, jobs, serve.arrivals(n_jobs, lam=lam), timeout_s=600)
+        st = srv.stats()
+        srv.close()
+        waits = sorted(r["queue_wait"] for r in recs if r["queue_wait"] is not None)
+        rows.append({"arrival_rate_per_s": lam, "offered_instance_cycles_per_s": round(work * lam / n_jobs, 1),
+                     "completed": summ["completed"], "p50_s": round(summ["p50_s"], 4),
+                     "p99_s": round(summ["p99_s"], 4), "mean_s": round(summ["mean_s"], 4),
+                     "max_queue_wait_s": round(waits[-1], 4) if waits else None,
+                     "wall_s": round(summ["wall_s"], 3), "instance_cycles_per_s": round(summ["instance_cycles_per_s"], 1),
+                     "device_busy_s": round(st["busy_seconds"], 3)})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"jobs": n_jobs, "total_work_instance_cycles": int(work),
+            "designs": ["core (4096 processes)", "soc8 (16384 processes)"],
+            "instances": "log-uniform [1, 1024]", "cycles": "log-uniform [100, 2000]", "rows": rows}
+
+
 def study_prng(F, g, ctx, cycles=2000, warm=200):
     """The synchronization experiment of Sec. 4.1 on this GPU: independent
     xorshift32 fibers (no communication), a fixed number of fibers per
@@ -365,9 +393,10 @@ def main():
                          "processes, or 64 one-wave processes of 7 independent PRNG fibers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of known size (the reference for HBM byte counters)")
-    ap.add_argument("--study", choices=["prng", "scaling"], default=None,
+    ap.add_argument("--study", choices=["prng", "scaling", "serving"], default=None,
                     help="run a study instead of the benchmark (prng: the barrier sweep of Sec. 4.1; "
-                         "scaling: strong and weak scaling of Sec. 6.3)")
+                         "scaling: strong and weak scaling of Sec. 6.3; serving: the served mix "
+                         "swept over the arrival rate)")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the batched, 8-tile plain and served sections")
     args = ap.parse_args()
@@ -414,6 +443,10 @@ def main():
     if args.study == "prng":
         ctx = F.Context(0)
         print(json.dumps({"study": "prng barrier sweep (Sec. 4.1)", "rows": study_prng(F, g, ctx)}), flush=True)
+        return
+    if args.study == "serving":
+        ctx = F.Context(0)
+        print(json.dumps({"study": "serving sweep", **study_serving(F, g, ctx)}), flush=True)
         return
     if args.study == "scaling":
         ctx = F.Context(0)

@@ -10,6 +10,17 @@
 // next copies never alias within a cycle, so one barrier per cycle suffices
 // where the IPU needs two (Sec. 4.1).
 //
+// Two kernels implement it.  plain_wave_* gives each process one 64-thread
+// wave: a wave's LDS operations complete in order, so the levels need no
+// barrier and the chunks of all levels run as one flat loop.  Its
+// instructions are either staged in LDS at launch or read from global memory
+// a few chunks ahead (then LDS holds only the value slots, and more
+// workgroups are resident at once).  plain_* runs one process on a
+// multi-wave workgroup, with a workgroup barrier between levels.  The
+// kernel boundary of per-cycle launches (captured in a hipGraph) serves as
+// the grid barrier.  It is cheaper on this chip than the flag barrier of
+// the persistent launch once there are more than a few dozen workgroups.
+//
 // The barrier (Sec. 4.1 measures the same cost on the IPU and on x64) uses
 // one epoch flag per workgroup: arrivals are plain stores to distinct words
 // and every workgroup polls all flags, so no read-modify-write serialises
