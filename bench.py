@@ -41,12 +41,16 @@ def algorithmic_bytes_per_cycle(nl, n_live_ops, n_instances=1):
 
 def kernel_source_hash():
     """Hash of the plain-form device code (the kernel file and the helpers it
-    shares with the batched form)."""
+    shares with the batched form), comments and blank lines left out."""
     import hashlib
+    import re
     h = hashlib.sha1()
     for name in ("kernels_plain.hip", "device_common.h"):
-        with open(os.path.join(ROOT, "paper_2403_04714_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2403_04714_amd", "csrc", name)) as f:
+            for line in f:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:12]
 
 
