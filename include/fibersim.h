@@ -238,7 +238,10 @@ int fsim_sync(fsim_sim* s);
 uint64_t fsim_cycle(const fsim_sim* s);
 
 /* State access (each synchronises).  out/in hold n_regs, n_outputs or the
- * memory's depth values; outputs are those of the last simulated cycle. */
+ * memory's depth values; outputs are those of the last simulated cycle.
+ * In the batched form one instance's values are gathered (or scattered) on
+ * the device through a staging buffer that the sim allocates on first use,
+ * sized for the largest column read so far, and frees with the sim. */
 int fsim_read_regs(fsim_sim* s, uint32_t inst, uint64_t* out);
 int fsim_write_regs(fsim_sim* s, uint32_t inst, const uint64_t* in);
 int fsim_read_outputs(fsim_sim* s, uint32_t inst, uint64_t* out);

@@ -87,5 +87,9 @@ hipError_t launch_digest_reduce(const uint64_t* part, uint32_t G, uint64_t n, ui
 hipError_t launch_stim_keys(uint64_t* keys, uint64_t seed_base, uint32_t n_inst, uint32_t I,
                             hipStream_t s);
 hipError_t launch_add_u64(uint64_t* p, uint64_t v, hipStream_t s);
+// column `col` of a row-major [rows][pitch] table of 4- or 8-byte values
+// copied into the contiguous vector `vec` (to_table false) or from it (true)
+hipError_t launch_column_copy(void* table, uint32_t elem, uint64_t pitch, uint64_t col, uint64_t rows,
+                              void* vec, bool to_table, hipStream_t s);
 
 }  // namespace fsim

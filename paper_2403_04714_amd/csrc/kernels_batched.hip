@@ -297,6 +297,20 @@ __global__ void __launch_bounds__(64) batched_multi(const BatchArgs* __restrict_
   batched_body(A, blockIdx.x - wg_start[j], cycle_base[j] + tick, reinterpret_cast<char*>(lds));
 }
 
+// One instance's column of an instance-minor [rows][pitch] table, gathered
+// into a contiguous [rows] vector or scattered back from one, so that a
+// readback or write of one instance's registers, outputs or memory is one
+// contiguous host copy rather than a strided copy of `rows` tiny rows.
+template <typename T>
+__global__ __launch_bounds__(256) void column_copy(T* table, uint64_t pitch, uint64_t col, uint64_t rows,
+                                                  T* vec, int to_table) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += stride) {
+    if (to_table) table[r * pitch + col] = vec[r];
+    else vec[r] = table[r * pitch + col];
+  }
+}
+
 }  // namespace fsim
 
 // ---------------------------------------------------------------- launches
@@ -314,6 +328,20 @@ hipError_t launch_batched_multi(const BatchArgs* jobs, const uint32_t* wg_start,
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL(batched_multi, dim3(grid), dim3(64), lds_bytes, s, jobs, wg_start, cycle_base, ticks,
                      n_jobs, tick);
+  return hipGetLastError();
+}
+
+hipError_t launch_column_copy(void* table, uint32_t elem, uint64_t pitch, uint64_t col, uint64_t rows,
+                              void* vec, bool to_table, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  if ((elem != 4 && elem != 8) || col >= pitch) return hipErrorInvalidValue;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((rows + 255) / 256, 4096);
+  if (elem == 8)
+    hipLaunchKernelGGL(column_copy<uint64_t>, dim3(grid), dim3(256), 0, s, static_cast<uint64_t*>(table),
+                       pitch, col, rows, static_cast<uint64_t*>(vec), (int)to_table);
+  else
+    hipLaunchKernelGGL(column_copy<uint32_t>, dim3(grid), dim3(256), 0, s, static_cast<uint32_t*>(table),
+                       pitch, col, rows, static_cast<uint32_t*>(vec), (int)to_table);
   return hipGetLastError();
 }
 

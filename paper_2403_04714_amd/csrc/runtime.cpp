@@ -672,17 +672,36 @@ static int check_inst(fsim_sim* s, uint32_t inst) {
   return fsim_sync(s);
 }
 
-// batched layout helpers: one instance's column of a [rows][pitch] array
-static int col_read(const void* base, size_t elem, size_t pitch_elems, size_t col, size_t rows, void* out) {
-  if (!rows) return FSIM_OK;
-  HIP_TRY(hipMemcpy2D(out, elem, (const char*)base + col * elem, pitch_elems * elem, elem, rows,
-                      hipMemcpyDeviceToHost));
+// batched layout helpers: one instance's column of a [rows][pitch] array,
+// gathered or scattered on the device through the sim's staging buffer, so
+// the host copy is one contiguous transfer
+static int col_xfer(fsim_sim* s, size_t bytes) {
+  if (s->xfer.n < bytes) HIP_TRY(s->xfer.alloc(bytes));
   return FSIM_OK;
 }
-static int col_write(void* base, size_t elem, size_t pitch_elems, size_t col, size_t rows, const void* in) {
+static int col_read(fsim_sim* s, const void* base, size_t elem, size_t pitch_elems, size_t col, size_t rows,
+                    void* out) {
   if (!rows) return FSIM_OK;
-  HIP_TRY(hipMemcpy2D((char*)base + col * elem, pitch_elems * elem, in, elem, elem, rows,
-                      hipMemcpyHostToDevice));
+  int rc = col_xfer(s, rows * elem);
+  if (rc) return rc;
+  const hipStream_t st = s->d->ctx->stream;
+  HIP_TRY(hipSetDevice(s->d->ctx->device));
+  HIP_TRY(fsim::launch_column_copy(const_cast<void*>(base), (uint32_t)elem, pitch_elems, col, rows, s->xfer.p,
+                                   false, st));
+  HIP_TRY(hipMemcpyAsync(out, s->xfer.p, rows * elem, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return FSIM_OK;
+}
+static int col_write(fsim_sim* s, void* base, size_t elem, size_t pitch_elems, size_t col, size_t rows,
+                     const void* in) {
+  if (!rows) return FSIM_OK;
+  int rc = col_xfer(s, rows * elem);
+  if (rc) return rc;
+  const hipStream_t st = s->d->ctx->stream;
+  HIP_TRY(hipSetDevice(s->d->ctx->device));
+  HIP_TRY(hipMemcpyAsync(s->xfer.p, in, rows * elem, hipMemcpyHostToDevice, st));
+  HIP_TRY(fsim::launch_column_copy(base, (uint32_t)elem, pitch_elems, col, rows, s->xfer.p, true, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return FSIM_OK;
 }
 
@@ -696,9 +715,9 @@ static int batched_regs_read(fsim_sim* s, uint32_t inst, BatchedRegs& R) {
   const size_t cur = s->cycle & 1, T = s->n_tiles, NP = s->n_pad;
   R.b.assign(D.reg_count[0], 0); R.w.assign(D.reg_count[1], 0); R.d.assign(D.reg_count[2], 0);
   int rc;
-  if ((rc = col_read(s->stB + cur * D.reg_count[0] * T, 8, T, inst / 64, D.reg_count[0], R.b.data()))) return rc;
-  if ((rc = col_read(s->stW + cur * D.reg_count[1] * NP, 4, NP, inst, D.reg_count[1], R.w.data()))) return rc;
-  if ((rc = col_read(s->stD + cur * D.reg_count[2] * NP, 8, NP, inst, D.reg_count[2], R.d.data()))) return rc;
+  if ((rc = col_read(s, s->stB + cur * D.reg_count[0] * T, 8, T, inst / 64, D.reg_count[0], R.b.data()))) return rc;
+  if ((rc = col_read(s, s->stW + cur * D.reg_count[1] * NP, 4, NP, inst, D.reg_count[1], R.w.data()))) return rc;
+  if ((rc = col_read(s, s->stD + cur * D.reg_count[2] * NP, 8, NP, inst, D.reg_count[2], R.d.data()))) return rc;
   return FSIM_OK;
 }
 
@@ -741,9 +760,9 @@ extern "C" int fsim_write_regs(fsim_sim* s, uint32_t inst, const uint64_t* in) {
     else B.d[i] = v[r];
   }
   const size_t cur = s->cycle & 1, T = s->n_tiles, NP = s->n_pad;
-  if ((rc = col_write(s->stB + cur * d.reg_count[0] * T, 8, T, inst / 64, d.reg_count[0], B.b.data()))) return rc;
-  if ((rc = col_write(s->stW + cur * d.reg_count[1] * NP, 4, NP, inst, d.reg_count[1], B.w.data()))) return rc;
-  if ((rc = col_write(s->stD + cur * d.reg_count[2] * NP, 8, NP, inst, d.reg_count[2], B.d.data()))) return rc;
+  if ((rc = col_write(s, s->stB + cur * d.reg_count[0] * T, 8, T, inst / 64, d.reg_count[0], B.b.data()))) return rc;
+  if ((rc = col_write(s, s->stW + cur * d.reg_count[1] * NP, 4, NP, inst, d.reg_count[1], B.w.data()))) return rc;
+  if ((rc = col_write(s, s->stD + cur * d.reg_count[2] * NP, 8, NP, inst, d.reg_count[2], B.d.data()))) return rc;
   return FSIM_OK;
 }
 
@@ -756,7 +775,7 @@ extern "C" int fsim_read_outputs(fsim_sim* s, uint32_t inst, uint64_t* out) {
     if (O) HIP_TRY(hipMemcpy(out, s->outputs, (size_t)O * 8, hipMemcpyDeviceToHost));
     return FSIM_OK;
   }
-  return col_read(s->outputs, 8, s->n_pad, inst, O, out);
+  return col_read(s, s->outputs, 8, s->n_pad, inst, O, out);
 }
 
 extern "C" int fsim_read_mem(fsim_sim* s, uint32_t inst, uint32_t m, uint64_t* out) {
@@ -769,7 +788,7 @@ extern "C" int fsim_read_mem(fsim_sim* s, uint32_t inst, uint32_t m, uint64_t* o
     HIP_TRY(hipMemcpy(out, s->mem + d.mem_off[m], (size_t)d.mem_depth[m] * 8, hipMemcpyDeviceToHost));
     return FSIM_OK;
   }
-  return col_read(s->mem + d.mem_off[m] * s->n_pad, 8, s->n_pad, inst, d.mem_depth[m], out);
+  return col_read(s, s->mem + d.mem_off[m] * s->n_pad, 8, s->n_pad, inst, d.mem_depth[m], out);
 }
 
 extern "C" int fsim_write_mem(fsim_sim* s, uint32_t inst, uint32_t m, const uint64_t* in) {
@@ -784,7 +803,7 @@ extern "C" int fsim_write_mem(fsim_sim* s, uint32_t inst, uint32_t m, const uint
     HIP_TRY(hipMemcpy(s->mem + d.mem_off[m], v.data(), v.size() * 8, hipMemcpyHostToDevice));
     return FSIM_OK;
   }
-  return col_write(s->mem + d.mem_off[m] * s->n_pad, 8, s->n_pad, inst, d.mem_depth[m], v.data());
+  return col_write(s, s->mem + d.mem_off[m] * s->n_pad, 8, s->n_pad, inst, d.mem_depth[m], v.data());
 }
 
 extern "C" int fsim_set_cycle(fsim_sim* s, uint64_t cycle) {

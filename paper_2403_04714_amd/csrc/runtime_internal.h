@@ -95,6 +95,8 @@ struct fsim_sim {
   uint64_t* dig_out = nullptr;
   uint64_t dig_first = 0, dig_max = 0;
   fsim::DevBuf dig_part;
+  // staging for one instance's column in the batched layout (readback, writes)
+  fsim::DevBuf xfer;
   // phase timestamps
   uint64_t* trace = nullptr;
   uint64_t trace_first = 0, trace_max = 0;

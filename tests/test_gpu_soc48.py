@@ -1,18 +1,22 @@
 """The 48-tile SoC (8 x 6 mesh, about 9.4M operators, 960k registers, 96
 memories of 4096 x 64) at full size on the GPU against the oracle: the plain
 form with one instance and the batched form with 64 instances, every cycle's
-digest and the complete final state, over a short run (the oracle needs about
-a tenth of a second per cycle at this size).  Compilation alone takes about a
-minute on the host."""
+digest, registers and outputs of every instance, and every memory of a fixed
+sample of instances, over a short run (the oracle needs about a tenth of a
+second per cycle at this size; instances run in host threads).  Compilation
+alone takes about a minute on the host."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2403_04714_amd import netgen as g
 
+from oracle_pool import run_instances
+
 pytestmark = pytest.mark.gpu
 
 SEED = g.STIM_SEED_BASE
+SAMPLE = (0, 31, 63)
 
 
 @pytest.fixture(scope="module")
@@ -59,9 +63,13 @@ def test_soc48_batched_64(F, soc48):
     s.enable_digest(cycles)
     s.step(cycles)
     dg = s.digests()
-    for i in (0, 63):
-        ref = O.Sim(nl, seed=SEED + i)
-        rd = ref.step(cycles, digests=True)
+    print("case soc48: oracle, 64 instances", flush=True)
+    refs = run_instances(nl, [SEED + i for i in range(64)], cycles)
+    for i, (rd, rr, ro, _) in enumerate(refs):
         assert np.array_equal(dg[:, i], rd), f"instance {i}"
-        assert np.array_equal(s.regs(i), ref.regs()), f"instance {i} registers"
-        assert np.array_equal(s.mem(95, i), ref.mem(95)), f"instance {i} memory 95"
+        assert np.array_equal(s.regs(i), rr), f"instance {i} registers"
+        assert np.array_equal(s.outputs(i), ro), f"instance {i} outputs"
+    refs = run_instances(nl, [SEED + i for i in SAMPLE], cycles, mems=range(nl.n_mems))
+    for i, (_, _, _, rm) in zip(SAMPLE, refs):
+        for m, v in rm.items():
+            assert np.array_equal(s.mem(m, i), v), f"instance {i} memory {m}"
