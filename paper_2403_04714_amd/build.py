@@ -31,7 +31,11 @@ def build(verbose: bool = False) -> str:
         cmd = ["hipcc", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
                "-packed-fp32-ops", *common, "-c", src, "-o", obj]
         if src.endswith(".hip"):
+            # Uniform branches (the interpreters' opcode and class dispatch)
+            # are left unstructured: structurizing them adds a scalar flag
+            # block per branch on every interpreted instruction.
             cmd[1:1] = ["-x", "hip"]
+            cmd += ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -74,6 +74,61 @@ __device__ __forceinline__ uint64_t mread(const char* base, uint32_t off) {
   return *reinterpret_cast<const uint64_t*>(base + off);
 }
 
+__device__ __forceinline__ uint32_t rlane(uint32_t v, uint32_t l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+
+// Raw operand load of a per-lane operator by class: a u64 row element (D), a
+// u32 row element (W) or a wave-uniform word (a B mask or a K constant).  The
+// value is not used here, so the loads of all operands are in flight before
+// the first wait.  lane4 and lane8 are the lane's byte offsets in W and D rows.
+__device__ __forceinline__ uint64_t vload(const char* base, uint32_t cls, uint32_t off, uint32_t lane4,
+                                          uint32_t lane8) {
+  if (cls == C_D) return *reinterpret_cast<const uint64_t*>(base + off + lane8);
+  if (cls == C_W) return *reinterpret_cast<const uint32_t*>(base + off + lane4);
+  return *reinterpret_cast<const uint64_t*>(base + off);
+}
+
+// The lane's bit of a loaded mask (class B); other classes pass unchanged.
+__device__ __forceinline__ uint64_t vbit(uint32_t cls, uint64_t v, uint32_t lane) {
+  return cls == C_B ? (v >> lane) & 1 : v;
+}
+
+// A per-lane operator on zero-extended operands (not yet masked to its
+// width), as a tree of uniform tests; cheap neighbours are selected, not
+// branched to.
+__device__ __forceinline__ uint64_t alu_tree(uint32_t op, uint64_t a, uint64_t b, uint64_t c) {
+  uint64_t r;
+  if (op <= I_NOT) {
+    if (op <= I_OR) r = op == I_AND ? (a & b) : (a | b);
+    else r = op == I_XOR ? (a ^ b) : ~a;
+  } else if (op <= I_MUX) {
+    if (op == I_ADD) r = a + b;
+    else if (op == I_SUB) r = a - b;
+    else r = a ? b : c;
+  } else if (op <= I_SHR) {
+    r = b >= 64 ? 0 : (op == I_SHL ? a << (b & 63) : a >> (b & 63));
+  } else if (op <= I_LT) {
+    r = op == I_EQ ? (uint64_t)(a == b) : (uint64_t)(a < b);
+  } else {
+    r = a * b;
+  }
+  return r;
+}
+
+// Store a per-lane result into a slot of class cls (never a constant).
+__device__ __forceinline__ void vstore(char* base, uint32_t cls, uint32_t off, uint64_t v, uint32_t lane4,
+                                       uint32_t lane8, uint32_t lane) {
+  if (cls == C_D) {
+    *reinterpret_cast<uint64_t*>(base + off + lane8) = v;
+  } else if (cls == C_W) {
+    *reinterpret_cast<uint32_t*>(base + off + lane4) = (uint32_t)v;
+  } else {
+    const uint64_t m = __ballot(v & 1);
+    if (lane == 0) *reinterpret_cast<uint64_t*>(base + off) = m;
+  }
+}
+
 // One simulated cycle of one (process, tile group) work item of a batched sim.
 __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block, uint64_t cyc, char* lds) {
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -107,6 +162,7 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
   uint64_t dacc = 0;
   uint32_t blk = 0;
   uint4 bc = load_blk(0), bn = load_blk(1);
+  const uint32_t lane4 = 4 * lane, lane8 = 8 * lane;
   // instruction j of the process, j in the current or the next block
   auto instr = [&](uint32_t j) -> IWord { return lane_word((j >> 6) == blk ? bc : bn, j & 63); };
   for (uint32_t i = 0; i < bp.n_instr;) {
@@ -116,10 +172,47 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
       ++blk;
       bn = load_blk(blk + 1);
     }
-    const IWord q = lane_word(bc, i & 63);
-    const uint32_t x = q.x, y = q.y, z = q.z, aux = q.w;
-    const uint32_t op = x & 0xFF, w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
-    if (op >= K_LDREG_B) {
+    const uint32_t l = i & 63;
+    const uint32_t x = rlane(bc.x, l);
+    const uint32_t op = x & 0xFF;
+    uint32_t step = 1;
+    // Uniform if/else trees throughout, each handler falling through to the
+    // common step: switch statements and early exits cost a cascade of
+    // scalar flag blocks per interpreted instruction on this target.
+    if (op >= K_MASK_AND && op <= K_MASK_MUX) {
+      // every operand and the result are 64-instance masks
+      const uint32_t y = rlane(bc.y, l), z = rlane(bc.z, l);
+      const uint64_t ma = mread(base, y >> 16), mb = mread(base, z & 0xFFFF);
+      uint64_t r;
+      if (op < K_MASK_NOT) {
+        if (op == K_MASK_AND) r = ma & mb;
+        else if (op == K_MASK_OR) r = ma | mb;
+        else r = ma ^ mb;                             // also 1-bit ADD and SUB (sums mod 2)
+      } else if (op < K_MASK_LT) {
+        r = op == K_MASK_NOT ? ~ma : ~(ma ^ mb);
+      } else if (op == K_MASK_LT) {
+        r = ~ma & mb;
+      } else {
+        r = (ma & mb) | (~ma & mread(base, z >> 16));   // MUX
+      }
+      if (lane == 0) *reinterpret_cast<uint64_t*>(base + (y & 0xFFFF)) = r;
+    } else if (op >= I_AND && op <= I_MUL) {
+      // one value per lane: every operand load is issued before the first
+      // is used, then 1-bit operands are taken out of their masks
+      const uint32_t y = rlane(bc.y, l), z = rlane(bc.z, l);
+      const uint32_t cls = (x >> 16) & 0xFF, w = (x >> 8) & 0xFF;
+      const uint32_t ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = cls >> 6;
+      uint64_t a = vload(base, ca, y >> 16, lane4, lane8);
+      uint64_t b = vload(base, cb, z & 0xFFFF, lane4, lane8);
+      uint64_t c = 0;
+      if (op == I_MUX) c = vload(base, cc, z >> 16, lane4, lane8);
+      a = vbit(ca, a, lane);
+      b = vbit(cb, b, lane);
+      if (op == I_MUX) c = vbit(cc, c, lane);
+      uint64_t r = alu_tree(op, a, b, c);
+      if (w < 64) r &= wmask(w);
+      vstore(base, cls & 3, y & 0xFFFF, r, lane4, lane8, lane);
+    } else if (op >= K_LDREG_B) {
       // a run of same-class register loads inside the current block: the
       // register index (aux) and the slot offset (dst) of each load come
       // straight from the block registers; loads first, then the stores
@@ -143,125 +236,104 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
           else if (lane == 0) *reinterpret_cast<uint64_t*>(base + o) = v[k];
         }
       }
-      i += n;
-      continue;
-    }
-    const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
-    const uint32_t dst = y & 0xFFFF, oa = y >> 16, ob = z & 0xFFFF, oc = z >> 16;
-    if (op >= I_AND && op <= I_MUL) {
-      const uint64_t a = lread(base, ca, oa, lane), b = lread(base, cb, ob, lane);
-      const uint64_t c = op == I_MUX ? lread(base, cc, oc, lane) : 0;
-      lwrite(base, cd, dst, lane, alu(op, w, a, b, c));
-      ++i;
-      continue;
-    }
-    if (op >= K_MASK_AND && op <= K_MASK_MUX) {
-      // every operand and the result are 64-instance masks
-      const uint64_t ma = mread(base, oa), mb = mread(base, ob);
-      uint64_t r;
+      step = n;
+    } else {
+      const IWord q = lane_word(bc, l);
+      const uint32_t y = q.y, z = q.z, aux = q.w;
+      const uint32_t w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
+      const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
+      const uint32_t dst = y & 0xFFFF, oa = y >> 16, ob = z & 0xFFFF, oc = z >> 16;
       switch (op) {
-        case K_MASK_AND: r = ma & mb; break;
-        case K_MASK_OR:  r = ma | mb; break;
-        case K_MASK_XOR: r = ma ^ mb; break;        // also 1-bit ADD and SUB (sums mod 2)
-        case K_MASK_NOT: r = ~ma; break;
-        case K_MASK_EQ:  r = ~(ma ^ mb); break;
-        case K_MASK_LT:  r = ~ma & mb; break;
-        default:         r = (ma & mb) | (~ma & mread(base, oc)); break;   // MUX
-      }
-      if (lane == 0) *reinterpret_cast<uint64_t*>(base + dst) = r;
-      ++i;
-      continue;
-    }
-    switch (op) {
-      case I_LDREG:
-      case I_LDIN: {
-        // a run of up to kLeafRun leaf loads (length in flags): every load is issued
-        // before any result is used, so the run costs one memory latency
-        const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
-        uint64_t val[kLeafRun];
+        case I_LDREG:
+        case I_LDIN: {
+          // a run of up to kLeafRun leaf loads (length in flags): every load is issued
+          // before any result is used, so the run costs one memory latency
+          const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
+          uint64_t val[kLeafRun];
 #pragma unroll
-        for (uint32_t k = 0; k < kLeafRun; ++k) {
-          if (k < n) {
-            const IWord qk = instr(i + k);
-            const uint32_t xk = qk.x, auxk = qk.w;
-            const uint32_t cak = (xk >> 18) & 3;
-            if ((xk & 0xFF) == I_LDREG) {
-              val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
-                     : cak == C_W ? (uint64_t)stW_cur[(size_t)auxk * A.n_pad + inst]
-                                  : stD_cur[(size_t)auxk * A.n_pad + inst];
-            } else if (A.in_vals) {
-              val[k] = (real && cyc >= A.in_first && cyc < A.in_first + A.in_count)
-                           ? A.in_vals[((cyc - A.in_first) * A.I + auxk) * A.n_inst + inst] : 0;
-            } else {
-              val[k] = A.keys[(size_t)auxk * A.n_pad + inst];
-            }
-          }
-        }
-#pragma unroll
-        for (uint32_t k = 0; k < kLeafRun; ++k) {
-          if (k < n) {
-            const IWord qk = instr(i + k);
-            const uint32_t xk = qk.x, yk = qk.y;
-            const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
-            const uint32_t dk = yk & 0xFFFF;
-            if ((xk & 0xFF) == I_LDREG) {
-              if (cak == C_B) {
-                if (cdk == C_B) { if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = val[k]; }
-                else lwrite(base, cdk, dk, lane, (val[k] >> lane) & 1);
+          for (uint32_t k = 0; k < kLeafRun; ++k) {
+            if (k < n) {
+              const IWord qk = instr(i + k);
+              const uint32_t xk = qk.x, auxk = qk.w;
+              const uint32_t cak = (xk >> 18) & 3;
+              if ((xk & 0xFF) == I_LDREG) {
+                val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
+                       : cak == C_W ? (uint64_t)stW_cur[(size_t)auxk * A.n_pad + inst]
+                                    : stD_cur[(size_t)auxk * A.n_pad + inst];
+              } else if (A.in_vals) {
+                val[k] = (real && cyc >= A.in_first && cyc < A.in_first + A.in_count)
+                             ? A.in_vals[((cyc - A.in_first) * A.I + auxk) * A.n_inst + inst] : 0;
               } else {
-                lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
-              }
-            } else {
-              if (A.in_vals) {
-                if (cyc < A.in_first || cyc >= A.in_first + A.in_count) atomicOr(&A.error[1], 1u);
-                lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
-              } else {
-                lwrite(base, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
+                val[k] = A.keys[(size_t)auxk * A.n_pad + inst];
               }
             }
           }
+#pragma unroll
+          for (uint32_t k = 0; k < kLeafRun; ++k) {
+            if (k < n) {
+              const IWord qk = instr(i + k);
+              const uint32_t xk = qk.x, yk = qk.y;
+              const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
+              const uint32_t dk = yk & 0xFFFF;
+              if ((xk & 0xFF) == I_LDREG) {
+                if (cak == C_B) {
+                  if (cdk == C_B) { if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = val[k]; }
+                  else lwrite(base, cdk, dk, lane, (val[k] >> lane) & 1);
+                } else {
+                  lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
+                }
+              } else {
+                if (A.in_vals) {
+                  if (cyc < A.in_first || cyc >= A.in_first + A.in_count) atomicOr(&A.error[1], 1u);
+                  lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
+                } else {
+                  lwrite(base, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
+                }
+              }
+            }
+          }
+          step = n;
+          break;
         }
-        i += n;
-        continue;
-      }
-      case I_MEMRD: {
-        const uint64_t a = lread(base, ca, oa, lane);
-        const uint64_t depth = mem_depth[aux];
-        const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-        lwrite(base, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
-        break;
-      }
-      case I_STREG: {
-        // cd: class of the register's state array, ca: class of the value
-        const uint64_t v = lread(base, ca, oa, lane) & wmask(w);
-        if (cd == C_B) {
-          const uint64_t m = __ballot(v & 1);
-          if (lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile] = m;
-        } else if (cd == C_W) {
-          stW_nxt[(size_t)aux * A.n_pad + inst] = (uint32_t)v;
-        } else {
-          stD_nxt[(size_t)aux * A.n_pad + inst] = v;
-        }
-        if (A.digest) dacc += hmix((uint64_t)(ob | (oc << 16)) ^ hmix(v));
-        break;
-      }
-      case I_STOUT:
-        A.outputs[(size_t)aux * A.n_pad + inst] = lread(base, ca, oa, lane) & wmask(w);
-        break;
-      case I_WPORT: {
-        const uint64_t en = lread(base, ca, oa, lane), a = lread(base, cb, ob, lane);
-        const uint64_t v = lread(base, cc, oc, lane);
-        if (en) {
+        case I_MEMRD: {
+          const uint64_t a = lread(base, ca, oa, lane);
           const uint64_t depth = mem_depth[aux];
           const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-          A.mem[(mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
+          lwrite(base, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
+          break;
         }
-        break;
+        case I_STREG: {
+          // cd: class of the register's state array, ca: class of the value
+          const uint64_t v = lread(base, ca, oa, lane) & wmask(w);
+          if (cd == C_B) {
+            const uint64_t m = __ballot(v & 1);
+            if (lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile] = m;
+          } else if (cd == C_W) {
+            stW_nxt[(size_t)aux * A.n_pad + inst] = (uint32_t)v;
+          } else {
+            stD_nxt[(size_t)aux * A.n_pad + inst] = v;
+          }
+          if (A.digest) dacc += hmix((uint64_t)(ob | (oc << 16)) ^ hmix(v));
+          break;
+        }
+        case I_STOUT:
+          A.outputs[(size_t)aux * A.n_pad + inst] = lread(base, ca, oa, lane) & wmask(w);
+          break;
+        case I_WPORT: {
+          const uint64_t en = lread(base, ca, oa, lane), a = lread(base, cb, ob, lane);
+          const uint64_t v = lread(base, cc, oc, lane);
+          if (en) {
+            const uint64_t depth = mem_depth[aux];
+            const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
+            A.mem[(mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
+          }
+          break;
+        }
+        default:
+          break;
       }
-      default:
-        break;
     }
-    ++i;
+    i += step;
   }
   if (A.digest && real) {
     const uint64_t k = cyc - A.digest_first;
