@@ -962,20 +962,19 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
     }
     for (uint32_t i = 0; i < n_ord; ++i) { emitted[order[i]] = UINT32_MAX; slot_of[order[i]] = UINT32_MAX; kidx[order[i]] = UINT32_MAX; last_use[order[i]] = 0; }
   }
-  // ---- final form: handler kinds and LDS byte offsets
-  uint32_t max_k = 0;
-  for (const BatchProc& bp : d.batch_procs) max_k = std::max(max_k, bp.n_consts);
-  const uint32_t kbase = 16 + 8 * d.batch_slots[0];
-  const uint32_t wbase = (kbase + 8 * max_k + 15) & ~15u;
-  const uint32_t dbase = wbase + 256 * d.batch_slots[1];
-  const uint32_t end = dbase + 512 * d.batch_slots[2] + 16;     // + slack for 8-byte reads of u32 rows
-  if (end > 0xFFFF)
-    return Status::err(FSIM_E_CAPACITY, fmt("batched form: %llu bytes of live values per wave exceed the "
-                                            "16-bit offsets; use more processes", end));
-  d.batch_kbase = kbase;
-  d.batch_wave_bytes = end;
+  // ---- final form: handler kinds and LDS byte offsets, laid out per process
+  d.batch_wave_bytes = 0;
   for (uint32_t p = 0; p < d.P; ++p) {
-    const BatchProc& bp = d.batch_procs[p];
+    BatchProc& bp = d.batch_procs[p];
+    const uint32_t kbase = 16 + 8 * bp.slots[0];
+    const uint32_t wbase = (kbase + 8 * bp.n_consts + 15) & ~15u;
+    const uint32_t dbase = wbase + 256 * bp.slots[1];
+    const uint32_t end = dbase + 512 * bp.slots[2] + 16;     // + slack for 8-byte reads of u32 rows
+    if (end > 0xFFFF)
+      return Status::err(FSIM_E_CAPACITY, fmt("batched form: %llu bytes of live values per wave exceed the "
+                                              "16-bit offsets; use more processes", end));
+    bp.kbase = kbase;
+    d.batch_wave_bytes = std::max(d.batch_wave_bytes, end);
     for (uint32_t i = bp.instr_off; i < bp.instr_off + bp.n_instr; ++i) {
       Instr& in = d.batch_instr[i];
       const uint8_t cd = in.cls & 3, ca = (in.cls >> 2) & 3, cb = (in.cls >> 4) & 3, cc = (in.cls >> 6) & 3;

@@ -64,7 +64,6 @@ struct Design {
   std::vector<Instr> batch_instr;
   std::vector<uint64_t> batch_consts;   // per-process constant pools, back to back
   uint32_t batch_slots[3] = {0, 0, 0};  // max live slots per class over procs
-  uint32_t batch_kbase = 0;             // LDS byte offset of the staged constants
   uint32_t batch_wave_bytes = 0;        // LDS bytes of one wave's region
   bool batch_encoded = false;
   // internal register numbering of the batched layout: class + index

@@ -82,6 +82,9 @@ inline uint32_t chunk_capacity(uint32_t op) {
 //   [kbase, wbase)    the process's constants (u64 each, staged per wave)
 //   [wbase, dbase)    <=32-bit value slots (64 x u32 each)
 //   [dbase, end)      <=64-bit value slots (64 x u64 each)
+// with the bounds of each process's own slot counts, so that a wave's region
+// is the largest single process's need rather than the sum of the largest
+// need of every class.
 // Operators on per-lane values keep their opcode (I_AND .. I_MUL, with the
 // operand classes in cls); operators whose operands and result are all 1-bit
 // become whole-mask handlers.
@@ -99,7 +102,7 @@ struct BatchProc {
   uint32_t slots[3];   // live slots needed per class
   uint32_t const_off;  // constant pool of the process (class K operands)
   uint32_t n_consts;
-  uint32_t pad;
+  uint32_t kbase;      // LDS byte offset of the staged constants
 };
 static_assert(sizeof(BatchProc) == 32, "BatchProc must be 32 bytes");
 

@@ -70,7 +70,6 @@ struct BatchArgs {
   uint32_t P, n_tiles, tpw, n_inst, n_pad, I;
   uint32_t nB, nW, nD;
   uint32_t wave_bytes;        // LDS bytes of one wave's region (multiple of 16)
-  uint32_t kbase;             // byte offset of the staged constants in that region
 };
 
 hipError_t launch_batched(const BatchArgs& a, uint32_t grid, uint32_t threads, size_t lds_bytes,

@@ -151,7 +151,7 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
   // the wave's region: the two constant masks, then the process's constants
   if (lane < 2) reinterpret_cast<uint64_t*>(base)[lane] = lane ? ~0ull : 0ull;
   for (uint32_t k = lane; k < bp.n_consts; k += 64)
-    reinterpret_cast<uint64_t*>(base + A.kbase)[k] = A.consts[bp.const_off + k];
+    reinterpret_cast<uint64_t*>(base + bp.kbase)[k] = A.consts[bp.const_off + k];
   const uint32_t cur = cyc & 1, nxt = cur ^ 1;
   const cptr<uint64_t> stB_cur = as_const(A.stB + (size_t)cur * A.nB * A.n_tiles);
   uint64_t* stB_nxt = A.stB + (size_t)nxt * A.nB * A.n_tiles;

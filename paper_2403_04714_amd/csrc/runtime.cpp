@@ -540,7 +540,6 @@ fsim::BatchArgs fsim::batch_args(fsim_sim* s) {
   a.P = D.P; a.n_tiles = s->n_tiles; a.tpw = s->tpw; a.n_inst = s->n_inst; a.n_pad = s->n_pad; a.I = D.I;
   a.nB = D.reg_count[0]; a.nW = D.reg_count[1]; a.nD = D.reg_count[2];
   a.wave_bytes = D.batch_wave_bytes;
-  a.kbase = D.batch_kbase;
   return a;
 }
 
