@@ -833,18 +833,42 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
         stores_after[emitted[d.out_node[s - d.R - d.W]]].push_back(s);
       }
     }
-    // ---- slot allocation per class and emission
-    std::vector<uint32_t> free_list[3];
-    uint32_t used[3] = {0, 0, 0};
+    // ---- slot allocation and emission.  1-bit masks get 8-byte slots of
+    // their own; per-lane values share one arena of 256-byte pages, where a
+    // <=32-bit value takes one page and a <=64-bit value two adjacent ones
+    // (first fit from the bottom), so the region follows the bytes live at
+    // once rather than the per-class peaks.
+    std::vector<uint32_t> free_masks;
+    std::vector<uint8_t> page_busy;
+    uint32_t used[3] = {0, 0, 0}, live[3] = {0, 0, 0}, pages = 0;
     std::vector<std::vector<uint32_t>> release_at(n_ord + 1);
     for (uint32_t i = 0; i < n_ord; ++i) {
       uint32_t x = order[i];
       if (d.op[x] == FSIM_OP_CONST) continue;
       release_at[std::min(last_use[x], n_ord)].push_back(x);
     }
+    uint32_t masks = 0;
     auto get_slot = [&](uint8_t k) -> uint32_t {
-      if (!free_list[k].empty()) { uint32_t s = free_list[k].back(); free_list[k].pop_back(); return s; }
-      return used[k]++;
+      used[k] = std::max(used[k], ++live[k]);
+      if (k == C_B) {
+        if (!free_masks.empty()) { uint32_t s = free_masks.back(); free_masks.pop_back(); return s; }
+        return masks++;
+      }
+      const uint32_t n = k == C_D ? 2 : 1;
+      // first s whose n pages are free (pages past the arena's end are free)
+      auto busy = [&](uint32_t j) { return j < page_busy.size() && page_busy[j]; };
+      uint32_t s = 0;
+      while (busy(s) || (n == 2 && busy(s + 1))) ++s;
+      if (page_busy.size() < s + n) page_busy.resize(s + n, 0);
+      for (uint32_t j = 0; j < n; ++j) page_busy[s + j] = 1;
+      pages = std::max(pages, s + n);
+      return s;
+    };
+    auto put_slot = [&](uint8_t k, uint32_t s) {
+      --live[k];
+      if (k == C_B) { free_masks.push_back(s); return; }
+      page_busy[s] = 0;
+      if (k == C_D) page_busy[s + 1] = 0;
     };
     auto operand = [&](uint32_t y, uint8_t& cls) -> uint16_t {
       if (d.op[y] == FSIM_OP_CONST) { cls = 3; return (uint16_t)kidx[y]; }
@@ -884,7 +908,8 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
           if (arity(op) > 1) in.b = operand(a[1], cb); else { in.b = in.a; cb = ca; }
           if (arity(op) > 2) in.c = operand(a[2], cc); else { in.c = in.a; cc = ca; }
         }
-        for (uint32_t y : release_at[i]) if (y != x && slot_of[y] != UINT32_MAX) free_list[cls_of[y]].push_back(slot_of[y]);
+        for (uint32_t y : release_at[i])
+          if (y != x && slot_of[y] < UINT32_MAX - 1) put_slot(cls_of[y], slot_of[y]);
         const uint8_t kd = cls_of[x];
         slot_of[x] = get_slot(kd);
         in.dst = (uint16_t)slot_of[x];
@@ -910,7 +935,7 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
         }
       }
       if (last_use[x] == i && slot_of[x] != UINT32_MAX && d.op[x] != FSIM_OP_CONST) {
-        free_list[cls_of[x]].push_back(slot_of[x]);
+        put_slot(cls_of[x], slot_of[x]);
         slot_of[x] = UINT32_MAX - 1;       // released (value no longer needed)
       }
     }
@@ -953,8 +978,9 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
         for (uint32_t k = i; k < j; ++k) d.batch_instr[k].op = (uint8_t)fk;
       i = j;
     }
+    bp.mask_slots = masks;
+    bp.row_pages = pages;
     for (int k = 0; k < 3; ++k) {
-      bp.slots[k] = used[k];
       d.batch_slots[k] = std::max(d.batch_slots[k], used[k]);
       if (max_slots_per_class && used[k] > max_slots_per_class[k])
         return Status::err(FSIM_E_CAPACITY,
@@ -966,10 +992,9 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
   d.batch_wave_bytes = 0;
   for (uint32_t p = 0; p < d.P; ++p) {
     BatchProc& bp = d.batch_procs[p];
-    const uint32_t kbase = 16 + 8 * bp.slots[0];
-    const uint32_t wbase = (kbase + 8 * bp.n_consts + 15) & ~15u;
-    const uint32_t dbase = wbase + 256 * bp.slots[1];
-    const uint32_t end = dbase + 512 * bp.slots[2] + 16;     // + slack for 8-byte reads of u32 rows
+    const uint32_t kbase = 16 + 8 * bp.mask_slots;
+    const uint32_t rbase = (kbase + 8 * bp.n_consts + 15) & ~15u;
+    const uint32_t end = rbase + 256 * bp.row_pages + 16;     // + slack for 8-byte reads of u32 rows
     if (end > 0xFFFF)
       return Status::err(FSIM_E_CAPACITY, fmt("batched form: %llu bytes of live values per wave exceed the "
                                               "16-bit offsets; use more processes", end));
@@ -981,8 +1006,8 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
       auto off = [&](uint8_t cls, uint16_t idx) -> uint16_t {
         switch (cls) {
           case C_B: return (uint16_t)(16 + 8 * idx);
-          case C_W: return (uint16_t)(wbase + 256 * idx);
-          case C_D: return (uint16_t)(dbase + 512 * idx);
+          case C_W:
+          case C_D: return (uint16_t)(rbase + 256 * idx);
           default:  return (uint16_t)(kbase + 8 * idx);
         }
       };

@@ -79,12 +79,12 @@ inline uint32_t chunk_capacity(uint32_t op) {
 // wave's region:
 //   [0, 16)           two 1-bit masks: all zeros, all ones
 //   [16, kbase)       1-bit value slots (one u64 mask each)
-//   [kbase, wbase)    the process's constants (u64 each, staged per wave)
-//   [wbase, dbase)    <=32-bit value slots (64 x u32 each)
-//   [dbase, end)      <=64-bit value slots (64 x u64 each)
-// with the bounds of each process's own slot counts, so that a wave's region
-// is the largest single process's need rather than the sum of the largest
-// need of every class.
+//   [kbase, rbase)    the process's constants (u64 each, staged per wave)
+//   [rbase, end)      256-byte pages of per-lane values: a <=32-bit value
+//                     takes one (64 x u32), a <=64-bit value two adjacent
+//                     ones (64 x u64)
+// with the bounds of each process's own needs, so that a wave's region is
+// the largest single process's need.
 // Operators on per-lane values keep their opcode (I_AND .. I_MUL, with the
 // operand classes in cls); operators whose operands and result are all 1-bit
 // become whole-mask handlers.
@@ -99,7 +99,9 @@ enum : uint8_t {
 struct BatchProc {
   uint32_t instr_off;
   uint32_t n_instr;
-  uint32_t slots[3];   // live slots needed per class
+  uint32_t mask_slots; // 8-byte slots of 1-bit masks
+  uint32_t row_pages;  // 256-byte pages of per-lane values (<=32-bit: one, <=64-bit: two)
+  uint32_t pad;
   uint32_t const_off;  // constant pool of the process (class K operands)
   uint32_t n_consts;
   uint32_t kbase;      // LDS byte offset of the staged constants
