@@ -393,7 +393,7 @@ def main():
                          "profiling runs")
     ap.add_argument("--profile-run", choices=["batched-core", "plain-core", "plain-prng"], default=None,
                     help="a short fixed run for hardware counters (per-cycle launches): batched "
-                         "single-core x256 on 1024 processes, plain single-core on 2048 one-wave "
+                         "single-core x1024 on 4096 processes, plain single-core on 2048 one-wave "
                          "processes, or 64 one-wave processes of 7 independent PRNG fibers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of known size (the reference for HBM byte counters)")
@@ -421,8 +421,8 @@ def main():
     if args.profile_run:
         ctx = F.Context(0)
         if args.profile_run == "batched-core":
-            d = F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=1024)
-            sim = F.Sim(d, 256, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
+            d = F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=4096)
+            sim = F.Sim(d, 1024, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
         elif args.profile_run == "plain-core":
             d = F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=2048)
             sim = F.Sim(d, 1, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
@@ -554,8 +554,8 @@ def main():
         del sim
         extra_t0 = time.time()
         out["batched"] = [
-            bench_batched(F, g, tune, ctx, "core", 1024, (2048, 4096, 8192), (64, 128), 512, 64, seed),
-            bench_batched(F, g, tune, ctx, "soc8", 256, (16384, 32768), (64, 128), 256, 32, seed),
+            bench_batched(F, g, tune, ctx, "core", 1024, (2048, 4096, 8192), (64, 256), 512, 64, seed),
+            bench_batched(F, g, tune, ctx, "soc8", 256, (16384, 32768), (64, 256), 256, 32, seed),
         ]
         out["plain_soc8"] = bench_plain_tuned(F, g, tune, ctx, "soc8", (1024, 2048, 4096), (64, 256),
                                               5000, 500, seed)

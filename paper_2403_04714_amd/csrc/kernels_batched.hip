@@ -160,180 +160,182 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
   const uint64_t* stD_cur = A.stD + (size_t)cur * A.nD * A.n_pad;
   uint64_t* stD_nxt = A.stD + (size_t)nxt * A.nD * A.n_pad;
   uint64_t dacc = 0;
-  uint32_t blk = 0;
-  uint4 bc = load_blk(0), bn = load_blk(1);
   const uint32_t lane4 = 4 * lane, lane8 = 8 * lane;
-  // instruction j of the process, j in the current or the next block
-  auto instr = [&](uint32_t j) -> IWord { return lane_word((j >> 6) == blk ? bc : bn, j & 63); };
-  for (uint32_t i = 0; i < bp.n_instr;) {
-    // a step advances i by at most 16, so it crosses at most one block
-    if ((i >> 6) != blk) {
-      bc = bn;
-      ++blk;
-      bn = load_blk(blk + 1);
-    }
-    const uint32_t l = i & 63;
-    const uint32_t x = rlane(bc.x, l);
-    const uint32_t op = x & 0xFF;
-    uint32_t step = 1;
-    // Uniform if/else trees throughout, each handler falling through to the
-    // common step: switch statements and early exits cost a cascade of
-    // scalar flag blocks per interpreted instruction on this target.
-    if (op >= K_MASK_AND && op <= K_MASK_MUX) {
-      // every operand and the result are 64-instance masks
-      const uint32_t y = rlane(bc.y, l), z = rlane(bc.z, l);
-      const uint64_t ma = mread(base, y >> 16), mb = mread(base, z & 0xFFFF);
-      uint64_t r;
-      if (op < K_MASK_NOT) {
-        if (op == K_MASK_AND) r = ma & mb;
-        else if (op == K_MASK_OR) r = ma | mb;
-        else r = ma ^ mb;                             // also 1-bit ADD and SUB (sums mod 2)
-      } else if (op < K_MASK_LT) {
-        r = op == K_MASK_NOT ? ~ma : ~(ma ^ mb);
-      } else if (op == K_MASK_LT) {
-        r = ~ma & mb;
+  uint32_t i = 0;
+  uint4 bc = load_blk(0);
+  for (uint32_t blk = 0; i < bp.n_instr; ++blk) {
+    // the next block is in flight while this one runs; it is waited for only
+    // where a leaf run reaches into it, or when it becomes the current block
+    // (a step advances i by at most 16, so it crosses at most one block)
+    const uint4 bn = load_blk(blk + 1);
+    // instruction j of the process, j in the current or the next block
+    auto instr = [&](uint32_t j) -> IWord { return lane_word((j >> 6) == blk ? bc : bn, j & 63); };
+    const uint32_t blk_end = bp.n_instr < 64 * (blk + 1) ? bp.n_instr : 64 * (blk + 1);
+    while (i < blk_end) {
+      const uint32_t l = i & 63;
+      const uint32_t x = rlane(bc.x, l);
+      const uint32_t op = x & 0xFF;
+      uint32_t step = 1;
+      // Uniform if/else trees throughout, each handler falling through to the
+      // common step: switch statements and early exits cost a cascade of
+      // scalar flag blocks per interpreted instruction on this target.
+      if (op >= K_MASK_AND && op <= K_MASK_MUX) {
+        // every operand and the result are 64-instance masks
+        const uint32_t y = rlane(bc.y, l), z = rlane(bc.z, l);
+        const uint64_t ma = mread(base, y >> 16), mb = mread(base, z & 0xFFFF);
+        uint64_t r;
+        if (op < K_MASK_NOT) {
+          if (op == K_MASK_AND) r = ma & mb;
+          else if (op == K_MASK_OR) r = ma | mb;
+          else r = ma ^ mb;                             // also 1-bit ADD and SUB (sums mod 2)
+        } else if (op < K_MASK_LT) {
+          r = op == K_MASK_NOT ? ~ma : ~(ma ^ mb);
+        } else if (op == K_MASK_LT) {
+          r = ~ma & mb;
+        } else {
+          r = (ma & mb) | (~ma & mread(base, z >> 16));   // MUX
+        }
+        if (lane == 0) *reinterpret_cast<uint64_t*>(base + (y & 0xFFFF)) = r;
+      } else if (op >= I_AND && op <= I_MUL) {
+        // one value per lane: every operand load is issued before the first
+        // is used, then 1-bit operands are taken out of their masks
+        const uint32_t y = rlane(bc.y, l), z = rlane(bc.z, l);
+        const uint32_t cls = (x >> 16) & 0xFF, w = (x >> 8) & 0xFF;
+        const uint32_t ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = cls >> 6;
+        uint64_t a = vload(base, ca, y >> 16, lane4, lane8);
+        uint64_t b = vload(base, cb, z & 0xFFFF, lane4, lane8);
+        uint64_t c = 0;
+        if (op == I_MUX) c = vload(base, cc, z >> 16, lane4, lane8);
+        a = vbit(ca, a, lane);
+        b = vbit(cb, b, lane);
+        if (op == I_MUX) c = vbit(cc, c, lane);
+        uint64_t r = alu_tree(op, a, b, c);
+        if (w < 64) r &= wmask(w);
+        vstore(base, cls & 3, y & 0xFFFF, r, lane4, lane8, lane);
+      } else if (op >= K_LDREG_B) {
+        // a run of same-class register loads inside the current block: the
+        // register index (aux) and the slot offset (dst) of each load come
+        // straight from the block registers; loads first, then the stores
+        const uint32_t n = (x >> 24) & 0xFF;
+        uint64_t v[kLeafRun];
+#pragma unroll
+        for (uint32_t k = 0; k < kLeafRun; ++k) {
+          if (k < n) {
+            const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)bc.w, (int)((i + k) & 63));
+            if (op == K_LDREG_D) v[k] = (stD_cur + (size_t)r * A.n_pad)[inst];
+            else if (op == K_LDREG_W) v[k] = (stW_cur + (size_t)r * A.n_pad)[inst];
+            else v[k] = stB_cur[(size_t)r * A.n_tiles + tile];
+          }
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kLeafRun; ++k) {
+          if (k < n) {
+            const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)bc.y, (int)((i + k) & 63)) & 0xFFFF;
+            if (op == K_LDREG_D) *reinterpret_cast<uint64_t*>(base + o + 8 * lane) = v[k];
+            else if (op == K_LDREG_W) *reinterpret_cast<uint32_t*>(base + o + 4 * lane) = (uint32_t)v[k];
+            else if (lane == 0) *reinterpret_cast<uint64_t*>(base + o) = v[k];
+          }
+        }
+        step = n;
       } else {
-        r = (ma & mb) | (~ma & mread(base, z >> 16));   // MUX
-      }
-      if (lane == 0) *reinterpret_cast<uint64_t*>(base + (y & 0xFFFF)) = r;
-    } else if (op >= I_AND && op <= I_MUL) {
-      // one value per lane: every operand load is issued before the first
-      // is used, then 1-bit operands are taken out of their masks
-      const uint32_t y = rlane(bc.y, l), z = rlane(bc.z, l);
-      const uint32_t cls = (x >> 16) & 0xFF, w = (x >> 8) & 0xFF;
-      const uint32_t ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = cls >> 6;
-      uint64_t a = vload(base, ca, y >> 16, lane4, lane8);
-      uint64_t b = vload(base, cb, z & 0xFFFF, lane4, lane8);
-      uint64_t c = 0;
-      if (op == I_MUX) c = vload(base, cc, z >> 16, lane4, lane8);
-      a = vbit(ca, a, lane);
-      b = vbit(cb, b, lane);
-      if (op == I_MUX) c = vbit(cc, c, lane);
-      uint64_t r = alu_tree(op, a, b, c);
-      if (w < 64) r &= wmask(w);
-      vstore(base, cls & 3, y & 0xFFFF, r, lane4, lane8, lane);
-    } else if (op >= K_LDREG_B) {
-      // a run of same-class register loads inside the current block: the
-      // register index (aux) and the slot offset (dst) of each load come
-      // straight from the block registers; loads first, then the stores
-      const uint32_t n = (x >> 24) & 0xFF;
-      uint64_t v[kLeafRun];
+        const IWord q = lane_word(bc, l);
+        const uint32_t y = q.y, z = q.z, aux = q.w;
+        const uint32_t w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
+        const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
+        const uint32_t dst = y & 0xFFFF, oa = y >> 16, ob = z & 0xFFFF, oc = z >> 16;
+        switch (op) {
+          case I_LDREG:
+          case I_LDIN: {
+            // a run of up to kLeafRun leaf loads (length in flags): every load is issued
+            // before any result is used, so the run costs one memory latency
+            const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
+            uint64_t val[kLeafRun];
 #pragma unroll
-      for (uint32_t k = 0; k < kLeafRun; ++k) {
-        if (k < n) {
-          const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)bc.w, (int)((i + k) & 63));
-          if (op == K_LDREG_D) v[k] = (stD_cur + (size_t)r * A.n_pad)[inst];
-          else if (op == K_LDREG_W) v[k] = (stW_cur + (size_t)r * A.n_pad)[inst];
-          else v[k] = stB_cur[(size_t)r * A.n_tiles + tile];
-        }
-      }
-#pragma unroll
-      for (uint32_t k = 0; k < kLeafRun; ++k) {
-        if (k < n) {
-          const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)bc.y, (int)((i + k) & 63)) & 0xFFFF;
-          if (op == K_LDREG_D) *reinterpret_cast<uint64_t*>(base + o + 8 * lane) = v[k];
-          else if (op == K_LDREG_W) *reinterpret_cast<uint32_t*>(base + o + 4 * lane) = (uint32_t)v[k];
-          else if (lane == 0) *reinterpret_cast<uint64_t*>(base + o) = v[k];
-        }
-      }
-      step = n;
-    } else {
-      const IWord q = lane_word(bc, l);
-      const uint32_t y = q.y, z = q.z, aux = q.w;
-      const uint32_t w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
-      const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
-      const uint32_t dst = y & 0xFFFF, oa = y >> 16, ob = z & 0xFFFF, oc = z >> 16;
-      switch (op) {
-        case I_LDREG:
-        case I_LDIN: {
-          // a run of up to kLeafRun leaf loads (length in flags): every load is issued
-          // before any result is used, so the run costs one memory latency
-          const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
-          uint64_t val[kLeafRun];
-#pragma unroll
-          for (uint32_t k = 0; k < kLeafRun; ++k) {
-            if (k < n) {
-              const IWord qk = instr(i + k);
-              const uint32_t xk = qk.x, auxk = qk.w;
-              const uint32_t cak = (xk >> 18) & 3;
-              if ((xk & 0xFF) == I_LDREG) {
-                val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
-                       : cak == C_W ? (uint64_t)stW_cur[(size_t)auxk * A.n_pad + inst]
-                                    : stD_cur[(size_t)auxk * A.n_pad + inst];
-              } else if (A.in_vals) {
-                val[k] = (real && cyc >= A.in_first && cyc < A.in_first + A.in_count)
-                             ? A.in_vals[((cyc - A.in_first) * A.I + auxk) * A.n_inst + inst] : 0;
-              } else {
-                val[k] = A.keys[(size_t)auxk * A.n_pad + inst];
-              }
-            }
-          }
-#pragma unroll
-          for (uint32_t k = 0; k < kLeafRun; ++k) {
-            if (k < n) {
-              const IWord qk = instr(i + k);
-              const uint32_t xk = qk.x, yk = qk.y;
-              const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
-              const uint32_t dk = yk & 0xFFFF;
-              if ((xk & 0xFF) == I_LDREG) {
-                if (cak == C_B) {
-                  if (cdk == C_B) { if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = val[k]; }
-                  else lwrite(base, cdk, dk, lane, (val[k] >> lane) & 1);
+            for (uint32_t k = 0; k < kLeafRun; ++k) {
+              if (k < n) {
+                const IWord qk = instr(i + k);
+                const uint32_t xk = qk.x, auxk = qk.w;
+                const uint32_t cak = (xk >> 18) & 3;
+                if ((xk & 0xFF) == I_LDREG) {
+                  val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
+                         : cak == C_W ? (uint64_t)stW_cur[(size_t)auxk * A.n_pad + inst]
+                                      : stD_cur[(size_t)auxk * A.n_pad + inst];
+                } else if (A.in_vals) {
+                  val[k] = (real && cyc >= A.in_first && cyc < A.in_first + A.in_count)
+                               ? A.in_vals[((cyc - A.in_first) * A.I + auxk) * A.n_inst + inst] : 0;
                 } else {
-                  lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
-                }
-              } else {
-                if (A.in_vals) {
-                  if (cyc < A.in_first || cyc >= A.in_first + A.in_count) atomicOr(&A.error[1], 1u);
-                  lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
-                } else {
-                  lwrite(base, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
+                  val[k] = A.keys[(size_t)auxk * A.n_pad + inst];
                 }
               }
             }
+#pragma unroll
+            for (uint32_t k = 0; k < kLeafRun; ++k) {
+              if (k < n) {
+                const IWord qk = instr(i + k);
+                const uint32_t xk = qk.x, yk = qk.y;
+                const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
+                const uint32_t dk = yk & 0xFFFF;
+                if ((xk & 0xFF) == I_LDREG) {
+                  if (cak == C_B) {
+                    if (cdk == C_B) { if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = val[k]; }
+                    else lwrite(base, cdk, dk, lane, (val[k] >> lane) & 1);
+                  } else {
+                    lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
+                  }
+                } else {
+                  if (A.in_vals) {
+                    if (cyc < A.in_first || cyc >= A.in_first + A.in_count) atomicOr(&A.error[1], 1u);
+                    lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
+                  } else {
+                    lwrite(base, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
+                  }
+                }
+              }
+            }
+            step = n;
+            break;
           }
-          step = n;
-          break;
-        }
-        case I_MEMRD: {
-          const uint64_t a = lread(base, ca, oa, lane);
-          const uint64_t depth = mem_depth[aux];
-          const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-          lwrite(base, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
-          break;
-        }
-        case I_STREG: {
-          // cd: class of the register's state array, ca: class of the value
-          const uint64_t v = lread(base, ca, oa, lane) & wmask(w);
-          if (cd == C_B) {
-            const uint64_t m = __ballot(v & 1);
-            if (lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile] = m;
-          } else if (cd == C_W) {
-            stW_nxt[(size_t)aux * A.n_pad + inst] = (uint32_t)v;
-          } else {
-            stD_nxt[(size_t)aux * A.n_pad + inst] = v;
-          }
-          if (A.digest) dacc += hmix((uint64_t)(ob | (oc << 16)) ^ hmix(v));
-          break;
-        }
-        case I_STOUT:
-          A.outputs[(size_t)aux * A.n_pad + inst] = lread(base, ca, oa, lane) & wmask(w);
-          break;
-        case I_WPORT: {
-          const uint64_t en = lread(base, ca, oa, lane), a = lread(base, cb, ob, lane);
-          const uint64_t v = lread(base, cc, oc, lane);
-          if (en) {
+          case I_MEMRD: {
+            const uint64_t a = lread(base, ca, oa, lane);
             const uint64_t depth = mem_depth[aux];
             const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-            A.mem[(mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
+            lwrite(base, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
+            break;
           }
-          break;
+          case I_STREG: {
+            // cd: class of the register's state array, ca: class of the value
+            const uint64_t v = lread(base, ca, oa, lane) & wmask(w);
+            if (cd == C_B) {
+              const uint64_t m = __ballot(v & 1);
+              if (lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile] = m;
+            } else if (cd == C_W) {
+              stW_nxt[(size_t)aux * A.n_pad + inst] = (uint32_t)v;
+            } else {
+              stD_nxt[(size_t)aux * A.n_pad + inst] = v;
+            }
+            if (A.digest) dacc += hmix((uint64_t)(ob | (oc << 16)) ^ hmix(v));
+            break;
+          }
+          case I_STOUT:
+            A.outputs[(size_t)aux * A.n_pad + inst] = lread(base, ca, oa, lane) & wmask(w);
+            break;
+          case I_WPORT: {
+            const uint64_t en = lread(base, ca, oa, lane), a = lread(base, cb, ob, lane);
+            const uint64_t v = lread(base, cc, oc, lane);
+            if (en) {
+              const uint64_t depth = mem_depth[aux];
+              const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
+              A.mem[(mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
+            }
+            break;
+          }
+          default:
+            break;
         }
-        default:
-          break;
       }
+      i += step;
     }
-    i += step;
+    bc = bn;
   }
   if (A.digest && real) {
     const uint64_t k = cyc - A.digest_first;
