@@ -247,13 +247,17 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
           case I_LDREG:
           case I_LDIN: {
             // a run of up to kLeafRun leaf loads (length in flags): every load is issued
-            // before any result is used, so the run costs one memory latency
+            // before any result is used, so the run costs one memory latency.  A
+            // shorter run repeats its last leaf (the same value to the same slot):
+            // every unrolled load is then used on every path, where a load left
+            // unused on some path would make every later handler wait for all
+            // outstanding memory operations.
             const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
             uint64_t val[kLeafRun];
 #pragma unroll
             for (uint32_t k = 0; k < kLeafRun; ++k) {
-              if (k < n) {
-                const IWord qk = instr(i + k);
+              {
+                const IWord qk = instr(i + (k < n ? k : n - 1));
                 const uint32_t xk = qk.x, auxk = qk.w;
                 const uint32_t cak = (xk >> 18) & 3;
                 if ((xk & 0xFF) == I_LDREG) {
@@ -270,14 +274,20 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
             }
 #pragma unroll
             for (uint32_t k = 0; k < kLeafRun; ++k) {
-              if (k < n) {
-                const IWord qk = instr(i + k);
+              {
+                const IWord qk = instr(i + (k < n ? k : n - 1));
                 const uint32_t xk = qk.x, yk = qk.y;
                 const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
                 const uint32_t dk = yk & 0xFFFF;
                 if ((xk & 0xFF) == I_LDREG) {
                   if (cak == C_B) {
-                    if (cdk == C_B) { if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = val[k]; }
+                    if (cdk == C_B) {
+                      // the mask is wave-uniform: taken into scalar registers here,
+                      // outside the one-lane store
+                      const uint64_t m = ((uint64_t)rlane((uint32_t)(val[k] >> 32), 0) << 32) |
+                                         rlane((uint32_t)val[k], 0);
+                      if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = m;
+                    }
                     else lwrite(base, cdk, dk, lane, (val[k] >> lane) & 1);
                   } else {
                     lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
