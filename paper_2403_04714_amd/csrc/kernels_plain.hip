@@ -319,49 +319,10 @@ __device__ void plain_wave_body(const PlainArgs& A) {
       const uint32_t v = cc - c_base < 64 ? cr[0] : cr[1];
       return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(cc & 63));
     };
-    uint32_t ch = n_ch ? word(0) : 0;
-    uint4 raw = first_instr(ch);
-    // unstaged: the first instruction of chunk c + 1 is already in flight
-    // while chunk c runs, and chunk c + 2's is issued
-    uint4 raw1 = make_uint4(0, 0, 0, 0);
-    if (!STAGED) raw1 = first_instr(n_ch > 1 ? word(1) : 0);
-    while (c < n_ch) {
-      if ((ch >> 24) == I_ALU) {
-        // a run of operator chunks: operand reads, then the next chunk's
-        // first instruction; only the operands are waited for
-        do {
-          const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
-          const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
-          const Dec in = decode(raw);
-          uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
-          uint4 rn;
-          if (STAGED) {
-            rn = first_instr(chn);
-          } else {
-            rn = raw1;
-            raw1 = first_instr(c + 2 < n_ch ? word(c + 2) : 0);
-          }
-          asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
-          const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
-          const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
-          if (lane < cnt) at(in.dst) = r;
-          ++c;
-          ch = chn;
-          raw = rn;
-          if (c - c_base == 64) rotate();
-          if (trace_row) stamp(c);
-        } while (c < n_ch && (ch >> 24) == I_ALU);
-        continue;
-      }
+    // a leaf-load, sink-store or memory-read chunk whose first instruction
+    // for this lane is `raw`
+    auto other_chunk = [&](const uint4 raw, const uint32_t ch) {
       const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 0xFF) + 1, op = ch >> 24;
-      const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
-      uint4 rn;
-      if (STAGED) {
-        rn = first_instr(chn);
-      } else {
-        rn = raw1;
-        raw1 = first_instr(c + 2 < n_ch ? word(c + 2) : 0);
-      }
       if (op == I_MEMRD) {
         if (lane < cnt) {
           const Dec in = decode(raw);
@@ -413,11 +374,76 @@ __device__ void plain_wave_body(const PlainArgs& A) {
           }
         }
       }
-      ++c;
-      ch = chn;
-      raw = rn;
-      if (c - c_base == 64) rotate();
-      if (trace_row) stamp(c);
+    };
+    uint32_t ch = n_ch ? word(0) : 0;
+    if (STAGED) {
+      // the next chunk's first instruction is read while this one runs
+      uint4 raw = first_instr(ch);
+      while (c < n_ch) {
+        if ((ch >> 24) == I_ALU) {
+          // a run of operator chunks: operand reads, then the next chunk's
+          // first instruction; only the operands are waited for
+          do {
+            const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
+            const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
+            const Dec in = decode(raw);
+            uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
+            const uint4 rn = first_instr(chn);
+            asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
+            const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
+            const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
+            if (lane < cnt) at(in.dst) = r;
+            ++c;
+            ch = chn;
+            raw = rn;
+            if (c - c_base == 64) rotate();
+            if (trace_row) stamp(c);
+          } while (c < n_ch && (ch >> 24) == I_ALU);
+          continue;
+        }
+        const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
+        const uint4 rn = first_instr(chn);
+        other_chunk(raw, ch);
+        ++c;
+        ch = chn;
+        raw = rn;
+        if (c - c_base == 64) rotate();
+        if (trace_row) stamp(c);
+      }
+    } else {
+      // instructions from global memory: two slots hold the first
+      // instructions of chunks c and c + 1; a chunk decodes its slot and
+      // refills it with chunk c + 2's, so every load has two chunks' time to
+      // land.  The loop is unrolled by two so that no slot is ever copied
+      // while its load is in flight (a copy would wait for it at once).
+      uint4 s0 = first_instr(ch), s1 = first_instr(n_ch > 1 ? word(1) : 0);
+      auto one = [&](uint4& slot) {
+        const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
+        const uint32_t ch2 = c + 2 < n_ch ? word(c + 2) : 0;
+        if ((ch >> 24) == I_ALU) {
+          const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
+          const Dec in = decode(slot);
+          uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
+          slot = first_instr(ch2);
+          asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
+          const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
+          const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
+          if (lane < cnt) at(in.dst) = r;
+        } else {
+          const uint4 raw = slot;
+          slot = first_instr(ch2);
+          other_chunk(raw, ch);
+        }
+        ++c;
+        ch = chn;
+        if (c - c_base == 64) rotate();
+        if (trace_row) stamp(c);
+      };
+      while (c < n_ch) {
+        one(s0);
+        if (c >= n_ch) break;
+        one(s1);
+      }
     }
     if (lane == 0) {
       for (uint32_t k = 0; k < pp.n_wp; ++k) {
