@@ -231,7 +231,7 @@ __device__ void plain_body(const PlainArgs& A) {
 // instruction of each chunk two chunks ahead, and the workgroup's LDS holds
 // only the value slots, so that many more workgroups are resident at once
 // (large designs) and nothing is copied per launch.
-template <bool PERSISTENT, bool STAGED>
+template <bool PERSISTENT, bool STAGED, bool TRACE>
 __device__ void plain_wave_body(const PlainArgs& A) {
   extern __shared__ uint64_t lds[];
   __shared__ int abort_flag;
@@ -292,7 +292,7 @@ __device__ void plain_wave_body(const PlainArgs& A) {
     const uint64_t* cur = A.state + (cyc & 1) * A.R;
     uint64_t* nxt = A.state + ((cyc + 1) & 1) * A.R;
     uint64_t dacc = 0;
-    if (A.trace) {
+    if (TRACE && A.trace) {
       const uint64_t k = cyc - A.trace_first;
       trace_row = k < A.trace_max ? A.trace + (k * gridDim.x + blockIdx.x) * A.trace_stride : nullptr;
       if (trace_row && lane == 0) trace_row[0] = __builtin_amdgcn_s_memrealtime();
@@ -473,10 +473,18 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   }
 }
 
-__global__ void __launch_bounds__(64) plain_wave_persistent(PlainArgs A) { plain_wave_body<true, true>(A); }
-__global__ void __launch_bounds__(64) plain_wave_cycle(PlainArgs A) { plain_wave_body<false, true>(A); }
-__global__ void __launch_bounds__(64) plain_wave_persistent_g(PlainArgs A) { plain_wave_body<true, false>(A); }
-__global__ void __launch_bounds__(64) plain_wave_cycle_g(PlainArgs A) { plain_wave_body<false, false>(A); }
+__global__ void __launch_bounds__(64) plain_wave_persistent(PlainArgs A) { plain_wave_body<true, true, false>(A); }
+__global__ void __launch_bounds__(64) plain_wave_cycle(PlainArgs A) { plain_wave_body<false, true, false>(A); }
+__global__ void __launch_bounds__(64) plain_wave_persistent_g(PlainArgs A) { plain_wave_body<true, false, false>(A); }
+__global__ void __launch_bounds__(64) plain_wave_cycle_g(PlainArgs A) { plain_wave_body<false, false, false>(A); }
+// the same with phase timestamps (a sim with tracing enabled): the untraced
+// kernels carry no per-chunk test for it
+__global__ void __launch_bounds__(64) plain_wave_persistent_trace(PlainArgs A) { plain_wave_body<true, true, true>(A); }
+__global__ void __launch_bounds__(64) plain_wave_cycle_trace(PlainArgs A) { plain_wave_body<false, true, true>(A); }
+__global__ void __launch_bounds__(64) plain_wave_persistent_g_trace(PlainArgs A) {
+  plain_wave_body<true, false, true>(A);
+}
+__global__ void __launch_bounds__(64) plain_wave_cycle_g_trace(PlainArgs A) { plain_wave_body<false, false, true>(A); }
 
 __global__ void __launch_bounds__(1024) plain_persistent(PlainArgs A) { plain_body<true, true>(A); }
 __global__ void __launch_bounds__(1024) plain_cycle(PlainArgs A) { plain_body<false, true>(A); }
@@ -512,14 +520,21 @@ namespace fsim {
 hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t lds_bytes,
                         bool persistent, hipStream_t s) {
   if (a.single_wave) {
+    const bool tr = a.trace != nullptr;
     if (persistent) {
       void* args[] = {const_cast<PlainArgs*>(&a)};
-      return hipLaunchCooperativeKernel(a.stage_instr ? (const void*)plain_wave_persistent
-                                                      : (const void*)plain_wave_persistent_g,
-                                        dim3(G), dim3(64), args, (unsigned)lds_bytes, s);
+      const void* k = a.stage_instr ? (tr ? (const void*)plain_wave_persistent_trace : (const void*)plain_wave_persistent)
+                                    : (tr ? (const void*)plain_wave_persistent_g_trace
+                                          : (const void*)plain_wave_persistent_g);
+      return hipLaunchCooperativeKernel(k, dim3(G), dim3(64), args, (unsigned)lds_bytes, s);
     }
-    if (a.stage_instr) hipLaunchKernelGGL(plain_wave_cycle, dim3(G), dim3(64), lds_bytes, s, a);
-    else hipLaunchKernelGGL(plain_wave_cycle_g, dim3(G), dim3(64), lds_bytes, s, a);
+    if (a.stage_instr) {
+      if (tr) hipLaunchKernelGGL(plain_wave_cycle_trace, dim3(G), dim3(64), lds_bytes, s, a);
+      else hipLaunchKernelGGL(plain_wave_cycle, dim3(G), dim3(64), lds_bytes, s, a);
+    } else {
+      if (tr) hipLaunchKernelGGL(plain_wave_cycle_g_trace, dim3(G), dim3(64), lds_bytes, s, a);
+      else hipLaunchKernelGGL(plain_wave_cycle_g, dim3(G), dim3(64), lds_bytes, s, a);
+    }
     return hipGetLastError();
   }
   if (persistent) {
@@ -534,9 +549,12 @@ hipError_t launch_plain(const PlainArgs& a, uint32_t G, uint32_t threads, size_t
 
 hipError_t plain_occupancy(int* blocks_per_cu, uint32_t threads, size_t lds_bytes, bool staged,
                            bool single_wave) {
+  // the traced variants use the most registers: a grid sized by them stays
+  // co-resident with tracing on or off
   if (single_wave)
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                        staged ? plain_wave_persistent : plain_wave_persistent_g,
+                                                        staged ? plain_wave_persistent_trace
+                                                               : plain_wave_persistent_g_trace,
                                                         64, lds_bytes);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, staged ? plain_persistent : plain_persistent_g,
                                                       (int)threads, lds_bytes);

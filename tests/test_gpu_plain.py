@@ -142,6 +142,36 @@ def test_core_full_size_single_wave(F, ctx):
     run_both(F, ctx, g.workload("core"), 500, 0, 2048, launch=3, threads=64, stage=2)
 
 
+@pytest.mark.parametrize("launch,stage,threads", [(3, 1, 64), (3, 2, 64), (1, 1, 64), (1, 2, 64), (3, 0, 256)])
+def test_phase_timestamps(F, ctx, launch, stage, threads):
+    """Phase timestamps (the traced kernel variants): results stay bit-exact
+    with tracing on, then off again, and each workgroup's stamps of a cycle
+    are ordered: start <= end of each level <= commit <= cycle end."""
+    nl = small_core()
+    cycles = 60
+    say(f"case trace: launch={launch} stage={stage} threads={threads}")
+    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=24)
+    s = F.Sim(d, 1, launch=launch, wg_threads=threads, seed=SEED, stage=stage)
+    s.enable_digest(2 * cycles)
+    s.enable_trace(cycles)
+    s.step(cycles)
+    tr = s.trace().astype(np.int64)            # [cycles][workgroups][stride]
+    s.enable_trace(0)
+    s.step(cycles)
+    ref = O.Sim(nl, seed=SEED)
+    assert np.array_equal(s.digests()[:, 0], ref.step(2 * cycles, digests=True))
+    assert np.array_equal(s.regs(), ref.regs())
+    start, commit, end = tr[:, :, 0], tr[:, :, -2], tr[:, :, -1]
+    assert (start > 0).all() and (commit >= start).all() and (end >= commit).all()
+    if threads == 64:
+        n_lv = int(d.info()["max_process_levels"])
+        for c in range(cycles):
+            for w in range(tr.shape[1]):
+                row = tr[c, w, 1:min(n_lv, tr.shape[2] - 2)]
+                row = row[row != 0]
+                assert (np.diff(row) >= 0).all() and (row >= start[c, w]).all() and (row <= commit[c, w]).all()
+
+
 def _pairs_inputs(n=4):
     pairs = list(itertools.product(range(2**n), repeat=2))
     return pairs, np.array(pairs, np.uint64)
