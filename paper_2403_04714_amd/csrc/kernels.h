@@ -34,6 +34,8 @@ struct PlainArgs {
   uint32_t R, I;
   uint32_t stage_instr;       // instructions staged in LDS
   uint32_t slot_words;        // u64 words of LDS reserved for slots
+  uint32_t ctab_words;        // one-wave kernel: u32 entries of the LDS chunk table after the slots
+                              // (the most chunks of any process + 3 zero entries, rounded up to 4)
   uint32_t instr_words;       // 16-byte instruction slots staged in LDS
   uint32_t chunk_words;       // u32 chunk words reserved in LDS
   uint64_t cycle0;            // absolute cycle at the first cycle of this launch

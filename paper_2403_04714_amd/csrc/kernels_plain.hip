@@ -242,14 +242,19 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   auto at = [slot_base](uint32_t off) -> uint64_t& { return *reinterpret_cast<uint64_t*>(slot_base + off); };
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
+  // after the slots: the process's chunk words (zero past the last chunk,
+  // read a few chunks ahead with one broadcast LDS read each), then the
+  // staged instructions
+  uint32_t* const ctab = reinterpret_cast<uint32_t*>(lds + A.slot_words);
+  char* const ibase = reinterpret_cast<char*>(ctab) + 4 * A.ctab_words;
   // instruction i of the process (LDS copy or global memory)
-  const uint4* const Is = STAGED ? reinterpret_cast<const uint4*>(lds + A.slot_words) : Ig;
+  const uint4* const Is = STAGED ? reinterpret_cast<const uint4*>(ibase) : Ig;
   // staging, eight loads in flight per lane (one memory latency per 512
   // instructions; the per-cycle launch modes stage on every launch)
   // (plain 16-byte words, not uint4: an array of the vector type is kept in
   // scratch memory by the compiler)
   const IWord* Igw = reinterpret_cast<const IWord*>(Ig);
-  IWord* Isw = reinterpret_cast<IWord*>(lds + A.slot_words);
+  IWord* Isw = reinterpret_cast<IWord*>(ibase);
   for (uint32_t base = 0; STAGED && base < n_all; base += 512) {
     IWord t[8];
 #pragma unroll
@@ -268,13 +273,10 @@ __device__ void plain_wave_body(const PlainArgs& A) {
     at(in.dst) = A.consts[in.aux];
   }
   const uint32_t n_ch = pp.n_chunks;
-  uint32_t cw[4];
-#pragma unroll
-  for (uint32_t q = 0; q < 4; ++q)
-    cw[q] = lane + 64 * q < n_ch ? A.chunks[pp.chunk_off + lane + 64 * q] : 0;
+  for (uint32_t i = lane; i < A.ctab_words; i += 64) ctab[i] = i < n_ch ? A.chunks[pp.chunk_off + i] : 0;
   // level starts, for the phase timestamps only
   const uint32_t n_lvls = pp.n_lvls;
-  const uint32_t lv_lo = lane <= n_lvls ? A.levels[pp.lvl_off + lane] : 0;
+  const uint32_t lv_lo = TRACE && lane <= n_lvls ? A.levels[pp.lvl_off + lane] : 0;
   if (lane == 0) abort_flag = 0;
   __syncthreads();
   // the first instruction of a chunk for this lane; lanes past the chunk's
@@ -307,18 +309,10 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         ++L_next;
       }
     };
-    uint32_t c = 0, c_base = 0;
-    uint32_t cr[4] = {cw[0], cw[1], cw[2], cw[3]};
-    auto rotate = [&]() {      // c has reached c_base + 64
-      cr[0] = cr[1];
-      cr[1] = cr[2];
-      cr[2] = cr[3];
-      c_base += 64;
-    };
-    auto word = [&](uint32_t cc) -> uint32_t {
-      const uint32_t v = cc - c_base < 64 ? cr[0] : cr[1];
-      return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(cc & 63));
-    };
+    uint32_t c = 0;
+    // chunk word cc, as a wave-uniform value (the read is issued where the
+    // word is loaded, the scalar copy taken where it is needed)
+    auto rfl = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
     // a leaf-load, sink-store or memory-read chunk whose first instruction
     // for this lane is `raw`
     auto other_chunk = [&](const uint4 raw, const uint32_t ch) {
@@ -375,9 +369,10 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         }
       }
     };
-    uint32_t ch = n_ch ? word(0) : 0;
     if (STAGED) {
-      // the next chunk's first instruction is read while this one runs
+      // the next chunk's first instruction is read while this one runs, and
+      // the chunk word two ahead
+      uint32_t ch = rfl(ctab[0]), chn = rfl(ctab[1]);
       uint4 raw = first_instr(ch);
       while (c < n_ch) {
         if ((ch >> 24) == I_ALU) {
@@ -385,30 +380,30 @@ __device__ void plain_wave_body(const PlainArgs& A) {
           // first instruction; only the operands are waited for
           do {
             const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
-            const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
             const Dec in = decode(raw);
             uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
             const uint4 rn = first_instr(chn);
+            const uint32_t w2 = ctab[c + 2];
             asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
             const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
             const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
             if (lane < cnt) at(in.dst) = r;
             ++c;
             ch = chn;
+            chn = rfl(w2);
             raw = rn;
-            if (c - c_base == 64) rotate();
-            if (trace_row) stamp(c);
+            if (TRACE && trace_row) stamp(c);
           } while (c < n_ch && (ch >> 24) == I_ALU);
           continue;
         }
-        const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
         const uint4 rn = first_instr(chn);
+        const uint32_t w2 = ctab[c + 2];
         other_chunk(raw, ch);
         ++c;
         ch = chn;
+        chn = rfl(w2);
         raw = rn;
-        if (c - c_base == 64) rotate();
-        if (trace_row) stamp(c);
+        if (TRACE && trace_row) stamp(c);
       }
     } else {
       // instructions from global memory: two slots hold the first
@@ -416,10 +411,10 @@ __device__ void plain_wave_body(const PlainArgs& A) {
       // refills it with chunk c + 2's, so every load has two chunks' time to
       // land.  The loop is unrolled by two so that no slot is ever copied
       // while its load is in flight (a copy would wait for it at once).
-      uint4 s0 = first_instr(ch), s1 = first_instr(n_ch > 1 ? word(1) : 0);
+      uint32_t ch = rfl(ctab[0]), chn = rfl(ctab[1]), ch2 = rfl(ctab[2]);
+      uint4 s0 = first_instr(ch), s1 = first_instr(chn);
       auto one = [&](uint4& slot) {
-        const uint32_t chn = c + 1 < n_ch ? word(c + 1) : 0;
-        const uint32_t ch2 = c + 2 < n_ch ? word(c + 2) : 0;
+        const uint32_t w3 = ctab[c + 3];
         if ((ch >> 24) == I_ALU) {
           const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
           const Dec in = decode(slot);
@@ -436,8 +431,9 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         }
         ++c;
         ch = chn;
-        if (c - c_base == 64) rotate();
-        if (trace_row) stamp(c);
+        chn = ch2;
+        ch2 = rfl(w3);
+        if (TRACE && trace_row) stamp(c);
       };
       while (c < n_ch) {
         one(s0);

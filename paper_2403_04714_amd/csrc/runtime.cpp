@@ -74,6 +74,11 @@ extern "C" int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_byt
 // ------------------------------------------------------------------- design
 static constexpr uint32_t kDefaultLds = 160 * 1024;
 static constexpr uint32_t kStaticLds = 1024;     // abort flag, reduction scratch
+// u32 entries of the one-wave kernel's LDS chunk table: every chunk of the
+// largest process, three zero entries for the words it reads ahead, rounded
+// up to a multiple of 4 so that the staged instructions after it stay
+// 16-byte aligned
+static uint32_t wave_ctab_words(const fsim_design* d) { return (d->max_chunks + 3 + 3) & ~3u; }
 
 template <class T>
 static int upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
@@ -417,11 +422,20 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
     lds += (size_t)d->max_proc_instr * sizeof(fsim::Instr);
   }
   if (lds > lds_limit) return fail(FSIM_E_CAPACITY, "process does not fit in LDS");
-  // one wave per process: the flat chunk loop (chunk words held in registers);
-  // its LDS holds the slots and, when staged, the instructions
+  // one wave per process: the flat chunk loop; its LDS holds the slots, the
+  // chunk table and, when staged, the instructions
   s->single_wave = s->threads == 64 && d->max_chunks <= 256;
-  if (s->single_wave)
-    lds = (size_t)d->slot_words * 8 + (s->stage_instr ? (size_t)d->max_proc_instr * sizeof(fsim::Instr) : 0);
+  if (s->single_wave) {
+    const size_t base = (size_t)d->slot_words * 8 + (size_t)wave_ctab_words(d) * 4;
+    const size_t instr = (size_t)d->max_proc_instr * sizeof(fsim::Instr);
+    if (s->stage_instr && base + instr > lds_limit) {
+      if (o.stage == FSIM_STAGE_LDS)
+        return fail(FSIM_E_CAPACITY, "plain form: a process's instructions do not fit in LDS beside its slots");
+      s->stage_instr = false;
+    }
+    lds = base + (s->stage_instr ? instr : 0);
+    if (lds > lds_limit) return fail(FSIM_E_CAPACITY, "process does not fit in LDS");
+  }
   s->lds_bytes = lds;
   if (s->launch == FSIM_LAUNCH_PERSISTENT) {
     int b = 0;
@@ -510,6 +524,7 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   a.I = dd->d.I;
   a.stage_instr = s->stage_instr ? 1 : 0;
   a.slot_words = dd->slot_words;
+  a.ctab_words = wave_ctab_words(dd);
   a.instr_words = dd->max_proc_instr;
   a.chunk_words = dd->max_chunks;
   a.single_wave = s->single_wave ? 1 : 0;
