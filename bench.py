@@ -394,7 +394,8 @@ def main():
     ap.add_argument("--profile-run", choices=["batched-core", "plain-core", "plain-prng"], default=None,
                     help="a short fixed run for hardware counters (per-cycle launches): batched "
                          "single-core x1024 on 4096 processes, plain single-core on 2048 one-wave "
-                         "processes, or 64 one-wave processes of 7 independent PRNG fibers")
+                         "processes reading instructions from global memory, or 64 one-wave "
+                         "processes of 7 independent PRNG fibers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of known size (the reference for HBM byte counters)")
     ap.add_argument("--study", choices=["prng", "scaling", "serving"], default=None,
@@ -425,7 +426,8 @@ def main():
             sim = F.Sim(d, 1024, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
         elif args.profile_run == "plain-core":
             d = F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=2048)
-            sim = F.Sim(d, 1, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
+            sim = F.Sim(d, 1, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE,
+                        stage=F.STAGE_GLOBAL)
         else:
             import numpy as np
             d = F.Design(ctx, g.prng_array(7 * 64), partition=np.arange(7 * 64, dtype=np.uint32) // 7)
