@@ -117,7 +117,8 @@ def bench_batched(F, g, tune, ctx, name, n_inst, targets, threads, cycles, warm,
     for t in targets:
         if t != best["target"]:
             del designs[t]
-    sim = F.Sim(d, n_inst, launch=F.LAUNCH_GRAPH, wg_threads=best["threads"], seed=seed)
+    tw = best.get("tiles_per_wave", 1)
+    sim = F.Sim(d, n_inst, launch=F.LAUNCH_GRAPH, wg_threads=best["threads"], seed=seed, tiles_per_wave=tw)
     gpu_s = time_sim(sim, ctx.torch_stream, cycles, warm)
     info = d.info()
     bpc, _ = algorithmic_bytes_per_cycle(nl, info["n_live_ops"], n_inst)
@@ -127,11 +128,12 @@ def bench_batched(F, g, tune, ctx, name, n_inst, targets, threads, cycles, warm,
     out = {"workload": f"{nl.name} x{n_inst}", "instances": n_inst, "cycles": cycles,
            "value": round(n_inst * cycles / gpu_s, 1), "unit": "instance-cycles/s",
            "us_per_cycle": round(gpu_s / cycles * 1e6, 2),
-           "roofline": {"bound": "alu", "kernel": "batched_cycle", "hbm_achieved_GBs": round(achieved, 2),
+           "roofline": {"bound": "alu", "kernel": "batched_cycle2" if tw == 2 else "batched_cycle",
+                        "hbm_achieved_GBs": round(achieved, 2),
                         "hbm_frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_cycle": bpc},
            "processes": int(info["n_processes"]), "dup_process": round(info["dup_process"], 4),
-           "workgroups": lay["workgroups"], "threads": lay["threads"],
-           "wave_lds_bytes": int(bi["wave_lds_bytes"]), "instructions": int(bi["n_instr"]),
+           "workgroups": lay["workgroups"], "threads": lay["threads"], "tiles_per_wave": tw,
+           "wave_lds_bytes": int(bi["wave_lds_bytes"]) * tw, "instructions": int(bi["n_instr"]),
            "compile_s": round(compile_s, 2)}
     del sim, d
     return out

@@ -208,6 +208,11 @@ typedef struct fsim_sim_opts {
   uint32_t graph_cycles;    /* cycles per captured graph (GRAPH mode)       */
   uint32_t form;            /* FSIM_FORM_*                                  */
   uint32_t stage;           /* plain form: FSIM_STAGE_*                     */
+  uint32_t tiles_per_wave;  /* batched form: tiles of 64 instances one wave
+                               interprets the program for (1 or 2; 0 = 1).
+                               With 2, fetch, decode and dispatch are shared
+                               by 128 instances and each wave needs twice
+                               the LDS                                       */
 } fsim_sim_opts;
 
 /* Device bytes a sim needs for n_instances (state x2, memories, outputs,

@@ -71,7 +71,8 @@ struct BatchArgs {
   uint64_t cycle0;
   uint32_t P, n_tiles, tpw, n_inst, n_pad, I;
   uint32_t nB, nW, nD;
-  uint32_t wave_bytes;        // LDS bytes of one wave's region (multiple of 16)
+  uint32_t wave_bytes;        // LDS bytes of one tile's region (multiple of 16)
+  uint32_t twave;             // tiles of 64 instances per wave (1 or 2)
 };
 
 hipError_t launch_batched(const BatchArgs& a, uint32_t grid, uint32_t threads, size_t lds_bytes,

@@ -95,25 +95,41 @@ __device__ __forceinline__ uint64_t vbit(uint32_t cls, uint64_t v, uint32_t lane
 }
 
 // A per-lane operator on zero-extended operands (not yet masked to its
-// width), as a tree of uniform tests; cheap neighbours are selected, not
-// branched to.
-__device__ __forceinline__ uint64_t alu_tree(uint32_t op, uint64_t a, uint64_t b, uint64_t c) {
-  uint64_t r;
+// width), for each of a wave's TW tiles, as one tree of uniform tests; cheap
+// neighbours are selected, not branched to.
+template <uint32_t TW>
+__device__ __forceinline__ void alu_tree(uint32_t op, const uint64_t (&a)[TW], const uint64_t (&b)[TW],
+                                         const uint64_t (&c)[TW], uint64_t (&r)[TW]) {
   if (op <= I_NOT) {
-    if (op <= I_OR) r = op == I_AND ? (a & b) : (a | b);
-    else r = op == I_XOR ? (a ^ b) : ~a;
+    if (op <= I_OR) {
+#pragma unroll
+      for (uint32_t t = 0; t < TW; ++t) r[t] = op == I_AND ? (a[t] & b[t]) : (a[t] | b[t]);
+    } else {
+#pragma unroll
+      for (uint32_t t = 0; t < TW; ++t) r[t] = op == I_XOR ? (a[t] ^ b[t]) : ~a[t];
+    }
   } else if (op <= I_MUX) {
-    if (op == I_ADD) r = a + b;
-    else if (op == I_SUB) r = a - b;
-    else r = a ? b : c;
+    if (op == I_ADD) {
+#pragma unroll
+      for (uint32_t t = 0; t < TW; ++t) r[t] = a[t] + b[t];
+    } else if (op == I_SUB) {
+#pragma unroll
+      for (uint32_t t = 0; t < TW; ++t) r[t] = a[t] - b[t];
+    } else {
+#pragma unroll
+      for (uint32_t t = 0; t < TW; ++t) r[t] = a[t] ? b[t] : c[t];
+    }
   } else if (op <= I_SHR) {
-    r = b >= 64 ? 0 : (op == I_SHL ? a << (b & 63) : a >> (b & 63));
+#pragma unroll
+    for (uint32_t t = 0; t < TW; ++t)
+      r[t] = b[t] >= 64 ? 0 : (op == I_SHL ? a[t] << (b[t] & 63) : a[t] >> (b[t] & 63));
   } else if (op <= I_LT) {
-    r = op == I_EQ ? (uint64_t)(a == b) : (uint64_t)(a < b);
+#pragma unroll
+    for (uint32_t t = 0; t < TW; ++t) r[t] = op == I_EQ ? (uint64_t)(a[t] == b[t]) : (uint64_t)(a[t] < b[t]);
   } else {
-    r = a * b;
+#pragma unroll
+    for (uint32_t t = 0; t < TW; ++t) r[t] = a[t] * b[t];
   }
-  return r;
 }
 
 // Store a per-lane result into a slot of class cls (never a constant).
@@ -129,15 +145,29 @@ __device__ __forceinline__ void vstore(char* base, uint32_t cls, uint32_t off, u
   }
 }
 
-// One simulated cycle of one (process, tile group) work item of a batched sim.
+// One simulated cycle of one (process, tile group) work item of a batched
+// sim.  Each wave interprets the process's instruction stream once for TW
+// tiles of 64 instances: fetch, decode and dispatch (the scalar work, which
+// bounds this kernel) are shared by the tiles, and only the per-lane data
+// work is repeated per tile.  A tile past the last one (ragged tile count)
+// repeats the last tile's reads and stores nothing.
+template <uint32_t TW>
 __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block, uint64_t cyc, char* lds) {
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t p = block % A.P, grp = block / A.P;
-  const uint32_t tile = grp * A.tpw + wave;
-  if (tile >= A.n_tiles) return;                 // no barriers below: a wave may leave early
-  const uint32_t inst = tile * 64 + lane;        // < n_pad
-  const bool real = inst < A.n_inst;
-  char* base = lds + (size_t)wave * A.wave_bytes;
+  const uint32_t tile0 = (grp * A.tpw + wave) * TW;
+  if (tile0 >= A.n_tiles) return;                // no barriers below: a wave may leave early
+  uint32_t tile[TW], inst[TW];
+  bool live[TW], real[TW];
+  char* base[TW];
+#pragma unroll
+  for (uint32_t t = 0; t < TW; ++t) {
+    live[t] = tile0 + t < A.n_tiles;             // wave-uniform
+    tile[t] = live[t] ? tile0 + t : A.n_tiles - 1;
+    inst[t] = tile[t] * 64 + lane;               // < n_pad
+    real[t] = live[t] && inst[t] < A.n_inst;
+    base[t] = lds + (size_t)(wave * TW + t) * A.wave_bytes;
+  }
   const BatchProc bp = A.procs[p];
   const uint4* prog = reinterpret_cast<const uint4*>(A.instr);
   // block b of this process: instructions instr_off + 64 b .. + 63, zero past
@@ -148,10 +178,13 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
   };
   const cptr<uint64_t> mem_off = as_const(A.mem_off);
   const cptr<uint32_t> mem_depth = as_const(A.mem_depth);
-  // the wave's region: the two constant masks, then the process's constants
-  if (lane < 2) reinterpret_cast<uint64_t*>(base)[lane] = lane ? ~0ull : 0ull;
-  for (uint32_t k = lane; k < bp.n_consts; k += 64)
-    reinterpret_cast<uint64_t*>(base + bp.kbase)[k] = A.consts[bp.const_off + k];
+  // each tile's region: the two constant masks, then the process's constants
+#pragma unroll
+  for (uint32_t t = 0; t < TW; ++t) {
+    if (lane < 2) reinterpret_cast<uint64_t*>(base[t])[lane] = lane ? ~0ull : 0ull;
+    for (uint32_t k = lane; k < bp.n_consts; k += 64)
+      reinterpret_cast<uint64_t*>(base[t] + bp.kbase)[k] = A.consts[bp.const_off + k];
+  }
   const uint32_t cur = cyc & 1, nxt = cur ^ 1;
   const cptr<uint64_t> stB_cur = as_const(A.stB + (size_t)cur * A.nB * A.n_tiles);
   uint64_t* stB_nxt = A.stB + (size_t)nxt * A.nB * A.n_tiles;
@@ -159,7 +192,9 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
   uint32_t* stW_nxt = A.stW + (size_t)nxt * A.nW * A.n_pad;
   const uint64_t* stD_cur = A.stD + (size_t)cur * A.nD * A.n_pad;
   uint64_t* stD_nxt = A.stD + (size_t)nxt * A.nD * A.n_pad;
-  uint64_t dacc = 0;
+  uint64_t dacc[TW];
+#pragma unroll
+  for (uint32_t t = 0; t < TW; ++t) dacc[t] = 0;
   const uint32_t lane4 = 4 * lane, lane8 = 8 * lane;
   uint32_t i = 0;
   uint4 bc = load_blk(0);
@@ -182,58 +217,99 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
       if (op >= K_MASK_AND && op <= K_MASK_MUX) {
         // every operand and the result are 64-instance masks
         const uint32_t y = rlane(bc.y, l), z = rlane(bc.z, l);
-        const uint64_t ma = mread(base, y >> 16), mb = mread(base, z & 0xFFFF);
-        uint64_t r;
-        if (op < K_MASK_NOT) {
-          if (op == K_MASK_AND) r = ma & mb;
-          else if (op == K_MASK_OR) r = ma | mb;
-          else r = ma ^ mb;                             // also 1-bit ADD and SUB (sums mod 2)
-        } else if (op < K_MASK_LT) {
-          r = op == K_MASK_NOT ? ~ma : ~(ma ^ mb);
-        } else if (op == K_MASK_LT) {
-          r = ~ma & mb;
-        } else {
-          r = (ma & mb) | (~ma & mread(base, z >> 16));   // MUX
+        uint64_t ma[TW], mb[TW], r[TW];
+#pragma unroll
+        for (uint32_t t = 0; t < TW; ++t) {
+          ma[t] = mread(base[t], y >> 16);
+          mb[t] = mread(base[t], z & 0xFFFF);
         }
-        if (lane == 0) *reinterpret_cast<uint64_t*>(base + (y & 0xFFFF)) = r;
+        if (op < K_MASK_NOT) {
+          if (op == K_MASK_AND) {
+#pragma unroll
+            for (uint32_t t = 0; t < TW; ++t) r[t] = ma[t] & mb[t];
+          } else if (op == K_MASK_OR) {
+#pragma unroll
+            for (uint32_t t = 0; t < TW; ++t) r[t] = ma[t] | mb[t];
+          } else {
+#pragma unroll
+            for (uint32_t t = 0; t < TW; ++t) r[t] = ma[t] ^ mb[t];   // also 1-bit ADD and SUB (sums mod 2)
+          }
+        } else if (op < K_MASK_LT) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) r[t] = op == K_MASK_NOT ? ~ma[t] : ~(ma[t] ^ mb[t]);
+        } else if (op == K_MASK_LT) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) r[t] = ~ma[t] & mb[t];
+        } else {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) r[t] = (ma[t] & mb[t]) | (~ma[t] & mread(base[t], z >> 16));   // MUX
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) *reinterpret_cast<uint64_t*>(base[t] + (y & 0xFFFF)) = r[t];
+        }
       } else if (op >= I_AND && op <= I_MUL) {
         // one value per lane: every operand load is issued before the first
         // is used, then 1-bit operands are taken out of their masks
         const uint32_t y = rlane(bc.y, l), z = rlane(bc.z, l);
         const uint32_t cls = (x >> 16) & 0xFF, w = (x >> 8) & 0xFF;
         const uint32_t ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = cls >> 6;
-        uint64_t a = vload(base, ca, y >> 16, lane4, lane8);
-        uint64_t b = vload(base, cb, z & 0xFFFF, lane4, lane8);
-        uint64_t c = 0;
-        if (op == I_MUX) c = vload(base, cc, z >> 16, lane4, lane8);
-        a = vbit(ca, a, lane);
-        b = vbit(cb, b, lane);
-        if (op == I_MUX) c = vbit(cc, c, lane);
-        uint64_t r = alu_tree(op, a, b, c);
-        if (w < 64) r &= wmask(w);
-        vstore(base, cls & 3, y & 0xFFFF, r, lane4, lane8, lane);
+        uint64_t a[TW], b[TW], c[TW], r[TW];
+#pragma unroll
+        for (uint32_t t = 0; t < TW; ++t) {
+          a[t] = vload(base[t], ca, y >> 16, lane4, lane8);
+          b[t] = vload(base[t], cb, z & 0xFFFF, lane4, lane8);
+          c[t] = 0;
+        }
+        if (op == I_MUX) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) c[t] = vload(base[t], cc, z >> 16, lane4, lane8);
+        }
+#pragma unroll
+        for (uint32_t t = 0; t < TW; ++t) {
+          a[t] = vbit(ca, a[t], lane);
+          b[t] = vbit(cb, b[t], lane);
+        }
+        if (op == I_MUX) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) c[t] = vbit(cc, c[t], lane);
+        }
+        alu_tree<TW>(op, a, b, c, r);
+        if (w < 64) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) r[t] &= wmask(w);
+        }
+        const uint32_t cd = cls & 3, dst = y & 0xFFFF;
+#pragma unroll
+        for (uint32_t t = 0; t < TW; ++t) vstore(base[t], cd, dst, r[t], lane4, lane8, lane);
       } else if (op >= K_LDREG_B) {
         // a run of same-class register loads inside the current block: the
         // register index (aux) and the slot offset (dst) of each load come
         // straight from the block registers; loads first, then the stores
         const uint32_t n = (x >> 24) & 0xFF;
-        uint64_t v[kLeafRun];
+        uint64_t v[kLeafRun][TW];
 #pragma unroll
         for (uint32_t k = 0; k < kLeafRun; ++k) {
           if (k < n) {
             const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)bc.w, (int)((i + k) & 63));
-            if (op == K_LDREG_D) v[k] = (stD_cur + (size_t)r * A.n_pad)[inst];
-            else if (op == K_LDREG_W) v[k] = (stW_cur + (size_t)r * A.n_pad)[inst];
-            else v[k] = stB_cur[(size_t)r * A.n_tiles + tile];
+#pragma unroll
+            for (uint32_t t = 0; t < TW; ++t) {
+              if (op == K_LDREG_D) v[k][t] = (stD_cur + (size_t)r * A.n_pad)[inst[t]];
+              else if (op == K_LDREG_W) v[k][t] = (stW_cur + (size_t)r * A.n_pad)[inst[t]];
+              else v[k][t] = stB_cur[(size_t)r * A.n_tiles + tile[t]];
+            }
           }
         }
 #pragma unroll
         for (uint32_t k = 0; k < kLeafRun; ++k) {
           if (k < n) {
             const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)bc.y, (int)((i + k) & 63)) & 0xFFFF;
-            if (op == K_LDREG_D) *reinterpret_cast<uint64_t*>(base + o + 8 * lane) = v[k];
-            else if (op == K_LDREG_W) *reinterpret_cast<uint32_t*>(base + o + 4 * lane) = (uint32_t)v[k];
-            else if (lane == 0) *reinterpret_cast<uint64_t*>(base + o) = v[k];
+#pragma unroll
+            for (uint32_t t = 0; t < TW; ++t) {
+              if (op == K_LDREG_D) *reinterpret_cast<uint64_t*>(base[t] + o + lane8) = v[k][t];
+              else if (op == K_LDREG_W) *reinterpret_cast<uint32_t*>(base[t] + o + lane4) = (uint32_t)v[k][t];
+              else if (lane == 0) *reinterpret_cast<uint64_t*>(base[t] + o) = v[k][t];
+            }
           }
         }
         step = n;
@@ -243,120 +319,133 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
         const uint32_t w = (x >> 8) & 0xFF, cls = (x >> 16) & 0xFF;
         const uint32_t cd = cls & 3, ca = (cls >> 2) & 3, cb = (cls >> 4) & 3, cc = (cls >> 6) & 3;
         const uint32_t dst = y & 0xFFFF, oa = y >> 16, ob = z & 0xFFFF, oc = z >> 16;
-        switch (op) {
-          case I_LDREG:
-          case I_LDIN: {
-            // a run of up to kLeafRun leaf loads (length in flags): every load is issued
-            // before any result is used, so the run costs one memory latency.  A
-            // shorter run repeats its last leaf (the same value to the same slot):
-            // every unrolled load is then used on every path, where a load left
-            // unused on some path would make every later handler wait for all
-            // outstanding memory operations.
-            const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
-            uint64_t val[kLeafRun];
+        if (op == I_LDREG || op == I_LDIN) {
+          // a run of up to kLeafRun leaf loads (length in flags): every load is
+          // issued before any result is used, so the run costs one memory
+          // latency.  A shorter run repeats its last leaf (the same value to
+          // the same slot): every unrolled load is then used on every path,
+          // where a load left unused on some path would make every later
+          // handler wait for all outstanding memory operations.
+          const uint32_t n = ((x >> 24) & 0xFF) ? ((x >> 24) & 0xFF) : 1;
+          uint64_t val[kLeafRun][TW];
 #pragma unroll
-            for (uint32_t k = 0; k < kLeafRun; ++k) {
-              {
-                const IWord qk = instr(i + (k < n ? k : n - 1));
-                const uint32_t xk = qk.x, auxk = qk.w;
-                const uint32_t cak = (xk >> 18) & 3;
-                if ((xk & 0xFF) == I_LDREG) {
-                  val[k] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile]
-                         : cak == C_W ? (uint64_t)stW_cur[(size_t)auxk * A.n_pad + inst]
-                                      : stD_cur[(size_t)auxk * A.n_pad + inst];
-                } else if (A.in_vals) {
-                  val[k] = (real && cyc >= A.in_first && cyc < A.in_first + A.in_count)
-                               ? A.in_vals[((cyc - A.in_first) * A.I + auxk) * A.n_inst + inst] : 0;
-                } else {
-                  val[k] = A.keys[(size_t)auxk * A.n_pad + inst];
-                }
+          for (uint32_t k = 0; k < kLeafRun; ++k) {
+            const IWord qk = instr(i + (k < n ? k : n - 1));
+            const uint32_t xk = qk.x, auxk = qk.w;
+            const uint32_t cak = (xk >> 18) & 3;
+#pragma unroll
+            for (uint32_t t = 0; t < TW; ++t) {
+              if ((xk & 0xFF) == I_LDREG) {
+                val[k][t] = cak == C_B ? stB_cur[(size_t)auxk * A.n_tiles + tile[t]]
+                          : cak == C_W ? (uint64_t)stW_cur[(size_t)auxk * A.n_pad + inst[t]]
+                                       : stD_cur[(size_t)auxk * A.n_pad + inst[t]];
+              } else if (A.in_vals) {
+                val[k][t] = (real[t] && cyc >= A.in_first && cyc < A.in_first + A.in_count)
+                                ? A.in_vals[((cyc - A.in_first) * A.I + auxk) * A.n_inst + inst[t]] : 0;
+              } else {
+                val[k][t] = A.keys[(size_t)auxk * A.n_pad + inst[t]];
               }
             }
-#pragma unroll
-            for (uint32_t k = 0; k < kLeafRun; ++k) {
-              {
-                const IWord qk = instr(i + (k < n ? k : n - 1));
-                const uint32_t xk = qk.x, yk = qk.y;
-                const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
-                const uint32_t dk = yk & 0xFFFF;
-                if ((xk & 0xFF) == I_LDREG) {
-                  if (cak == C_B) {
-                    if (cdk == C_B) {
-                      // the mask is wave-uniform: taken into scalar registers here,
-                      // outside the one-lane store
-                      const uint64_t m = ((uint64_t)rlane((uint32_t)(val[k] >> 32), 0) << 32) |
-                                         rlane((uint32_t)val[k], 0);
-                      if (lane == 0) *reinterpret_cast<uint64_t*>(base + dk) = m;
-                    }
-                    else lwrite(base, cdk, dk, lane, (val[k] >> lane) & 1);
-                  } else {
-                    lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
-                  }
-                } else {
-                  if (A.in_vals) {
-                    if (cyc < A.in_first || cyc >= A.in_first + A.in_count) atomicOr(&A.error[1], 1u);
-                    lwrite(base, cdk, dk, lane, val[k] & wmask(wk));
-                  } else {
-                    lwrite(base, cdk, dk, lane, hmix(val[k] ^ cyc) & wmask(wk));
-                  }
-                }
-              }
-            }
-            step = n;
-            break;
           }
-          case I_MEMRD: {
-            const uint64_t a = lread(base, ca, oa, lane);
+#pragma unroll
+          for (uint32_t k = 0; k < kLeafRun; ++k) {
+            const IWord qk = instr(i + (k < n ? k : n - 1));
+            const uint32_t xk = qk.x, yk = qk.y;
+            const uint32_t wk = (xk >> 8) & 0xFF, cdk = (xk >> 16) & 3, cak = (xk >> 18) & 3;
+            const uint32_t dk = yk & 0xFFFF;
+#pragma unroll
+            for (uint32_t t = 0; t < TW; ++t) {
+              if ((xk & 0xFF) == I_LDREG) {
+                if (cak == C_B) {
+                  if (cdk == C_B) {
+                    // the mask is wave-uniform: taken into scalar registers here,
+                    // outside the one-lane store
+                    const uint64_t m = ((uint64_t)rlane((uint32_t)(val[k][t] >> 32), 0) << 32) |
+                                       rlane((uint32_t)val[k][t], 0);
+                    if (lane == 0) *reinterpret_cast<uint64_t*>(base[t] + dk) = m;
+                  } else {
+                    lwrite(base[t], cdk, dk, lane, (val[k][t] >> lane) & 1);
+                  }
+                } else {
+                  lwrite(base[t], cdk, dk, lane, val[k][t] & wmask(wk));
+                }
+              } else {
+                if (A.in_vals) {
+                  if (live[t] && (cyc < A.in_first || cyc >= A.in_first + A.in_count)) atomicOr(&A.error[1], 1u);
+                  lwrite(base[t], cdk, dk, lane, val[k][t] & wmask(wk));
+                } else {
+                  lwrite(base[t], cdk, dk, lane, hmix(val[k][t] ^ cyc) & wmask(wk));
+                }
+              }
+            }
+          }
+          step = n;
+        } else if (op == I_MEMRD) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) {
+            const uint64_t a = lread(base[t], ca, oa, lane);
             const uint64_t depth = mem_depth[aux];
             const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-            lwrite(base, cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst] & wmask(w));
-            break;
+            lwrite(base[t], cd, dst, lane, A.mem[(mem_off[aux] + addr) * A.n_pad + inst[t]] & wmask(w));
           }
-          case I_STREG: {
-            // cd: class of the register's state array, ca: class of the value
-            const uint64_t v = lread(base, ca, oa, lane) & wmask(w);
+        } else if (op == I_STREG) {
+          // cd: class of the register's state array, ca: class of the value
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) {
+            const uint64_t v = lread(base[t], ca, oa, lane) & wmask(w);
             if (cd == C_B) {
               const uint64_t m = __ballot(v & 1);
-              if (lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile] = m;
+              if (live[t] && lane == 0) stB_nxt[(size_t)aux * A.n_tiles + tile[t]] = m;
             } else if (cd == C_W) {
-              stW_nxt[(size_t)aux * A.n_pad + inst] = (uint32_t)v;
+              if (live[t]) stW_nxt[(size_t)aux * A.n_pad + inst[t]] = (uint32_t)v;
             } else {
-              stD_nxt[(size_t)aux * A.n_pad + inst] = v;
+              if (live[t]) stD_nxt[(size_t)aux * A.n_pad + inst[t]] = v;
             }
-            if (A.digest) dacc += hmix((uint64_t)(ob | (oc << 16)) ^ hmix(v));
-            break;
+            if (A.digest) dacc[t] += hmix((uint64_t)(ob | (oc << 16)) ^ hmix(v));
           }
-          case I_STOUT:
-            A.outputs[(size_t)aux * A.n_pad + inst] = lread(base, ca, oa, lane) & wmask(w);
-            break;
-          case I_WPORT: {
-            const uint64_t en = lread(base, ca, oa, lane), a = lread(base, cb, ob, lane);
-            const uint64_t v = lread(base, cc, oc, lane);
-            if (en) {
+        } else if (op == I_STOUT) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) {
+            const uint64_t v = lread(base[t], ca, oa, lane) & wmask(w);
+            if (live[t]) A.outputs[(size_t)aux * A.n_pad + inst[t]] = v;
+          }
+        } else if (op == I_WPORT) {
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) {
+            const uint64_t en = lread(base[t], ca, oa, lane), a = lread(base[t], cb, ob, lane);
+            const uint64_t v = lread(base[t], cc, oc, lane);
+            if (live[t] && en) {
               const uint64_t depth = mem_depth[aux];
               const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-              A.mem[(mem_off[aux] + addr) * A.n_pad + inst] = v & wmask(w);
+              A.mem[(mem_off[aux] + addr) * A.n_pad + inst[t]] = v & wmask(w);
             }
-            break;
           }
-          default:
-            break;
         }
       }
       i += step;
     }
     bc = bn;
   }
-  if (A.digest && real) {
+  if (A.digest) {
     const uint64_t k = cyc - A.digest_first;
-    if (k < A.digest_max) atomicAdd((unsigned long long*)&A.digest[k * A.n_inst + inst], (unsigned long long)dacc);
+#pragma unroll
+    for (uint32_t t = 0; t < TW; ++t)
+      if (real[t] && k < A.digest_max)
+        atomicAdd((unsigned long long*)&A.digest[k * A.n_inst + inst[t]], (unsigned long long)dacc[t]);
   }
 }
 
 __global__ void __launch_bounds__(256) batched_cycle(BatchArgs A) {
   extern __shared__ uint64_t lds[];
   const uint64_t cyc = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
-  batched_body(A, blockIdx.x, cyc, reinterpret_cast<char*>(lds));
+  batched_body<1>(A, blockIdx.x, cyc, reinterpret_cast<char*>(lds));
+}
+
+// two tiles (128 instances) per wave
+__global__ void __launch_bounds__(256) batched_cycle2(BatchArgs A) {
+  extern __shared__ uint64_t lds[];
+  const uint64_t cyc = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
+  batched_body<2>(A, blockIdx.x, cyc, reinterpret_cast<char*>(lds));
 }
 
 // Serving: one launch advances every resident job by one cycle.  Job j owns
@@ -378,7 +467,7 @@ __global__ void __launch_bounds__(64) batched_multi(const BatchArgs* __restrict_
   const uint32_t j = lo;
   if (tick >= ticks[j]) return;
   const BatchArgs A = jobs[j];
-  batched_body(A, blockIdx.x - wg_start[j], cycle_base[j] + tick, reinterpret_cast<char*>(lds));
+  batched_body<1>(A, blockIdx.x - wg_start[j], cycle_base[j] + tick, reinterpret_cast<char*>(lds));
 }
 
 // One instance's column of an instance-minor [rows][pitch] table, gathered
@@ -402,7 +491,8 @@ namespace fsim {
 
 hipError_t launch_batched(const BatchArgs& a, uint32_t grid, uint32_t threads, size_t lds_bytes,
                           hipStream_t s) {
-  hipLaunchKernelGGL(batched_cycle, dim3(grid), dim3(threads), lds_bytes, s, a);
+  if (a.twave == 2) hipLaunchKernelGGL(batched_cycle2, dim3(grid), dim3(threads), lds_bytes, s, a);
+  else hipLaunchKernelGGL(batched_cycle, dim3(grid), dim3(threads), lds_bytes, s, a);
   return hipGetLastError();
 }
 

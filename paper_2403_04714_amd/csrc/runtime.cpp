@@ -345,10 +345,12 @@ static int sim_create_batched(fsim_sim* s, void* workspace, size_t ws_bytes, con
   if (s->tpw < 1 || s->tpw > 4 || (o.wg_threads && o.wg_threads % 64))
     return fail(FSIM_E_ARG, "batched form: wg_threads must be 64, 128, 192 or 256");
   s->threads = 64 * s->tpw;
+  s->twave = o.tiles_per_wave ? o.tiles_per_wave : 1;
+  if (s->twave > 2) return fail(FSIM_E_ARG, "batched form: tiles_per_wave must be 1 or 2");
   s->launch = o.launch ? o.launch : FSIM_LAUNCH_GRAPH;
   if (s->launch == FSIM_LAUNCH_PERSISTENT) s->launch = FSIM_LAUNCH_GRAPH;   // kernel boundary is the barrier
   s->graph_cycles = o.graph_cycles ? o.graph_cycles : 64;
-  s->lds_bytes = batched_wave_bytes(D) * s->tpw;
+  s->lds_bytes = batched_wave_bytes(D) * s->tpw * s->twave;
   if (s->lds_bytes > d->ctx->lds_bytes)
     return fail(FSIM_E_CAPACITY, "batched form: a process's live values exceed LDS (" +
                                      std::to_string(s->lds_bytes) + " bytes); use more processes");
@@ -555,11 +557,13 @@ fsim::BatchArgs fsim::batch_args(fsim_sim* s) {
   a.P = D.P; a.n_tiles = s->n_tiles; a.tpw = s->tpw; a.n_inst = s->n_inst; a.n_pad = s->n_pad; a.I = D.I;
   a.nB = D.reg_count[0]; a.nW = D.reg_count[1]; a.nD = D.reg_count[2];
   a.wave_bytes = D.batch_wave_bytes;
+  a.twave = s->twave;
   return a;
 }
 
 uint32_t fsim::batch_grid(const fsim_sim* s) {
-  return s->d->d.P * ((s->n_tiles + s->tpw - 1) / s->tpw);
+  const uint32_t per_wg = s->tpw * s->twave;   // tiles per workgroup
+  return s->d->d.P * ((s->n_tiles + per_wg - 1) / per_wg);
 }
 
 static int build_graph(fsim_sim* s) {

@@ -72,7 +72,7 @@ struct fsim_sim {
   fsim_design* d = nullptr;
   uint32_t n_inst = 1;
   bool batched = false;
-  uint32_t n_tiles = 1, n_pad = 64, tpw = 1;
+  uint32_t n_tiles = 1, n_pad = 64, tpw = 1, twave = 1;
   uint64_t *stB = nullptr, *stD = nullptr;
   uint32_t* stW = nullptr;
   uint32_t G = 1, threads = 256, launch = FSIM_LAUNCH_PERSISTENT, graph_cycles = 64;

@@ -71,7 +71,8 @@ class DesignInfo(C.Structure):
 
 class SimOpts(C.Structure):
     _fields_ = [("launch", C.c_uint32), ("wg_threads", C.c_uint32), ("grid", C.c_uint32),
-                ("graph_cycles", C.c_uint32), ("form", C.c_uint32), ("stage", C.c_uint32)]
+                ("graph_cycles", C.c_uint32), ("form", C.c_uint32), ("stage", C.c_uint32),
+                ("tiles_per_wave", C.c_uint32)]
 
 
 # every symbol include/fibersim.h declares, with its signature
@@ -277,7 +278,7 @@ class Sim:
 
     def __init__(self, design: Design, n_instances: int = 1, launch=LAUNCH_AUTO,
                  wg_threads=0, grid=0, graph_cycles=0, seed=None, use_torch_workspace=True,
-                 form=FORM_AUTO, stage=STAGE_AUTO):
+                 form=FORM_AUTO, stage=STAGE_AUTO, tiles_per_wave=0):
         import torch
         self.design = design
         self.n_instances = n_instances
@@ -290,7 +291,7 @@ class Sim:
             base = self._ws.data_ptr()
             ws_ptr = (base + 255) // 256 * 256
             ws_bytes = fp.value
-        o = SimOpts(launch, wg_threads, grid, graph_cycles, form, stage)
+        o = SimOpts(launch, wg_threads, grid, graph_cycles, form, stage, tiles_per_wave)
         h = C.c_void_p()
         _check(lib().fsim_sim_create(design._h, n_instances, ws_ptr, ws_bytes, C.byref(o), C.byref(h)),
                "fsim_sim_create")

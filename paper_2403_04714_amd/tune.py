@@ -114,10 +114,11 @@ def tune_plain(ctx, nl, targets=(16, 32, 64, 128, 256), threads=(256, 512, 1024)
     return best, trials
 
 
-def time_batched(ctx, design, n_inst, threads, cycles, seed=0x5EED0000, reps=2):
+def time_batched(ctx, design, n_inst, threads, cycles, seed=0x5EED0000, reps=2, tiles_per_wave=0):
     """Seconds per simulated cycle of the batched form (all n_inst instances)."""
     import torch
-    s = F.Sim(design, n_inst, launch=F.LAUNCH_GRAPH, wg_threads=threads, seed=seed)
+    s = F.Sim(design, n_inst, launch=F.LAUNCH_GRAPH, wg_threads=threads, seed=seed,
+              tiles_per_wave=tiles_per_wave)
     s.step(min(64, cycles))
     s.sync()
     best = float("inf")
@@ -134,9 +135,10 @@ def time_batched(ctx, design, n_inst, threads, cycles, seed=0x5EED0000, reps=2):
 
 
 def tune_batched(ctx, nl, n_inst, targets=(256, 512, 1024, 2048), threads=(64, 128, 256),
-                 cycles=256, use_cache=True, verbose=False, designs=None):
-    """Batched-form autotuner: packing target and tiles of 64 instances per
-    workgroup.  Returns (best, trials); best has s_per_cycle for all instances."""
+                 cycles=256, use_cache=True, verbose=False, designs=None, tiles=(1, 2)):
+    """Batched-form autotuner: packing target, tiles of 64 instances per
+    workgroup and per wave.  Returns (best, trials); best has s_per_cycle for
+    all instances."""
     key = f"batched/{design_hash(nl)}/{n_inst}/{_device_name()}"
     cache = _load_cache() if use_cache else {}
     if key in cache:
@@ -149,17 +151,17 @@ def tune_batched(ctx, nl, n_inst, targets=(256, 512, 1024, 2048), threads=(64, 1
             if verbose:
                 print(f"tune: target {t}: {e}", flush=True)
             continue
-        for th in threads:
-            if th > 64 * ((n_inst + 63) // 64):
+        for th, tw in [(th, tw) for th in threads for tw in tiles]:
+            if th * tw > 64 * ((n_inst + 63) // 64):
                 continue
             try:
-                spc = time_batched(ctx, d, n_inst, th, cycles)
+                spc = time_batched(ctx, d, n_inst, th, cycles, tiles_per_wave=tw)
             except F.FsimError as e:
                 if verbose:
-                    print(f"tune: target {t} threads {th}: {e}", flush=True)
+                    print(f"tune: target {t} threads {th} tiles/wave {tw}: {e}", flush=True)
                 continue
-            rec = dict(target=t, processes=d.info()["n_processes"], threads=th, s_per_cycle=spc,
-                       inst_cycles_per_s=n_inst / spc)
+            rec = dict(target=t, processes=d.info()["n_processes"], threads=th, tiles_per_wave=tw,
+                       s_per_cycle=spc, inst_cycles_per_s=n_inst / spc)
             trials.append(rec)
             if verbose:
                 print(f"tune: {rec}", flush=True)

@@ -30,11 +30,11 @@ def say(*a):
 
 
 def check_batched(F, ctx, nl, n_inst, cycles, target=0, threads=0, launch=0, full_state=None,
-                  chunks=(None,), seed=SEED, digest_insts=None):
+                  chunks=(None,), seed=SEED, digest_insts=None, tiles_per_wave=0):
     say(f"case {nl.name}: batched n_inst={n_inst} target={target} threads={threads} "
-        f"launch={launch} cycles={cycles}")
+        f"launch={launch} tiles_per_wave={tiles_per_wave} cycles={cycles}")
     d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=target)
-    s = F.Sim(d, n_inst, launch=launch, wg_threads=threads, seed=seed)
+    s = F.Sim(d, n_inst, launch=launch, wg_threads=threads, seed=seed, tiles_per_wave=tiles_per_wave)
     s.enable_digest(cycles)
     done = 0
     for c in chunks:
@@ -95,6 +95,42 @@ def test_core_full_size_sampled(F, ctx):
     of instances every cycle and their full state."""
     check_batched(F, ctx, g.workload("core"), 128, 60, target=512, full_state={0, 127},
                   digest_insts=[0, 1, 77, 127])
+
+
+# two tiles (128 instances) per wave: instance counts that fill both tiles,
+# leave the second tile of the last wave empty (ragged: 1, 3 or 5 tiles), or
+# end inside a tile; workgroups of 1, 2 and 4 waves; memories; full size
+@pytest.mark.parametrize("n_inst,threads", [(1, 0), (64, 0), (65, 64), (130, 0), (200, 128), (320, 256)])
+def test_two_tiles_per_wave(F, ctx, n_inst, threads):
+    check_batched(F, ctx, g.gen_tiny(9), n_inst, 140, target=7, threads=threads, tiles_per_wave=2,
+                  full_state={0, n_inst - 1})
+
+
+def test_two_tiles_per_wave_memories_and_chunks(F, ctx):
+    check_batched(F, ctx, small_core(), 190, 150, target=40, launch=3, chunks=(3, 64, None),
+                  tiles_per_wave=2, full_state={0, 64, 127, 128, 189})
+
+
+def test_two_tiles_per_wave_core_full_size(F, ctx):
+    check_batched(F, ctx, g.workload("core"), 256, 40, target=4096, threads=256, tiles_per_wave=2,
+                  full_state={0, 255}, digest_insts=[0, 63, 64, 127, 128, 255])
+
+
+def test_two_tiles_per_wave_explicit_inputs(F, ctx):
+    """Gate-level 4-bit adder with explicit per-instance inputs, 200 instances
+    (the last wave's second tile half full)."""
+    nl = g.ripple_adder(4)
+    d = F.Design(ctx, nl, pack=F.PACK_SINGLE)
+    n = 200
+    s = F.Sim(d, n, tiles_per_wave=2)
+    T = 8
+    rng = np.random.default_rng(4)
+    vals = rng.integers(0, 16, (T, 2, n)).astype(np.uint64)
+    s.set_inputs(0, vals)
+    for t in range(T):
+        s.step(1)
+        for i in (0, 63, 64, 127, 128, 199):
+            assert int(s.regs(i)[0]) == int(vals[t, 0, i] + vals[t, 1, i]), (t, i)
 
 
 def test_batched_single_instance_equals_plain(F, ctx):
