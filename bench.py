@@ -27,6 +27,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X published HBM3E bandwidth
 
+# packing policies the autotuner tries: bottom-up SLB (Sec. 5.1) and the
+# hypergraph alternative (Sec. 6.6)
+PACKS = (0, 3)
+PACK_NAMES = {0: "slb", 1: "fibers", 2: "single", 3: "hypergraph"}
+
 
 def algorithmic_bytes_per_cycle(nl, n_live_ops, n_instances=1):
     """Bytes the method itself must move per simulated cycle: read the
@@ -109,14 +114,12 @@ def bench_batched(F, g, tune, ctx, name, n_inst, targets, threads, cycles, warm,
     packing target and threads per workgroup autotuned."""
     nl = g.workload(name)
     t0 = time.time()
-    designs = {t: F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=t) for t in targets}
+    designs = {(pk, t): F.Design(ctx, nl, pack=pk, target_processes=t) for pk in PACKS for t in targets}
     compile_s = time.time() - t0
     best, _ = tune.tune_batched(ctx, nl, n_inst, targets=targets, threads=threads, cycles=32,
-                                use_cache=False, designs=designs)
-    d = designs[best["target"]]
-    for t in targets:
-        if t != best["target"]:
-            del designs[t]
+                                use_cache=False, designs=designs, packs=PACKS)
+    d = designs.pop((best["pack"], best["target"]))
+    designs.clear()
     tw = best.get("tiles_per_wave", 1)
     sim = F.Sim(d, n_inst, launch=F.LAUNCH_GRAPH, wg_threads=best["threads"], seed=seed, tiles_per_wave=tw)
     gpu_s = time_sim(sim, ctx.torch_stream, cycles, warm)
@@ -131,7 +134,8 @@ def bench_batched(F, g, tune, ctx, name, n_inst, targets, threads, cycles, warm,
            "roofline": {"bound": "alu", "kernel": "batched_cycle2" if tw == 2 else "batched_cycle",
                         "hbm_achieved_GBs": round(achieved, 2),
                         "hbm_frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_cycle": bpc},
-           "processes": int(info["n_processes"]), "dup_process": round(info["dup_process"], 4),
+           "pack": PACK_NAMES[best["pack"]], "processes": int(info["n_processes"]),
+           "dup_process": round(info["dup_process"], 4),
            "workgroups": lay["workgroups"], "threads": lay["threads"], "tiles_per_wave": tw,
            "wave_lds_bytes": int(bi["wave_lds_bytes"]) * tw, "instructions": int(bi["n_instr"]),
            "compile_s": round(compile_s, 2)}
@@ -146,9 +150,9 @@ def bench_plain_tuned(F, g, tune, ctx, name, targets, threads, cycles, warm, see
     nl = g.workload(name)
     t0 = time.time()
     best, _ = tune.tune_plain(ctx, nl, targets=targets, threads=threads, launches=(F.LAUNCH_GRAPH,),
-                              cycles=500, use_cache=False)
+                              cycles=500, use_cache=False, packs=PACKS)
     tune_s = time.time() - t0
-    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=best["target"])
+    d = F.Design(ctx, nl, pack=best["pack"], target_processes=best["target"])
     sim = F.Sim(d, 1, launch=best["launch"], wg_threads=best["threads"], seed=seed,
                 stage=best.get("stage", F.STAGE_AUTO))
     gpu_s = time_sim(sim, ctx.torch_stream, cycles, warm)
@@ -156,7 +160,8 @@ def bench_plain_tuned(F, g, tune, ctx, name, targets, threads, cycles, warm, see
     lay = sim.layout()
     out = {"workload": f"{nl.name} x1", "instances": 1, "cycles": cycles,
            "value": round(cycles / gpu_s, 1), "unit": "instance-cycles/s",
-           "us_per_cycle": round(gpu_s / cycles * 1e6, 2), "processes": int(info["n_processes"]),
+           "us_per_cycle": round(gpu_s / cycles * 1e6, 2), "pack": PACK_NAMES[best["pack"]],
+           "processes": int(info["n_processes"]),
            "workgroups": lay["workgroups"], "threads": lay["threads"],
            "process_levels": int(info["max_process_levels"]) + 2,
            "dup_process": round(info["dup_process"], 4), "compile_s": round(info["compile_seconds"], 2),
@@ -182,9 +187,11 @@ def barrier_estimate(F, sim, cycles=24):
             "barrier_us": round(float(np.median(period) - np.median(comp[1:])), 3)}
 
 
-def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=32768, cycles=200):
+def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=32768, cycles=200,
+                batched_packs=(0, 3)):
     """The 48-tile SoC: compile statistics (duplication overhead), the plain
-    form at one instance and the batched form at 64 instances."""
+    form at one instance and the batched form at 64 instances.  A plain
+    config is (target, threads[, stage[, pack]])."""
     nl = g.workload("soc48")
     out = {"workload": nl.name, "registers": int(nl.n_regs), "word_ops": int(nl.n_comb_ops()),
            "memories": int(nl.n_mems), "plain": [], "batched": None}
@@ -192,13 +199,14 @@ def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=32768,
     for cfg in plain_cfgs:
         target, threads = cfg[0], cfg[1]
         stage = cfg[2] if len(cfg) > 2 else F.STAGE_AUTO
-        if target not in designs:
-            designs[target] = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=target)
-        d = designs[target]
+        pack = cfg[3] if len(cfg) > 3 else F.PACK_SLB
+        if (pack, target) not in designs:
+            designs[(pack, target)] = F.Design(ctx, nl, pack=pack, target_processes=target)
+        d = designs[(pack, target)]
         info = d.info()
         sim = F.Sim(d, 1, launch=F.LAUNCH_GRAPH, wg_threads=threads, seed=seed, stage=stage)
         gpu_s = time_sim(sim, ctx.torch_stream, cycles, 20)
-        rec = {"processes": int(info["n_processes"]), "threads": threads,
+        rec = {"pack": PACK_NAMES[pack], "processes": int(info["n_processes"]), "threads": threads,
                "instructions_in_lds": bool(sim.layout()["staged"]),
                "value": round(cycles / gpu_s, 1), "unit": "instance-cycles/s",
                "us_per_cycle": round(gpu_s / cycles * 1e6, 2), "compile_s": round(info["compile_seconds"], 1),
@@ -209,19 +217,23 @@ def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=32768,
         out["plain"].append(rec)
         print(json.dumps({"soc48_plain": rec}), file=sys.stderr, flush=True)
         del sim
-    if batched_target not in designs:
-        designs[batched_target] = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=batched_target)
-    d = designs[batched_target]
-    sim = F.Sim(d, 64, launch=F.LAUNCH_GRAPH, seed=seed)
-    bc = max(8, cycles // 10)
-    gpu_s = time_sim(sim, ctx.torch_stream, bc, 4)
-    info = d.info()
-    bpc, _ = algorithmic_bytes_per_cycle(nl, info["n_live_ops"], 64)
-    out["batched"] = {"instances": 64, "processes": int(info["n_processes"]), "cycles": bc,
-                      "value": round(64 * bc / gpu_s, 1), "unit": "instance-cycles/s",
-                      "us_per_cycle": round(gpu_s / bc * 1e6, 1),
-                      "hbm_achieved_GBs": round(bpc / (gpu_s / bc) / 1e9, 2),
-                      "wave_lds_bytes": int(d.batched_info()["wave_lds_bytes"])}
+    out["batched"] = []
+    for bp in batched_packs:
+        if (bp, batched_target) not in designs:
+            designs[(bp, batched_target)] = F.Design(ctx, nl, pack=bp, target_processes=batched_target)
+        d = designs[(bp, batched_target)]
+        sim = F.Sim(d, 64, launch=F.LAUNCH_GRAPH, seed=seed)
+        bc = max(8, cycles // 10)
+        gpu_s = time_sim(sim, ctx.torch_stream, bc, 4)
+        info = d.info()
+        bpc, _ = algorithmic_bytes_per_cycle(nl, info["n_live_ops"], 64)
+        out["batched"].append({"instances": 64, "pack": PACK_NAMES[bp], "processes": int(info["n_processes"]),
+                               "cycles": bc, "value": round(64 * bc / gpu_s, 1), "unit": "instance-cycles/s",
+                               "us_per_cycle": round(gpu_s / bc * 1e6, 1),
+                               "hbm_achieved_GBs": round(bpc / (gpu_s / bc) / 1e9, 2),
+                               "dup_process": round(info["dup_process"], 4),
+                               "wave_lds_bytes": int(d.batched_info()["wave_lds_bytes"])})
+        del sim
     print(json.dumps({"soc48_batched": out["batched"]}), file=sys.stderr, flush=True)
     return out
 
@@ -326,6 +338,40 @@ def trace_split(sim, cycles=24):
             "gather_us": round(float(np.median(lvl0[1:])), 3)}
 
 
+def study_packing(F, g, tune, ctx):
+    """Bottom-up SLB (Sec. 5.1) against hypergraph packing (Sec. 6.6) on the
+    single-core and 8-tile designs: duplication, straggler cost, compile
+    time, and the rate of the plain form (one instance, one-wave processes,
+    instructions from global memory, graph launches) and of the batched
+    form (single-core x1024, 8-tile x256)."""
+    rows = []
+    cases = (("core", (1024, 2048, 4096), 1024, (2048, 4096, 8192)),
+             ("soc8", (2048, 4096), 256, (16384, 32768)))
+    for name, ptargets, n_inst, btargets in cases:
+        nl = g.workload(name)
+        for t in sorted(set(ptargets) | set(btargets)):
+            for pk in PACKS:
+                t0 = time.time()
+                d = F.Design(ctx, nl, pack=pk, target_processes=t)
+                comp = time.time() - t0
+                info = d.info()
+                rec = {"design": name, "target": t, "pack": PACK_NAMES[pk], "processes": int(info["n_processes"]),
+                       "dup_process": round(info["dup_process"], 4),
+                       "max_process_cost": int(info["max_process_cost"]),
+                       "max_fiber_cost": int(info["max_fiber_cost"]), "compile_s": round(comp, 2)}
+                if t in ptargets:
+                    s = tune.time_plain(ctx, d, F.LAUNCH_GRAPH, 64, 3000 if name == "core" else 1500,
+                                        stage=F.STAGE_GLOBAL, reps=3)
+                    rec["plain_khz"] = round(1 / s / 1e3, 2)
+                if t in btargets:
+                    s = tune.time_batched(ctx, d, n_inst, 256, 128 if name == "core" else 64)
+                    rec[f"batched_x{n_inst}_M"] = round(n_inst / s / 1e6, 4)
+                rows.append(rec)
+                print(json.dumps(rec), file=sys.stderr, flush=True)
+                del d
+    return {"rows": rows}
+
+
 def study_scaling(F, g, tune, ctx, seed):
     """The scaling study of Sec. 6.3 on this GPU.  Strong scaling: the
     single-core design at a growing number of one-wave processes, split into
@@ -386,13 +432,14 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache")
     ap.add_argument("--soc48", action="store_true",
                     help="also measure the 48-tile SoC (compiling it takes about a minute)")
-    ap.add_argument("--soc48-plain", default="8192:64:2,16384:64:2,16384:64:1",
-                    help="plain configurations for --soc48, target:threads[:stage][,...] "
-                         "(stage 1: instructions in LDS, 2: from global memory)")
+    ap.add_argument("--soc48-plain", default="16384:64:2:0,16384:64:2:3,8192:64:2:3",
+                    help="plain configurations for --soc48, target:threads[:stage[:pack]][,...] "
+                         "(stage 1: instructions in LDS, 2: from global memory; pack 0 SLB, 3 "
+                         "hypergraph)")
     ap.add_argument("--plain-config", default=None,
-                    help="target:threads:launch[:stage] for the headline plain run, skipping the "
-                         "autotuner (launch 1 persistent, 3 graph; stage 1 LDS, 2 global); used for "
-                         "profiling runs")
+                    help="target:threads:launch[:stage[:pack]] for the headline plain run, skipping "
+                         "the autotuner (launch 1 persistent, 3 graph; stage 1 LDS, 2 global; pack 0 "
+                         "SLB, 3 hypergraph); used for profiling runs")
     ap.add_argument("--profile-run", choices=["batched-core", "plain-core", "plain-prng"], default=None,
                     help="a short fixed run for hardware counters (per-cycle launches): batched "
                          "single-core x1024 on 4096 processes, plain single-core on 2048 one-wave "
@@ -400,10 +447,11 @@ def main():
                          "processes of 7 independent PRNG fibers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of known size (the reference for HBM byte counters)")
-    ap.add_argument("--study", choices=["prng", "scaling", "serving"], default=None,
+    ap.add_argument("--study", choices=["prng", "scaling", "serving", "packing"], default=None,
                     help="run a study instead of the benchmark (prng: the barrier sweep of Sec. 4.1; "
                          "scaling: strong and weak scaling of Sec. 6.3; serving: the served mix "
-                         "swept over the arrival rate)")
+                         "swept over the arrival rate; packing: SLB against hypergraph packing, "
+                         "Sec. 6.6)")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the batched, 8-tile plain and served sections")
     args = ap.parse_args()
@@ -456,6 +504,11 @@ def main():
         ctx = F.Context(0)
         print(json.dumps({"study": "serving sweep", **study_serving(F, g, ctx)}), flush=True)
         return
+    if args.study == "packing":
+        ctx = F.Context(0)
+        print(json.dumps({"study": "packing: SLB vs hypergraph (Sec. 6.6)",
+                          **study_packing(F, g, tune, ctx)}), flush=True)
+        return
     if args.study == "scaling":
         ctx = F.Context(0)
         print(json.dumps({"study": "scaling (Sec. 6.3)",
@@ -471,12 +524,14 @@ def main():
     if args.plain_config:
         vals = [int(v) for v in args.plain_config.split(":")]
         best = {"target": vals[0], "threads": vals[1], "launch": vals[2],
-                "stage": vals[3] if len(vals) > 3 else F.STAGE_AUTO}
+                "stage": vals[3] if len(vals) > 3 else F.STAGE_AUTO,
+                "pack": vals[4] if len(vals) > 4 else F.PACK_SLB}
     else:
         best, _ = tune.tune_plain(ctx, nl, targets=(512, 1024, 2048, 4096), threads=(64, 256),
-                                  launches=(F.LAUNCH_GRAPH,), cycles=2000, use_cache=not args.retune)
+                                  launches=(F.LAUNCH_GRAPH,), cycles=2000, use_cache=not args.retune,
+                                  packs=PACKS)
     tune_s = time.time() - t0
-    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=best["target"])
+    d = F.Design(ctx, nl, pack=best["pack"], target_processes=best["target"])
     info = d.info()
     sim = F.Sim(d, 1, launch=best["launch"], wg_threads=best["threads"], seed=seed,
                 stage=best.get("stage", F.STAGE_AUTO))
@@ -542,7 +597,8 @@ def main():
                     "process_levels": int(info["max_process_levels"]) + 2,
                     "ns_per_level_if_all_latency": round(gpu_s / total_cycles * 1e9 /
                                                           (info["max_process_levels"] + 2), 1)},
-        "design": {"processes": int(info["n_processes"]), "dup_fiber": round(info["dup_fiber"], 4),
+        "design": {"pack": PACK_NAMES[best["pack"]], "processes": int(info["n_processes"]),
+                   "dup_fiber": round(info["dup_fiber"], 4),
                    "dup_process": round(info["dup_process"], 4), "live_ops": int(info["n_live_ops"]),
                    "max_fiber_cost": int(info["max_fiber_cost"]),
                    "max_process_cost": int(info["max_process_cost"]),

@@ -117,10 +117,16 @@ typedef struct fsim_partition {
 #define FSIM_PACK_SLB      0   /* Sec. 5.1 stages 1, 3, 4: bottom-up merge   */
 #define FSIM_PACK_FIBERS   1   /* one fiber per process (memory groups kept) */
 #define FSIM_PACK_SINGLE   2   /* one process holding every fiber            */
+#define FSIM_PACK_HYPER    3   /* hypergraph packing, the alternative of
+                                  Sec. 6.6 (fibers as nodes, shared cone
+                                  nodes as hyperedges): runs of units in
+                                  node order, then moves that lower total
+                                  replication under the straggler bound    */
 
 typedef struct fsim_compile_opts {
   uint32_t pack;              /* FSIM_PACK_*                                 */
-  uint32_t target_processes;  /* SLB target process count; 0 = device CUs    */
+  uint32_t target_processes;  /* SLB / hypergraph target process count;
+                                 0 = device CUs                              */
   uint32_t max_process_nodes; /* capacity of one process (Sec. 5.1 memory
                                  limit); 0 = derived from the LDS size       */
 } fsim_compile_opts;

@@ -355,6 +355,151 @@ SlbResult slb_merge(const Design& d, const std::vector<std::vector<uint32_t>>& n
   return r;
 }
 
+// ---- hypergraph packing (the alternative to bottom-up SLB that Sec. 6.6
+// compares against: fibers are the hypergraph's nodes, and the fibers
+// sharing a combinational node form a hyperedge of weight c(node)).  A
+// partition replicates every node once per process its hyperedge spans, so
+// its total replication is sum_P tau(P) minus the design's cost.  Units are
+// the stage-1 groups (memory co-location).
+//  1. Units are ordered by the median node of their cones (netlists keep
+//     related logic close in node order) and cut into consecutive runs
+//     whose union cost tau stays within a bound; the smallest bound that
+//     gives at most `target` runs is searched (geometric steps, then
+//     bisection), and runs also respect the node cap.
+//  2. FM-style passes move a unit to the process it shares the most cost
+//     with whenever that lowers total replication and keeps the receiving
+//     process within the bound and the node cap.  Nodes shared by very many
+//     processes are replicated everywhere anyway and are left out of the
+//     shared-cost estimate, which only makes a move look costlier.
+// Returns the process of every unit, ids compacted; more than `target`
+// processes when the node cap leaves no other way.
+std::vector<uint32_t> hyper_pack(const Design& d, const std::vector<std::vector<uint32_t>>& unit_nodes,
+                                 uint32_t target, uint64_t max_nodes, uint32_t* n_procs) {
+  const uint32_t U = (uint32_t)unit_nodes.size();
+  std::vector<uint64_t> ucost(U);
+  uint64_t max_unit = 0;
+  for (uint32_t u = 0; u < U; ++u) {
+    ucost[u] = set_cost(d, unit_nodes[u]);
+    max_unit = std::max(max_unit, ucost[u]);
+  }
+  std::vector<uint32_t> order(U);
+  std::iota(order.begin(), order.end(), 0u);
+  auto key = [&](uint32_t u) -> uint32_t {
+    const auto& v = unit_nodes[u];
+    return v.empty() ? 0u : v[v.size() / 2];
+  };
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
+  // ---- 1. runs under a union-cost bound
+  std::vector<uint32_t> stamp(d.N, UINT32_MAX), proc(U, 0);
+  auto cut = [&](uint64_t bound, std::vector<uint32_t>* assign) -> uint32_t {
+    std::fill(stamp.begin(), stamp.end(), UINT32_MAX);
+    uint32_t run = 0;
+    uint64_t tau = 0, nodes = 0;
+    for (uint32_t u : order) {
+      uint64_t add = 0, addn = 0;
+      for (uint32_t x : unit_nodes[u]) if (stamp[x] != run) { add += d.cost[x]; ++addn; }
+      if (nodes > 0 && (tau + add > bound || nodes + addn > max_nodes)) {
+        ++run;
+        tau = 0;
+        nodes = 0;
+        add = ucost[u];
+        addn = unit_nodes[u].size();
+      }
+      for (uint32_t x : unit_nodes[u]) stamp[x] = run;
+      tau += add;
+      nodes += addn;
+      if (assign) (*assign)[u] = run;
+    }
+    return run + 1;
+  };
+  uint64_t total = 0;
+  for (uint64_t c : ucost) total += c;
+  uint64_t lo = std::max<uint64_t>(max_unit, 1), hi = 0;
+  for (uint64_t B = lo;; B = std::max<uint64_t>(B + 1, B + B / 8)) {
+    if (cut(B, nullptr) <= target) { hi = B; break; }
+    lo = B + 1;
+    if (B >= total) { hi = total; break; }
+  }
+  for (int it = 0; it < 24 && lo < hi; ++it) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (cut(mid, nullptr) <= target) hi = mid; else lo = mid + 1;
+  }
+  const uint64_t bound = hi;
+  const uint32_t P = cut(bound, &proc);
+  // ---- incidence: for every node, the processes holding it and how many of
+  // their units contain it
+  struct Inc { uint32_t p, n; };
+  std::vector<std::vector<Inc>> inc(d.N);
+  std::vector<uint64_t> tau(P, 0), pnodes(P, 0);
+  auto add = [&](uint32_t u, uint32_t p) {
+    for (uint32_t x : unit_nodes[u]) {
+      bool found = false;
+      for (Inc& e : inc[x]) if (e.p == p) { ++e.n; found = true; break; }
+      if (!found) { inc[x].push_back({p, 1}); tau[p] += d.cost[x]; ++pnodes[p]; }
+    }
+  };
+  auto remove = [&](uint32_t u, uint32_t p) {
+    for (uint32_t x : unit_nodes[u]) {
+      auto& v = inc[x];
+      for (size_t i = 0; i < v.size(); ++i) {
+        if (v[i].p != p) continue;
+        if (--v[i].n == 0) { v[i] = v.back(); v.pop_back(); tau[p] -= d.cost[x]; --pnodes[p]; }
+        break;
+      }
+    }
+  };
+  for (uint32_t u = 0; u < U; ++u) add(u, proc[u]);
+  // ---- 2. refinement
+  constexpr size_t kWide = 32;             // nodes in more processes than this: left out of the estimate
+  std::vector<uint64_t> shared_c(P, 0), shared_n(P, 0);
+  std::vector<uint32_t> touched;
+  for (int pass = 0; pass < 6; ++pass) {
+    uint64_t moved = 0;
+    for (uint32_t u : order) {
+      const uint32_t a = proc[u];
+      uint64_t save = 0;                   // cost freed in a by taking u out
+      touched.clear();
+      for (uint32_t x : unit_nodes[u]) {
+        const auto& v = inc[x];
+        for (const Inc& e : v) {
+          if (e.p == a) { if (e.n == 1) save += d.cost[x]; continue; }
+          if (v.size() > kWide) continue;
+          if (!shared_c[e.p] && !shared_n[e.p]) touched.push_back(e.p);
+          shared_c[e.p] += d.cost[x];
+          ++shared_n[e.p];
+        }
+      }
+      uint32_t best = UINT32_MAX;
+      int64_t best_delta = 0;
+      for (uint32_t b : touched) {
+        const uint64_t addc = ucost[u] - shared_c[b], addn = unit_nodes[u].size() - shared_n[b];
+        const int64_t delta = (int64_t)addc - (int64_t)save;   // change of total replication
+        if (delta < best_delta && tau[b] + addc <= bound && pnodes[b] + addn <= max_nodes) {
+          best_delta = delta;
+          best = b;
+        }
+      }
+      for (uint32_t b : touched) shared_c[b] = shared_n[b] = 0;
+      if (best != UINT32_MAX) {
+        remove(u, a);
+        add(u, best);
+        proc[u] = best;
+        ++moved;
+      }
+    }
+    if (!moved) break;
+  }
+  // ---- compact ids (a process may have lost all its units)
+  std::vector<uint32_t> id(P, UINT32_MAX);
+  uint32_t n = 0;
+  for (uint32_t u : order) {
+    if (id[proc[u]] == UINT32_MAX) id[proc[u]] = n++;
+    proc[u] = id[proc[u]];
+  }
+  *n_procs = n;
+  return proc;
+}
+
 }  // namespace
 
 Status partition_design(Design& d, const fsim_partition* part, const fsim_compile_opts& opts,
@@ -451,7 +596,30 @@ Status partition_design(Design& d, const fsim_partition* part, const fsim_compil
     d.P = std::max(P0, 1u);
     uint32_t target = opts.target_processes ? opts.target_processes : default_target;
     uint64_t max_nodes = opts.max_process_nodes ? opts.max_process_nodes : default_max_nodes;
-    if (opts.pack == FSIM_PACK_SLB && P0 > target) {
+    if (opts.pack == FSIM_PACK_HYPER && P0 > target) {
+      std::vector<std::vector<uint32_t>> unodes(P0);
+      {
+        std::vector<std::vector<uint32_t>> usinks(P0);
+        for (uint32_t s = 0; s < S; ++s) usinks[d.sink_proc[s]].push_back(s);
+        for (uint32_t p = 0; p < P0; ++p) {
+          std::vector<uint32_t> acc;
+          for (uint32_t s : usinks[p]) {
+            std::vector<uint32_t> c(cone.begin() + cone_off[s], cone.begin() + cone_off[s + 1]);
+            acc = acc.empty() ? std::move(c) : set_union(acc, c);
+          }
+          unodes[p] = std::move(acc);
+        }
+      }
+      phase("initial processes");
+      uint32_t n = 0;
+      std::vector<uint32_t> up = hyper_pack(d, unodes, target, max_nodes, &n);
+      if (n > target)
+        return Status::err(FSIM_E_CAPACITY,
+            fmt("cannot pack the design into %llu processes of at most %llu nodes", target, max_nodes));
+      for (uint32_t s = 0; s < S; ++s) d.sink_proc[s] = up[d.sink_proc[s]];
+      d.P = std::max(n, 1u);
+      phase("hypergraph packing");
+    } else if (opts.pack == FSIM_PACK_SLB && P0 > target) {
       std::vector<std::vector<uint32_t>> nodes0(P0), sinks0(P0);
       for (uint32_t s = 0; s < S; ++s) sinks0[d.sink_proc[s]].push_back(s);
       std::vector<uint64_t> cost0(P0);

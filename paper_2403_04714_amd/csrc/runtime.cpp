@@ -95,7 +95,7 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   auto dz = std::make_unique<fsim_design>();
   fsim_compile_opts o{};
   if (opts) o = *opts;
-  if (o.pack > FSIM_PACK_SINGLE) return fail(FSIM_E_ARG, "unknown packing policy");
+  if (o.pack > FSIM_PACK_HYPER) return fail(FSIM_E_ARG, "unknown packing policy");
   Design& d = dz->d;
   Status s = fsim::copy_and_validate(nl, d);
   if (!s.ok()) return fail(s);

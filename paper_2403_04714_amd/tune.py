@@ -72,20 +72,21 @@ def time_plain(ctx, design, launch, threads, cycles, seed=0x5EED0000, reps=2, st
 
 def tune_plain(ctx, nl, targets=(16, 32, 64, 128, 256), threads=(256, 512, 1024),
                launches=(F.LAUNCH_PERSISTENT, F.LAUNCH_GRAPH), cycles=2000, use_cache=True,
-               verbose=False):
-    """Returns (best, trials): best = dict(target, threads, launch, s_per_cycle)."""
-    key = f"plain/{design_hash(nl)}/{_device_name()}"
+               verbose=False, packs=(F.PACK_SLB,)):
+    """Returns (best, trials): best = dict(pack, target, threads, launch,
+    stage, s_per_cycle)."""
+    key = f"plain/{design_hash(nl)}/{'-'.join(map(str, packs))}/{_device_name()}"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key], []
     trials = []
     best = None
-    for t in targets:
+    for pk, t in [(pk, t) for pk in packs for t in targets]:
         try:
-            d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=t)
+            d = F.Design(ctx, nl, pack=pk, target_processes=t)
         except F.FsimError as e:
             if verbose:
-                print(f"tune: target {t}: {e}", flush=True)
+                print(f"tune: pack {pk} target {t}: {e}", flush=True)
             continue
         for th in threads:
             # one-wave processes: instructions staged in LDS or read from global memory
@@ -97,8 +98,8 @@ def tune_plain(ctx, nl, targets=(16, 32, 64, 128, 256), threads=(256, 512, 1024)
                     if verbose:
                         print(f"tune: target {t} threads {th} launch {la} stage {st}: {e}", flush=True)
                     continue
-                rec = dict(target=t, processes=d.info()["n_processes"], threads=th, launch=la, stage=st,
-                           s_per_cycle=spc)
+                rec = dict(pack=pk, target=t, processes=d.info()["n_processes"], threads=th, launch=la,
+                           stage=st, s_per_cycle=spc)
                 trials.append(rec)
                 if verbose:
                     print(f"tune: {rec}  ({1/spc/1e3:.1f} kHz)", flush=True)
@@ -135,21 +136,24 @@ def time_batched(ctx, design, n_inst, threads, cycles, seed=0x5EED0000, reps=2, 
 
 
 def tune_batched(ctx, nl, n_inst, targets=(256, 512, 1024, 2048), threads=(64, 128, 256),
-                 cycles=256, use_cache=True, verbose=False, designs=None, tiles=(1, 2)):
-    """Batched-form autotuner: packing target, tiles of 64 instances per
-    workgroup and per wave.  Returns (best, trials); best has s_per_cycle for
-    all instances."""
-    key = f"batched/{design_hash(nl)}/{n_inst}/{_device_name()}"
+                 cycles=256, use_cache=True, verbose=False, designs=None, tiles=(1, 2),
+                 packs=(F.PACK_SLB,)):
+    """Batched-form autotuner: packing policy and target, tiles of 64
+    instances per workgroup and per wave.  designs: optional {(pack,
+    target): Design} already compiled.  Returns (best, trials); best has
+    s_per_cycle for all instances."""
+    key = f"batched/{design_hash(nl)}/{n_inst}/{'-'.join(map(str, packs))}/{_device_name()}"
     cache = _load_cache() if use_cache else {}
     if key in cache:
         return cache[key], []
     trials, best = [], None
-    for t in targets:
+    for pk, t in [(pk, t) for pk in packs for t in targets]:
         try:
-            d = designs[t] if designs and t in designs else F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=t)
+            d = designs[(pk, t)] if designs and (pk, t) in designs else \
+                F.Design(ctx, nl, pack=pk, target_processes=t)
         except F.FsimError as e:
             if verbose:
-                print(f"tune: target {t}: {e}", flush=True)
+                print(f"tune: pack {pk} target {t}: {e}", flush=True)
             continue
         for th, tw in [(th, tw) for th in threads for tw in tiles]:
             if th * tw > 64 * ((n_inst + 63) // 64):
@@ -160,7 +164,7 @@ def tune_batched(ctx, nl, n_inst, targets=(256, 512, 1024, 2048), threads=(64, 1
                 if verbose:
                     print(f"tune: target {t} threads {th} tiles/wave {tw}: {e}", flush=True)
                 continue
-            rec = dict(target=t, processes=d.info()["n_processes"], threads=th, tiles_per_wave=tw,
+            rec = dict(pack=pk, target=t, processes=d.info()["n_processes"], threads=th, tiles_per_wave=tw,
                        s_per_cycle=spc, inst_cycles_per_s=n_inst / spc)
             trials.append(rec)
             if verbose:

@@ -98,13 +98,14 @@ def test_partition_must_colocate_memory_ports():
 
 
 @pytest.mark.parametrize("pack,target", [(F.PACK_SINGLE, 0), (F.PACK_FIBERS, 0),
-                                         (F.PACK_SLB, 7), (F.PACK_SLB, 64)])
+                                         (F.PACK_SLB, 7), (F.PACK_SLB, 64),
+                                         (F.PACK_HYPER, 7), (F.PACK_HYPER, 64)])
 def test_compiler_node_lists_reproduce_monolithic(pack, target):
     for nl in (g.gen_tiny(2), small_core(5)):
         d = host_design(nl, pack=pack, target_processes=target)
         stp, off, nodes = d.partition()
         info = d.info()
-        if pack == F.PACK_SLB:
+        if pack in (F.PACK_SLB, F.PACK_HYPER):
             assert info["n_processes"] <= target
         s0 = O.Sim(nl, seed=3)
         d0 = s0.step(60, digests=True)
@@ -125,6 +126,78 @@ def test_node_lists_are_closed_cones():
             for a in nl.arg[x]:
                 if a != g.NONE:
                     assert int(a) in have
+
+
+def union_cost(nl, nodes):
+    """tau of a node set in the compiler's cost unit (Sec. 4.3): constants
+    0, register and input leaves 1, operators and memory reads 2 above 32
+    bits and 1 otherwise."""
+    c = 0
+    for x in nodes:
+        op = int(nl.op[x])
+        if op in (1, 2):
+            c += 1
+        elif op >= 3:
+            c += 2 if int(nl.width[x]) > 32 else 1
+    return c
+
+
+@pytest.mark.parametrize("target", [3, 16, 50])
+def test_hypergraph_packing_is_valid(target):
+    """Hypergraph packing: every sink in one process, memory groups kept,
+    at most `target` processes, each process's node list the union of its
+    fibers' cones (checked against a brute-force crawl), and the reported
+    duplication and straggler equal to what the node lists give."""
+    nl = small_core(5)
+    d = host_design(nl, pack=F.PACK_HYPER, target_processes=target)
+    stp, off, nodes = d.partition()
+    info = d.info()
+    P = len(off) - 1
+    assert info["n_processes"] == P <= target
+    assert stp.min() >= 0 and stp.max() < P
+    # the union of cones by brute force
+    R, W = nl.n_regs, len(nl.wp_mem)
+    def cone(roots):
+        seen, st = set(), list(roots)
+        while st:
+            x = st.pop()
+            if x in seen:
+                continue
+            seen.add(x)
+            st.extend(int(a) for a in nl.arg[x] if a != g.NONE)
+        return seen
+    roots = [[int(nl.reg_next[s])] for s in range(R)]
+    roots += [[int(nl.wp_en[k]), int(nl.wp_addr[k]), int(nl.wp_data[k])] for k in range(W)]
+    roots += [[int(o)] for o in nl.out_node]
+    want = [set() for _ in range(P)]
+    for s, r in enumerate(roots):
+        want[int(stp[s])] |= cone(r)
+    for p in range(P):
+        assert set(int(x) for x in nodes[off[p]:off[p + 1]]) == want[p]
+    # memory co-location: every reader of a written memory shares the
+    # process of its write ports
+    for m in range(nl.n_mems):
+        ports = [R + k for k in range(W) if int(nl.wp_mem[k]) == m]
+        if not ports:
+            continue
+        home = {int(stp[s]) for s in ports}
+        assert len(home) == 1
+        for s, r in enumerate(roots):
+            if any(int(nl.op[x]) == 3 and int(nl.imm[x]) == m for x in cone(r)):
+                assert int(stp[s]) in home
+    costs = [union_cost(nl, want[p]) for p in range(P)]
+    assert info["max_process_cost"] == max(costs)
+
+
+def test_hypergraph_packing_beats_fiber_duplication():
+    """On the single-core workload, hypergraph packing replicates less than
+    one fiber per process does (D_p < D_f) and never exceeds the target."""
+    nl = g.workload("core")
+    d = host_design(nl, pack=F.PACK_HYPER, target_processes=1024)
+    info = d.info()
+    assert info["n_processes"] <= 1024
+    assert 1.0 <= info["dup_process"] < info["dup_fiber"]
+    assert info["max_process_cost"] >= info["max_fiber_cost"]
 
 
 def equal_fibers(n_fibers, ops_each, width=16):
@@ -222,13 +295,14 @@ def test_memory_premerge_bound():
     assert sorted(owner) == list(range(len(mems)))
 
 
-def test_capacity_limit_respected():
+@pytest.mark.parametrize("pack", [F.PACK_SLB, F.PACK_HYPER])
+def test_capacity_limit_respected(pack):
     nl = g.gen_tiny(1)
-    d = host_design(nl, pack=F.PACK_SLB, target_processes=20, max_process_nodes=400)
+    d = host_design(nl, pack=pack, target_processes=20, max_process_nodes=400)
     stp, off, nodes = d.partition()
     assert np.diff(off).max() <= 400
     with pytest.raises(F.FsimError) as e:
-        host_design(nl, pack=F.PACK_SLB, target_processes=1, max_process_nodes=50)
+        host_design(nl, pack=pack, target_processes=1, max_process_nodes=50)
     assert e.value.code == F.E_CAPACITY
 
 

@@ -30,10 +30,10 @@ def say(*a):
 
 
 def check_batched(F, ctx, nl, n_inst, cycles, target=0, threads=0, launch=0, full_state=None,
-                  chunks=(None,), seed=SEED, digest_insts=None, tiles_per_wave=0):
+                  chunks=(None,), seed=SEED, digest_insts=None, tiles_per_wave=0, pack=None):
     say(f"case {nl.name}: batched n_inst={n_inst} target={target} threads={threads} "
         f"launch={launch} tiles_per_wave={tiles_per_wave} cycles={cycles}")
-    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=target)
+    d = F.Design(ctx, nl, pack=F.PACK_SLB if pack is None else pack, target_processes=target)
     s = F.Sim(d, n_inst, launch=launch, wg_threads=threads, seed=seed, tiles_per_wave=tiles_per_wave)
     s.enable_digest(cycles)
     done = 0
@@ -131,6 +131,14 @@ def test_two_tiles_per_wave_explicit_inputs(F, ctx):
         s.step(1)
         for i in (0, 63, 64, 127, 128, 199):
             assert int(s.regs(i)[0]) == int(vals[t, 0, i] + vals[t, 1, i]), (t, i)
+
+
+def test_hypergraph_packing(F, ctx):
+    """Hypergraph packing in the batched form: memories, a ragged instance
+    count, and the full single-core design."""
+    check_batched(F, ctx, small_core(), 70, 150, target=40, pack=F.PACK_HYPER, full_state={0, 69})
+    check_batched(F, ctx, g.workload("core"), 128, 40, target=2048, pack=F.PACK_HYPER, full_state={0, 127},
+                  digest_insts=[0, 64, 127])
 
 
 def test_batched_single_instance_equals_plain(F, ctx):

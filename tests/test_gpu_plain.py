@@ -172,6 +172,17 @@ def test_phase_timestamps(F, ctx, launch, stage, threads):
                 assert (np.diff(row) >= 0).all() and (row >= start[c, w]).all() and (row <= commit[c, w]).all()
 
 
+@pytest.mark.parametrize("target,stage", [(24, 2), (200, 1)])
+def test_hypergraph_packing_small_core(F, ctx, target, stage):
+    """Hypergraph packing (the alternative of Sec. 6.6) through the one-wave
+    kernel, memories included."""
+    run_both(F, ctx, small_core(), 300, F.PACK_HYPER, target, launch=3, threads=64, stage=stage)
+
+
+def test_hypergraph_packing_core_full_size(F, ctx):
+    run_both(F, ctx, g.workload("core"), 500, F.PACK_HYPER, 2048, launch=3, threads=64, stage=2)
+
+
 def _pairs_inputs(n=4):
     pairs = list(itertools.product(range(2**n), repeat=2))
     return pairs, np.array(pairs, np.uint64)
