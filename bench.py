@@ -441,9 +441,10 @@ def main():
                          "the autotuner (launch 1 persistent, 3 graph; stage 1 LDS, 2 global; pack 0 "
                          "SLB, 3 hypergraph); used for profiling runs")
     ap.add_argument("--profile-run", choices=["batched-core", "plain-core", "plain-prng"], default=None,
-                    help="a short fixed run for hardware counters (per-cycle launches): batched "
-                         "single-core x1024 on 4096 processes, plain single-core on 2048 one-wave "
-                         "processes reading instructions from global memory, or 64 one-wave "
+                    help="a short fixed run for hardware counters (per-cycle launches, hypergraph "
+                         "packing): batched single-core x1024 at target 4096, plain single-core at "
+                         "target 2048 in one-wave processes reading instructions from global memory, "
+                         "or 64 one-wave "
                          "processes of 7 independent PRNG fibers")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of known size (the reference for HBM byte counters)")
@@ -472,10 +473,10 @@ def main():
     if args.profile_run:
         ctx = F.Context(0)
         if args.profile_run == "batched-core":
-            d = F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=4096)
+            d = F.Design(ctx, g.workload("core"), pack=F.PACK_HYPER, target_processes=4096)
             sim = F.Sim(d, 1024, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE)
         elif args.profile_run == "plain-core":
-            d = F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=2048)
+            d = F.Design(ctx, g.workload("core"), pack=F.PACK_HYPER, target_processes=2048)
             sim = F.Sim(d, 1, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE,
                         stage=F.STAGE_GLOBAL)
         else:
