@@ -32,6 +32,7 @@
  *         leaves: REG -> R[r], INPUT -> I_t[p], CONST -> imm,
  *                 MEMRD -> M[m][v[addr] mod depth]   (reads see M_t)
  *     R'[r]   = mask(w_r, v[reg_next[r]])         (all registers at once)
+ *               if r has no enable or v[reg_en[r]] != 0, else R[r]
  *     O_t[o]  = v[out_node[o]]
  *     for write port k in index order:             (after every read)
  *         if v[en_k] != 0: M[m_k][v[addr_k] mod depth] = mask(w_m, v[data_k])
@@ -46,6 +47,11 @@
  *   - memory reads see the state at the start of the cycle; writes commit at
  *     the end of the cycle in port order, so the highest port index wins when
  *     two enabled ports hit one address; addresses wrap modulo the depth;
+ *   - gated and divided clocks (Sec. 5.3, Limitations: one top clock plus
+ *     any number of gated or divided ones) are modelled as a per-register
+ *     enable of the top clock: in a cycle where the enable node is zero the
+ *     register keeps its value.  A divided clock is a gate driven by the
+ *     divider's own state; the design builds that logic from ordinary nodes;
  *   - the on-device test driver of Sec. 5.3 (Limitations) is modelled as a
  *     counter-based stimulus stim = H(H(H(seed) xor p) xor t), H being the
  *     SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
@@ -88,6 +94,7 @@ typedef struct {
   const uint64_t *mem_init;     /* all memories back to back, mem 0 first */
   uint32_t n_wports;
   const uint32_t *wp_mem, *wp_en, *wp_addr, *wp_data;
+  const uint32_t *reg_en;       /* NULL, or per register a node / ORC_NONE */
 } orc_netlist;
 
 /* ---------------------------------------------------------------- helpers */
@@ -176,6 +183,8 @@ static int validate(const orc_netlist *nl) {
   for (uint32_t r = 0; r < nl->n_regs; ++r) {
     if (nl->reg_width[r] < 1 || nl->reg_width[r] > 64) return ORC_E_NETLIST;
     if (nl->reg_next[r] >= nl->n_nodes) return ORC_E_NETLIST;
+    if (nl->reg_en && nl->reg_en[r] != ORC_NONE && nl->reg_en[r] >= nl->n_nodes)
+      return ORC_E_NETLIST;
   }
   for (uint32_t p = 0; p < nl->n_inputs; ++p)
     if (nl->in_width[p] < 1 || nl->in_width[p] > 64) return ORC_E_NETLIST;
@@ -241,7 +250,7 @@ void orc_free(orc_sim *s) {
   free((void *)s->nl.mem_depth); free((void *)s->nl.mem_width);
   free((void *)s->nl.mem_init); free((void *)s->nl.wp_mem);
   free((void *)s->nl.wp_en); free((void *)s->nl.wp_addr);
-  free((void *)s->nl.wp_data);
+  free((void *)s->nl.wp_data); free((void *)s->nl.reg_en);
   free(s->topo); free(s->mem_off); free(s->R); free(s->Rn); free(s->O);
   free(s->M); free(s->v); free(s->I); free(s->in_vals);
   free(s);
@@ -280,6 +289,7 @@ int orc_new(const orc_netlist *src, uint64_t order_seed, orc_sim **out) {
   nl->wp_en = dup(src->wp_en, 4ull * src->n_wports);
   nl->wp_addr = dup(src->wp_addr, 4ull * src->n_wports);
   nl->wp_data = dup(src->wp_data, 4ull * src->n_wports);
+  nl->reg_en = src->reg_en ? dup(src->reg_en, 4ull * src->n_regs) : NULL;
   s->topo = malloc((n ? n : 1) * sizeof(uint32_t));
   rc = topo_sort(nl, order_seed, s->topo, &s->n_topo);
   if (rc) { orc_free(s); return rc; }
@@ -354,11 +364,19 @@ static uint64_t digest(const orc_sim *s) {
 
 uint64_t orc_digest(const orc_sim *s) { return digest(s); }
 
+/* Whether register r's clock ticks this cycle (Sec. 5.3: a gated or divided
+ * clock is the top clock with an enable). */
+static int clock_enabled(const orc_netlist *nl, uint32_t r, const uint64_t *v) {
+  uint32_t e = nl->reg_en ? nl->reg_en[r] : ORC_NONE;
+  return e == ORC_NONE || v[e] != 0;
+}
+
 /* Register update, outputs and memory commit from a complete value table. */
 static void end_of_cycle(orc_sim *s, const uint64_t *v) {
   const orc_netlist *nl = &s->nl;
   for (uint32_t r = 0; r < nl->n_regs; ++r)
-    s->Rn[r] = mask_w(nl->reg_width[r], v[nl->reg_next[r]]);
+    s->Rn[r] = clock_enabled(nl, r, v)
+        ? mask_w(nl->reg_width[r], v[nl->reg_next[r]]) : s->R[r];
   for (uint32_t o = 0; o < nl->n_outputs; ++o) s->O[o] = v[nl->out_node[o]];
   for (uint32_t k = 0; k < nl->n_wports; ++k) {
     if (v[nl->wp_en[k]] == 0) continue;
@@ -413,7 +431,12 @@ typedef struct {
 static uint32_t sink_node_list(const orc_netlist *nl, uint32_t sink,
                                uint32_t *roots) {
   uint32_t R = nl->n_regs, W = nl->n_wports;
-  if (sink < R) { roots[0] = nl->reg_next[sink]; return 1; }
+  if (sink < R) {
+    /* a register's fiber also produces its clock enable, if it has one */
+    roots[0] = nl->reg_next[sink];
+    if (nl->reg_en && nl->reg_en[sink] != ORC_NONE) { roots[1] = nl->reg_en[sink]; return 2; }
+    return 1;
+  }
   if (sink < R + W) {
     uint32_t k = sink - R;
     roots[0] = nl->wp_en[k]; roots[1] = nl->wp_addr[k]; roots[2] = nl->wp_data[k];
@@ -523,7 +546,8 @@ int orc_step_partitioned(orc_sim *s, uint64_t n_cycles, uint32_t n_proc,
         uint32_t k = sk[j], roots[3], nr = sink_node_list(nl, k, roots);
         for (uint32_t q = 0; q < nr; ++q) if (!have[roots[q]]) rc = ORC_E_CONE;
         if (rc) break;
-        if (k < nl->n_regs) Rn[k] = mask_w(nl->reg_width[k], v[roots[0]]);
+        if (k < nl->n_regs)
+          Rn[k] = clock_enabled(nl, k, v) ? mask_w(nl->reg_width[k], v[roots[0]]) : s->R[k];
         else if (k < nl->n_regs + nl->n_wports) {
           uint32_t q = k - nl->n_regs;
           wen[q] = v[roots[0]] != 0; waddr[q] = v[roots[1]]; wdata[q] = v[roots[2]];

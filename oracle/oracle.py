@@ -46,6 +46,7 @@ class _Netlist(C.Structure):
         ("mem_init", C.c_void_p),
         ("n_wports", C.c_uint32), ("wp_mem", C.c_void_p), ("wp_en", C.c_void_p),
         ("wp_addr", C.c_void_p), ("wp_data", C.c_void_p),
+        ("reg_en", C.c_void_p),
     ]
 
 
@@ -133,6 +134,10 @@ class Sim:
             wp_addr=np.ascontiguousarray(nl.wp_addr, np.uint32),
             wp_data=np.ascontiguousarray(nl.wp_data, np.uint32),
         )
+        en = getattr(nl, "reg_en", None)
+        if en is not None:
+            keep["reg_en"] = np.ascontiguousarray(en, np.uint32)
+            assert keep["reg_en"].shape == keep["reg_width"].shape
         s = _Netlist()
         s.n_nodes = len(keep["op"])
         s.n_regs = len(keep["reg_width"])
