@@ -241,15 +241,16 @@ def bench_soc48(F, g, ctx, seed, plain_cfgs=((8192, 64),), batched_target=32768,
 def bench_served(F, g, ctx, n_jobs, lam, inst_hi, cyc_lo, cyc_hi):
     """Served Poisson stream over the single-core and 8-tile SoC designs."""
     from paper_2403_04714_amd import serve
-    designs = [F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=4096),
-               F.Design(ctx, g.workload("soc8"), pack=F.PACK_SLB, target_processes=16384)]
+    designs = [F.Design(ctx, g.workload("core"), pack=F.PACK_HYPER, target_processes=2048),
+               F.Design(ctx, g.workload("soc8"), pack=F.PACK_HYPER, target_processes=16384)]
     jobs = serve.draw_jobs(n_jobs, designs, inst_lo=1, inst_hi=inst_hi, cyc_lo=cyc_lo, cyc_hi=cyc_hi)
     arr = serve.arrivals(n_jobs, lam=lam)
     srv = F.Server(ctx, 64 << 30, quantum_cycles=256)
     recs, summ = serve.run(srv, designs, jobs, arr, timeout_s=600)
     st = srv.stats()
     srv.close()
-    return {"designs": ["core (4096 processes)", "soc8 (16384 processes)"], "jobs": n_jobs,
+    return {"designs": [f"core ({designs[0].info()['n_processes']} processes, hypergraph packing)",
+                        f"soc8 ({designs[1].info()['n_processes']} processes, hypergraph packing)"], "jobs": n_jobs,
             "arrival_rate_per_s": lam, "instances": f"log-uniform [1, {inst_hi}]",
             "cycles": f"log-uniform [{cyc_lo}, {cyc_hi}]",
             "completed": summ["completed"], "p50_s": round(summ["p50_s"], 4), "p99_s": round(summ["p99_s"], 4),
@@ -264,8 +265,8 @@ def study_serving(F, g, ctx, n_jobs=24, lams=(1.0, 2.0, 4.0, 8.0, 16.0, 64.0)):
     arrival) and aggregate instance-cycles/s per rate, one fresh server per
     rate over the same compiled designs and the same job draw."""
     from paper_2403_04714_amd import serve
-    designs = [F.Design(ctx, g.workload("core"), pack=F.PACK_SLB, target_processes=4096),
-               F.Design(ctx, g.workload("soc8"), pack=F.PACK_SLB, target_processes=16384)]
+    designs = [F.Design(ctx, g.workload("core"), pack=F.PACK_HYPER, target_processes=2048),
+               F.Design(ctx, g.workload("soc8"), pack=F.PACK_HYPER, target_processes=16384)]
     jobs = serve.draw_jobs(n_jobs, designs, inst_lo=1, inst_hi=1024, cyc_lo=100, cyc_hi=2000)
     work = sum(j["instances"] * j["cycles"] for j in jobs)
     rows = []
@@ -283,7 +284,8 @@ def study_serving(F, g, ctx, n_jobs=24, lams=(1.0, 2.0, 4.0, 8.0, 16.0, 64.0)):
                      "device_busy_s": round(st["busy_seconds"], 3)})
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     return {"jobs": n_jobs, "total_work_instance_cycles": int(work),
-            "designs": ["core (4096 processes)", "soc8 (16384 processes)"],
+            "designs": [f"core ({designs[0].info()['n_processes']} processes, hypergraph packing)",
+                        f"soc8 ({designs[1].info()['n_processes']} processes, hypergraph packing)"],
             "instances": "log-uniform [1, 1024]", "cycles": "log-uniform [100, 2000]", "rows": rows}
 
 

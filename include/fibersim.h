@@ -78,7 +78,12 @@ enum {
  *   reg_next:  node whose value becomes the register's next value.
  *   mem_init:  all memories back to back (sum of depths words), or NULL = 0.
  *   write ports (wp_*): node indices of enable, address and data; ports are
- *   applied at the end of the cycle in index order (the highest port wins). */
+ *   applied at the end of the cycle in index order (the highest port wins).
+ *   reg_en:    NULL, or per register a node index or FSIM_NONE.  A register
+ *   with an enable node takes its next value only in cycles where that node
+ *   is non-zero and keeps its value otherwise: a gated or divided clock
+ *   (Sec. 5.3) expressed as an enable of the single top clock.  FSIM_NONE
+ *   (and a NULL array) means the register follows the top clock. */
 typedef struct fsim_netlist {
   uint32_t n_nodes;
   const uint8_t* op;
@@ -102,6 +107,7 @@ typedef struct fsim_netlist {
   const uint32_t* wp_en;
   const uint32_t* wp_addr;
   const uint32_t* wp_data;
+  const uint32_t* reg_en;
 } fsim_netlist;
 
 /* Sinks are numbered registers 0..R-1, then write ports, then outputs.
@@ -171,7 +177,10 @@ int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl,
 int fsim_design_info_get(const fsim_design* d, fsim_design_info* out);
 /* The process of every sink (n_sinks entries) and each process's node list
  * (CSR: proc_off[n_processes + 1], proc_nodes[proc_off[n_processes]]), as
- * compiled.  Any pointer may be NULL to skip it. */
+ * compiled.  Any pointer may be NULL to skip it.  Every register with an
+ * enable (reg_en) adds two nodes after the netlist's own, in register order:
+ * a REG leaf of that register at n_nodes + 2k and MUX(en, next, leaf) at
+ * n_nodes + 2k + 1, k counting enabled registers; info.n_nodes counts them. */
 int fsim_design_partition(const fsim_design* d, uint32_t* sink_to_process,
                           uint32_t* proc_off, uint32_t* proc_nodes);
 void fsim_design_free(fsim_design* d);

@@ -139,6 +139,35 @@ Status copy_and_validate(const fsim_netlist* nl, Design& d) {
       return Status::err(FSIM_E_NETLIST, fmt("write port %llu: index out of range", k));
   for (uint32_t r = 0; r < d.R; ++r) d.reg_init[r] &= ~0ull >> (64 - d.reg_width[r]);
 
+  // Gated and divided clocks (Sec. 5.3) arrive as a per-register enable of
+  // the top clock.  Lower each one to next' = MUX(en, next, REG r) at the
+  // register's width, so the register keeps its value in cycles where the
+  // enable is zero.  The two new nodes go after the netlist's own, in
+  // register order; fibers, packing and both kernel forms then see an
+  // ordinary netlist.
+  if (nl->reg_en) {
+    const uint32_t n0 = d.N;
+    uint64_t n_en = 0;
+    for (uint32_t r = 0; r < d.R; ++r) {
+      uint32_t e = nl->reg_en[r];
+      if (e == FSIM_NONE) continue;
+      if (e >= n0) return Status::err(FSIM_E_NETLIST, fmt("register %llu: enable node out of range", r));
+      ++n_en;
+    }
+    if (n0 + 2 * n_en >= 0x7FFFFFFFull) return Status::err(FSIM_E_CAPACITY, "too many nodes");
+    for (uint32_t r = 0; r < d.R; ++r) {
+      uint32_t e = nl->reg_en[r];
+      if (e == FSIM_NONE) continue;
+      const uint32_t leaf = d.N, mux = d.N + 1;
+      d.op.push_back(FSIM_OP_REG); d.width.push_back(d.reg_width[r]);
+      d.arg.insert(d.arg.end(), {FSIM_NONE, FSIM_NONE, FSIM_NONE}); d.imm.push_back(r);
+      d.op.push_back(FSIM_OP_MUX); d.width.push_back(d.reg_width[r]);
+      d.arg.insert(d.arg.end(), {e, d.reg_next[r], leaf}); d.imm.push_back(0);
+      d.reg_next[r] = mux;
+      d.N += 2;
+    }
+  }
+
   // Kahn's algorithm; ASAP level = 1 + max operand level, leaves at 0.
   std::vector<uint32_t> indeg(d.N, 0), ucount(d.N + 1, 0);
   for (uint32_t n = 0; n < d.N; ++n)

@@ -22,27 +22,6 @@ __device__ __forceinline__ uint64_t hmix(uint64_t x) {
 
 __device__ __forceinline__ uint64_t wmask(uint32_t w) { return ~0ull >> (64u - w); }
 
-// One combinational operator on zero-extended operands, masked to w.
-__device__ __forceinline__ uint64_t alu(uint32_t op, uint32_t w, uint64_t a, uint64_t b, uint64_t c) {
-  uint64_t r;
-  switch (op) {
-    case I_AND: r = a & b; break;
-    case I_OR:  r = a | b; break;
-    case I_XOR: r = a ^ b; break;
-    case I_NOT: r = ~a; break;
-    case I_ADD: r = a + b; break;
-    case I_SUB: r = a - b; break;
-    case I_MUX: r = a ? b : c; break;
-    case I_SHL: r = b >= 64 ? 0 : (a << b); break;   // explicit: the hardware
-    case I_SHR: r = b >= 64 ? 0 : (a >> b); break;   // takes amounts mod 64
-    case I_EQ:  r = a == b; break;
-    case I_LT:  r = a < b; break;
-    case I_MUL: r = a * b; break;
-    default:    r = 0; break;
-  }
-  return r & wmask(w);
-}
-
 // One operator per lane, opcodes differing between lanes.  `present` (wave
 // uniform) holds the opcodes that occur in the chunk: each of them is
 // evaluated for every lane and kept where it is the lane's own, so the cost

@@ -42,6 +42,7 @@ class Netlist(C.Structure):
         ("mem_init", C.c_void_p),
         ("n_wports", C.c_uint32), ("wp_mem", C.c_void_p), ("wp_en", C.c_void_p),
         ("wp_addr", C.c_void_p), ("wp_data", C.c_void_p),
+        ("reg_en", C.c_void_p),
     ]
 
 
@@ -184,6 +185,11 @@ def _netlist_struct(nl):
         wp_mem=np.ascontiguousarray(nl.wp_mem, np.uint32), wp_en=np.ascontiguousarray(nl.wp_en, np.uint32),
         wp_addr=np.ascontiguousarray(nl.wp_addr, np.uint32),
         wp_data=np.ascontiguousarray(nl.wp_data, np.uint32))
+    en = getattr(nl, "reg_en", None)
+    if en is not None:
+        keep["reg_en"] = np.ascontiguousarray(en, np.uint32)
+        if keep["reg_en"].shape != keep["reg_width"].shape:
+            raise ValueError("reg_en needs one entry per register")
     s = Netlist()
     s.n_nodes, s.n_regs = len(keep["op"]), len(keep["reg_width"])
     s.n_inputs, s.n_outputs = len(keep["in_width"]), len(keep["out_node"])

@@ -15,6 +15,9 @@ hierarchy):
   in_width[I] u8; out_node[O] u32
   mem_depth[M] u32, mem_width[M] u8, mem_init[sum(depth)] u64
   wp_mem/wp_en/wp_addr/wp_data[W] u32 (write ports, applied in index order)
+  reg_en[R] u32 or None: per register an enable node (NONE = top clock); a
+      register with an enable keeps its value in cycles where that node is 0
+      (gated and divided clocks, Sec. 5.3)
 
 The synthetic designs stand in for the paper's benchmark SoCs (Sec. 6: a
 Constellation 2D mesh of Rocket tiles, Chipyard) whose RTL is not available.
@@ -57,6 +60,7 @@ class Netlist:
     wp_data: np.ndarray
     name: str = ""
     meta: dict = dataclasses.field(default_factory=dict)
+    reg_en: np.ndarray | None = None
 
     @property
     def n_nodes(self):
@@ -104,6 +108,7 @@ class Builder:
     def __init__(self):
         self.op, self.w, self.a0, self.a1, self.a2, self.imm = [], [], [], [], [], []
         self.reg_w, self.reg_init, self.reg_next, self._reg_node = [], [], [], []
+        self.reg_en = []
         self.in_w, self.outs = [], []
         self.mem_depth, self.mem_w, self.mem_init = [], [], []
         self.wp = []
@@ -135,6 +140,7 @@ class Builder:
         self.reg_w.append(w)
         self.reg_init.append(int(init) & ((1 << w) - 1))
         self.reg_next.append(NONE)
+        self.reg_en.append(NONE)
         self._reg_node.append(None)
         return len(self.reg_w) - 1
 
@@ -146,6 +152,10 @@ class Builder:
 
     def set_next(self, r, node):
         self.reg_next[r] = node
+
+    def set_enable(self, r, node):
+        """Register r takes its next value only in cycles where node != 0."""
+        self.reg_en[r] = node
 
     def op2(self, op, a, b, w=None):
         if w is None:
@@ -184,6 +194,7 @@ class Builder:
         wp = np.array(self.wp, np.uint32).reshape(-1, 4)
         rn = np.array(self.reg_next, np.uint32)
         assert not (rn == NONE).any(), "register without a next value"
+        en = np.array(self.reg_en, np.uint32)
         return Netlist(
             op=np.array(self.op, np.uint8), width=np.array(self.w, np.uint8), arg=arg,
             imm=np.array(self.imm, np.uint64),
@@ -193,7 +204,8 @@ class Builder:
             mem_depth=np.array(self.mem_depth, np.uint32), mem_width=np.array(self.mem_w, np.uint8),
             mem_init=(np.concatenate(self.mem_init) if self.mem_init else np.zeros(0, np.uint64)),
             wp_mem=wp[:, 0].copy(), wp_en=wp[:, 1].copy(), wp_addr=wp[:, 2].copy(),
-            wp_data=wp[:, 3].copy(), name=name, meta=dict(meta))
+            wp_data=wp[:, 3].copy(), name=name, meta=dict(meta),
+            reg_en=en if (en != NONE).any() else None)
 
 
 def _shift_mask(w):
@@ -581,7 +593,67 @@ def workload(name: str, **kw) -> Netlist:
         return gen_soc(2, 4, gen_core(seed=1), mesh_seed=2)
     if name == "soc48":
         return gen_soc(8, 6, gen_core(seed=1), mesh_seed=4)
+    if name == "core_clocks":
+        return add_clock_domains(gen_core(seed=1), seed=kw.get("seed", 7))
     raise KeyError(name)
+
+
+def add_clock_domains(nl: Netlist, seed=7, divisors=(2, 3, 8), n_gated=1, frac=0.5) -> Netlist:
+    """A copy of nl in which a share `frac` of the registers, drawn at random,
+    runs on a divided or gated clock instead of the top clock (Sec. 5.3:
+    one top clock and any number of gated or divided ones).
+
+    Per divisor k one 8-bit divider register counts 0..k-1 on the top clock;
+    its domain's enable is (divider == k-1), one tick every k cycles.  Per
+    gated domain one new 1-bit input port is the enable (a testbench-driven
+    clock gate).  The domains are spread uniformly over the chosen registers;
+    registers that already had an enable keep it."""
+    assert nl.reg_en is None or len(nl.reg_en) == nl.n_regs
+    rng = np.random.default_rng(seed)
+    b = Builder()
+    R0, N0, I0 = nl.n_regs, nl.n_nodes, nl.n_inputs
+    enables = []
+    div_regs = []
+    for k in divisors:
+        assert 2 <= k <= 255
+        d = b.add_reg(8, 0)
+        cur = b.reg(d)
+        tick = b.op2("EQ", cur, b.const(8, k - 1))
+        b.set_next(d, b.mux(tick, b.const(8, 0), b.op2("ADD", cur, b.const(8, 1)), w=8))
+        enables.append(tick)
+        div_regs.append(d)
+    for _ in range(n_gated):
+        enables.append(b.input(b.add_input(1)))
+    tail = b.build()
+    # renumber the new nodes, registers and ports after nl's own
+    op = np.concatenate([nl.op, tail.op])
+    width = np.concatenate([nl.width, tail.width])
+    targ = tail.arg.astype(np.uint64)
+    targ = np.where(targ == NONE, NONE, targ + N0).astype(np.uint32)
+    arg = np.concatenate([nl.arg, targ.reshape(-1, 3)])
+    timm = tail.imm.copy()
+    timm[tail.op == OPS["REG"]] += np.uint64(R0)
+    timm[tail.op == OPS["INPUT"]] += np.uint64(I0)
+    imm = np.concatenate([nl.imm, timm])
+    reg_next = np.concatenate([nl.reg_next, (tail.reg_next.astype(np.uint64) + N0).astype(np.uint32)])
+    en = np.full(R0 + tail.n_regs, NONE, np.uint32)
+    if nl.reg_en is not None:
+        en[:R0] = nl.reg_en
+    free = np.flatnonzero(en[:R0] == NONE)
+    pick = rng.permutation(free)[: int(round(frac * len(free)))]
+    dom = rng.integers(0, len(enables), len(pick))
+    en[pick] = np.array(enables, np.uint64)[dom].astype(np.uint32) + np.uint32(N0)
+    meta = dict(nl.meta, clock_domains=[f"div{k}" for k in divisors] + ["gated"] * n_gated,
+                gated_regs=int(len(pick)), divider_regs=[R0 + d for d in div_regs])
+    return Netlist(
+        op=op, width=width, arg=arg, imm=imm,
+        reg_width=np.concatenate([nl.reg_width, tail.reg_width]),
+        reg_init=np.concatenate([nl.reg_init, tail.reg_init]),
+        reg_next=reg_next, in_width=np.concatenate([nl.in_width, tail.in_width]),
+        out_node=nl.out_node.copy(), mem_depth=nl.mem_depth.copy(), mem_width=nl.mem_width.copy(),
+        mem_init=nl.mem_init.copy(), wp_mem=nl.wp_mem.copy(), wp_en=nl.wp_en.copy(),
+        wp_addr=nl.wp_addr.copy(), wp_data=nl.wp_data.copy(),
+        name=(nl.name + "+clocks") if nl.name else "clocks", meta=meta, reg_en=en)
 
 
 STIM_SEED_BASE = 0x5EED0000
@@ -596,6 +668,32 @@ def counter(w) -> Netlist:
     b.set_next(r, b.op2("ADD", b.reg(r), b.const(w, 1)))
     b.output(b.reg(r))
     return b.build(name=f"counter{w}")
+
+
+def divided_counter(w, k) -> Netlist:
+    """A w-bit counter on a clock divided by k: register 0 counts 0..k-1 on the
+    top clock, register 1 adds 1 only in cycles where register 0 is k-1, so
+    after t cycles it holds floor(t / k) mod 2**w."""
+    b = Builder()
+    d = b.add_reg(8, 0)
+    r = b.add_reg(w, 0)
+    tick = b.op2("EQ", b.reg(d), b.const(8, k - 1))
+    b.set_next(d, b.mux(tick, b.const(8, 0), b.op2("ADD", b.reg(d), b.const(8, 1)), w=8))
+    b.set_next(r, b.op2("ADD", b.reg(r), b.const(w, 1)))
+    b.set_enable(r, tick)
+    b.output(b.reg(r))
+    return b.build(name=f"divided_counter{w}_{k}")
+
+
+def gated_counter(w) -> Netlist:
+    """A w-bit counter whose clock is gated by the 1-bit input port 0: it
+    counts the cycles in which the port was 1."""
+    b = Builder()
+    g = b.add_input(1)
+    r = b.add_reg(w, 0)
+    b.set_next(r, b.op2("ADD", b.reg(r), b.const(w, 1)))
+    b.set_enable(r, b.input(g))
+    return b.build(name=f"gated_counter{w}")
 
 
 def lfsr(n, taps) -> Netlist:

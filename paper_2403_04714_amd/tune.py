@@ -28,6 +28,9 @@ def design_hash(nl) -> str:
     for f in ("op", "width", "arg", "imm", "reg_width", "reg_init", "reg_next", "in_width",
               "out_node", "mem_depth", "mem_width", "wp_mem", "wp_en", "wp_addr", "wp_data"):
         h.update(np.ascontiguousarray(getattr(nl, f)).tobytes())
+    en = getattr(nl, "reg_en", None)
+    if en is not None:
+        h.update(b"reg_en" + np.ascontiguousarray(en, np.uint32).tobytes())
     return h.hexdigest()[:16]
 
 

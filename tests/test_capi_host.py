@@ -327,3 +327,50 @@ def test_gpu_test_designs_compile(make, pack, target):
     d = F.Design(None, nl, pack=pack, target_processes=target)
     assert d.info()["n_processes"] >= 1
     d.batched_info()
+
+
+def lowered(nl):
+    """nl with every register enable written out as the header numbers it:
+    per enabled register, in register order, a REG leaf then
+    MUX(en, next, leaf) after the netlist's own nodes."""
+    import dataclasses
+    op, width, arg, imm = list(nl.op), list(nl.width), [list(a) for a in nl.arg], list(nl.imm)
+    nxt = nl.reg_next.copy()
+    for r in np.flatnonzero(nl.reg_en != g.NONE):
+        leaf = len(op)
+        op += [g.OPS["REG"], g.OPS["MUX"]]
+        width += [nl.reg_width[r]] * 2
+        arg += [[g.NONE] * 3, [nl.reg_en[r], nl.reg_next[r], leaf]]
+        imm += [r, 0]
+        nxt[r] = leaf + 1
+    return dataclasses.replace(nl, op=np.array(op, np.uint8), width=np.array(width, np.uint8),
+                               arg=np.array(arg, np.uint32), imm=np.array(imm, np.uint64),
+                               reg_next=nxt, reg_en=None)
+
+
+@pytest.mark.parametrize("pack,target", [(F.PACK_FIBERS, 0), (F.PACK_SLB, 9), (F.PACK_HYPER, 9)])
+def test_clock_enables_lowered_by_the_compiler(pack, target):
+    """Gated and divided clocks (Sec. 5.3): the compiler's processes, run by
+    the oracle's partitioned mode on the netlist with its enables written out
+    as multiplexers, give the oracle's own enable semantics; the compiled node
+    count includes the two nodes per enabled register."""
+    nl = g.add_clock_domains(g.gen_tiny(6), seed=4)
+    n_en = int((nl.reg_en != g.NONE).sum())
+    d = host_design(nl, pack=pack, target_processes=target)
+    assert d.info()["n_nodes"] == nl.n_nodes + 2 * n_en
+    stp, off, nodes = d.partition()
+    s0 = O.Sim(nl, seed=2)
+    d0 = s0.step(120, digests=True)
+    s1 = O.Sim(lowered(nl), seed=2)
+    d1 = s1.step_partitioned(120, stp, off, nodes, digests=True)
+    assert np.array_equal(d0, d1)
+
+
+def test_clock_enable_out_of_range_rejected():
+    import dataclasses
+    nl = g.gen_tiny(0)
+    en = np.full(nl.n_regs, g.NONE, np.uint32)
+    en[5] = nl.n_nodes + 1
+    with pytest.raises(F.FsimError) as e:
+        host_design(dataclasses.replace(nl, reg_en=en))
+    assert e.value.code == F.E_NETLIST
