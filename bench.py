@@ -622,6 +622,9 @@ def main():
         ]
         out["plain_soc8"] = bench_plain_tuned(F, g, tune, ctx, "soc8", (1024, 2048, 4096), (64, 256),
                                               5000, 500, seed)
+        # the single-core design with half of its registers on gated or divided clocks
+        out["plain_core_clocks"] = bench_plain_tuned(F, g, tune, ctx, "core_clocks", (1024, 2048, 4096),
+                                                     (64,), 5000, 500, seed)
         out["served"] = bench_served(F, g, ctx, n_jobs=24, lam=4.0, inst_hi=1024, cyc_lo=100, cyc_hi=2000)
         out["extra_sections_s"] = round(time.time() - extra_t0, 1)
     if args.soc48:
