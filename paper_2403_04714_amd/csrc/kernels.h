@@ -9,6 +9,12 @@
 
 namespace fsim {
 
+// One-wave plain kernel reading instructions from global memory: the first
+// instructions of this many chunks are in flight at once (a chunk's load is
+// issued this many chunks before it runs).  The LDS chunk table holds at
+// least kWaveSlots + 1 zero words past a process's last chunk.
+constexpr uint32_t kWaveSlots = 2;
+
 struct PlainArgs {
   const Instr* instr;
   const uint32_t* levels;      // per process: chunk index where each level starts

@@ -223,14 +223,15 @@ __device__ void plain_body(const PlainArgs& A) {
 
 // Single-wave processes (64 threads): LDS operations of one wave complete in
 // order, so the levels need no barrier and the chunks of all levels run as
-// one flat sequence.  The chunk words sit in four registers (lane k of word q
-// holds chunk 64 q + k, read with v_readlane) and the first instruction of
-// the next chunk is fetched while the current chunk runs.
+// one flat sequence.  The chunk words sit in an LDS table after the value
+// slots, each read with one broadcast LDS read a few chunks ahead, and the
+// first instruction of a later chunk is fetched while the current one runs.
 // STAGED: the process's instructions are copied into LDS at launch and read
 // from there.  Otherwise they are read from global memory, the first
-// instruction of each chunk two chunks ahead, and the workgroup's LDS holds
-// only the value slots, so that many more workgroups are resident at once
-// (large designs) and nothing is copied per launch.
+// instruction of each chunk kWaveSlots chunks ahead, and the workgroup's LDS
+// holds only the value slots and the chunk table, so that many more
+// workgroups are resident at once (large designs) and nothing is copied per
+// launch.
 template <bool PERSISTENT, bool STAGED, bool TRACE>
 __device__ void plain_wave_body(const PlainArgs& A) {
   extern __shared__ uint64_t lds[];
@@ -406,39 +407,57 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         if (TRACE && trace_row) stamp(c);
       }
     } else {
-      // instructions from global memory: two slots hold the first
-      // instructions of chunks c and c + 1; a chunk decodes its slot and
-      // refills it with chunk c + 2's, so every load has two chunks' time to
-      // land.  The loop is unrolled by two so that no slot is ever copied
-      // while its load is in flight (a copy would wait for it at once).
-      uint32_t ch = rfl(ctab[0]), chn = rfl(ctab[1]), ch2 = rfl(ctab[2]);
-      uint4 s0 = first_instr(ch), s1 = first_instr(chn);
+      // instructions from global memory: kWaveSlots slots hold the first
+      // instructions of chunks c .. c + kWaveSlots - 1; a chunk decodes its
+      // slot and refills it with chunk c + kWaveSlots's, so every load has
+      // kWaveSlots chunks' time to land.  The loop is unrolled by kWaveSlots
+      // so that no slot is ever copied while its load is in flight (a copy
+      // would wait for it at once).  cw holds the wave-uniform chunk words
+      // c .. c + kWaveSlots.
+      constexpr uint32_t K = kWaveSlots;
+      static_assert(K >= 2 && K <= 4, "two to four slots");
+      uint32_t cw[K + 1];
+#pragma unroll
+      for (uint32_t k = 0; k <= K; ++k) cw[k] = rfl(ctab[k]);
+      uint4 s0 = first_instr(cw[0]), s1 = first_instr(cw[1]);
+      uint4 s2 = K > 2 ? first_instr(cw[2]) : uint4{0, 0, 0, 0};
+      uint4 s3 = K > 3 ? first_instr(cw[3]) : uint4{0, 0, 0, 0};
       auto one = [&](uint4& slot) {
-        const uint32_t w3 = ctab[c + 3];
+        const uint32_t wn = ctab[c + K + 1];
+        const uint32_t ch = cw[0];
         if ((ch >> 24) == I_ALU) {
           const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
           const Dec in = decode(slot);
           uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
-          slot = first_instr(ch2);
+          slot = first_instr(cw[K]);
           asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
           const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
           const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
           if (lane < cnt) at(in.dst) = r;
         } else {
           const uint4 raw = slot;
-          slot = first_instr(ch2);
+          slot = first_instr(cw[K]);
           other_chunk(raw, ch);
         }
         ++c;
-        ch = chn;
-        chn = ch2;
-        ch2 = rfl(w3);
+#pragma unroll
+        for (uint32_t k = 0; k < K; ++k) cw[k] = cw[k + 1];
+        cw[K] = rfl(wn);
         if (TRACE && trace_row) stamp(c);
       };
       while (c < n_ch) {
         one(s0);
         if (c >= n_ch) break;
         one(s1);
+        if (c >= n_ch) break;
+        if constexpr (K > 2) {
+          one(s2);
+          if (c >= n_ch) break;
+        }
+        if constexpr (K > 3) {
+          one(s3);
+          if (c >= n_ch) break;
+        }
       }
     }
     if (lane == 0) {

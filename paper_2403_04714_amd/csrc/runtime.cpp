@@ -78,7 +78,7 @@ static constexpr uint32_t kStaticLds = 1024;     // abort flag, reduction scratc
 // largest process, three zero entries for the words it reads ahead, rounded
 // up to a multiple of 4 so that the staged instructions after it stay
 // 16-byte aligned
-static uint32_t wave_ctab_words(const fsim_design* d) { return (d->max_chunks + 3 + 3) & ~3u; }
+static uint32_t wave_ctab_words(const fsim_design* d) { return (d->max_chunks + fsim::kWaveSlots + 1 + 3) & ~3u; }
 
 template <class T>
 static int upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
