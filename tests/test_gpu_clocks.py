@@ -60,7 +60,9 @@ def test_clock_domains_tiny_batched(F, ctx):
 
 def test_clock_domains_tiny_batched_two_tiles(F, ctx):
     nl = g.add_clock_domains(g.gen_tiny(7), seed=5)
-    check_batched(F, ctx, nl, 200, 150, target=6, tiles_per_wave=2, full_state={0, 127, 199})
+    # one wave per workgroup: two tiles of this design's slots need 40 KiB of LDS
+    check_batched(F, ctx, nl, 200, 150, target=6, threads=64, tiles_per_wave=2,
+                  full_state={0, 127, 199})
 
 
 def test_core_with_clock_domains_plain_full_size(F, ctx):
