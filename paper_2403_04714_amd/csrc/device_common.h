@@ -23,13 +23,33 @@ __device__ __forceinline__ uint64_t hmix(uint64_t x) {
 __device__ __forceinline__ uint64_t wmask(uint32_t w) { return ~0ull >> (64u - w); }
 
 // One operator per lane, opcodes differing between lanes.  `present` (wave
-// uniform) holds the opcodes that occur in the chunk: each of them is
-// evaluated for every lane and kept where it is the lane's own, so the cost
-// is a few vector instructions per opcode present, without divergent
-// branches.
+// uniform) holds the opcodes that occur in the chunk.  A chunk of a single
+// opcode (most chunks of deep, narrow processes) dispatches once on it with
+// scalar branches and evaluates it alone.  Otherwise each opcode present is
+// evaluated for every lane and kept where it is the lane's own, a few vector
+// instructions per opcode present, without divergent branches.
 __device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uint32_t w, uint64_t a,
                                               uint64_t b, uint64_t c) {
   uint64_t r = 0;
+  if ((present & (present - 1)) == 0) {
+    // the empty asm keeps the dispatch a tree of real (scalar) branches
+    switch (__builtin_ctz(present | (1u << 31))) {
+      case I_AND: asm volatile(""); r = a & b; break;
+      case I_OR:  asm volatile(""); r = a | b; break;
+      case I_XOR: asm volatile(""); r = a ^ b; break;
+      case I_NOT: asm volatile(""); r = ~a; break;
+      case I_ADD: asm volatile(""); r = a + b; break;
+      case I_SUB: asm volatile(""); r = a - b; break;
+      case I_MUX: asm volatile(""); r = a ? b : c; break;
+      case I_SHL: asm volatile(""); r = b >= 64 ? 0 : (a << (b & 63)); break;
+      case I_SHR: asm volatile(""); r = b >= 64 ? 0 : (a >> (b & 63)); break;
+      case I_EQ:  asm volatile(""); r = a == b; break;
+      case I_LT:  asm volatile(""); r = a < b; break;
+      case I_MUL: asm volatile(""); r = a * b; break;
+      default: break;
+    }
+    return r & wmask(w);
+  }
   // the empty asm keeps each test a real (scalar) branch, so opcodes absent
   // from the chunk cost two scalar instructions instead of being computed
 #define FSIM_MIXED(OPC, EXPR) \

@@ -380,15 +380,16 @@ __device__ void plain_wave_body(const PlainArgs& A) {
           // a run of operator chunks: operand reads, then the next chunk's
           // first instruction; only the operands are waited for
           do {
-            const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
             const Dec in = decode(raw);
             uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
             const uint4 rn = first_instr(chn);
             const uint32_t w2 = ctab[c + 2];
             asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
             const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
-            const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
-            if (lane < cnt) at(in.dst) = r;
+            // lanes past the chunk's end repeat its last instruction on the
+            // same operands, so their store writes the same value to the
+            // same slot and needs no guard
+            at(in.dst) = alu_mixed(present, in.op, in.w, a, b, cc);
             ++c;
             ch = chn;
             chn = rfl(w2);
@@ -426,14 +427,14 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         const uint32_t wn = ctab[c + K + 1];
         const uint32_t ch = cw[0];
         if ((ch >> 24) == I_ALU) {
-          const uint32_t cnt = ((ch >> 16) & 0xFF) + 1;
           const Dec in = decode(slot);
           uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
           slot = first_instr(cw[K]);
           asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
           const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
-          const uint64_t r = alu_mixed(present, in.op, in.w, a, b, cc);
-          if (lane < cnt) at(in.dst) = r;
+          // unguarded store: lanes past the chunk's end repeat its last
+          // instruction (same operands, same slot, same value)
+          at(in.dst) = alu_mixed(present, in.op, in.w, a, b, cc);
         } else {
           const uint4 raw = slot;
           slot = first_instr(cw[K]);
