@@ -610,7 +610,10 @@ def main():
                    "autotune_s": round(tune_s, 2), "state_bytes_packed": state_bytes},
         "launch": {"mode": {1: "persistent", 2: "per_cycle", 3: "graph"}[best["launch"]],
                    "workgroups": lay["workgroups"], "threads": lay["threads"],
-                   "instructions_in_lds": lay["staged"]},
+                   "instructions_in_lds": lay["staged"],
+                   # the same run again: bench.py --plain-config <this>
+                   "plain_config": f"{best['target']}:{best['threads']}:{best['launch']}:"
+                                   f"{F.STAGE_LDS if lay['staged'] else F.STAGE_GLOBAL}:{best['pack']}"},
         "wall_s_timed": round(wall, 3),
     }
     if not args.no_extra:
