@@ -77,17 +77,18 @@ def measured_traffic(kernel, workload, processes, threads):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(nl, seed, budget_s=12.0):
-    """The oracle as it stands, single thread, on a bounded prefix."""
+def cpu_baseline(nl, seed, budget_s=15.0):
+    """The oracle as it stands, single thread, on a bounded prefix: 20
+    warm-up cycles, then blocks of 100 cycles until budget_s has passed."""
     from oracle import oracle as orc
     sim = orc.Sim(nl, seed=seed)
-    t0 = time.perf_counter()
     sim.step(20)
-    per = (time.perf_counter() - t0) / 20
-    n = max(50, int(budget_s / max(per, 1e-9)))
+    n, dt = 0, 0.0
     t0 = time.perf_counter()
-    sim.step(n)
-    dt = time.perf_counter() - t0
+    while dt < budget_s:
+        sim.step(100)
+        n += 100
+        dt = time.perf_counter() - t0
     return dict(value=n / dt, unit="instance-cycles/s", cores=1, kind="oracle",
                 sample=f"{nl.name}: 1 instance, cycles 20..{20 + n} of the same stimulus, "
                        f"single-threaded C oracle ({dt:.1f} s)")
