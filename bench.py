@@ -481,7 +481,7 @@ def main():
         elif args.profile_run == "plain-core":
             d = F.Design(ctx, g.workload("core"), pack=F.PACK_HYPER, target_processes=2048)
             sim = F.Sim(d, 1, launch=F.LAUNCH_PER_CYCLE, wg_threads=64, seed=g.STIM_SEED_BASE,
-                        stage=F.STAGE_GLOBAL)
+                        stage=F.STAGE_LDS)
         else:
             import numpy as np
             d = F.Design(ctx, g.prng_array(7 * 64), partition=np.arange(7 * 64, dtype=np.uint32) // 7)
