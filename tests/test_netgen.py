@@ -76,3 +76,35 @@ def test_prng_array_is_independent_xorshift32():
     for _ in range(11):
         x = [xs(v) for v in x]
     assert [int(v) for v in ref.regs()] == x
+
+
+def test_clock_domains_structure():
+    """add_clock_domains keeps the design, adds one divider register per
+    divisor and one 1-bit gate port per gated domain, and gives half of the
+    original registers an enable that is a 1-bit node of one of the domains."""
+    base = g.gen_tiny(3)
+    nl = g.add_clock_domains(base, seed=5, divisors=(2, 3, 8), n_gated=1, frac=0.5)
+    R0, N0 = base.n_regs, base.n_nodes
+    assert nl.n_regs == R0 + 3 and nl.n_inputs == base.n_inputs + 1
+    for f in ("op", "width", "imm"):
+        assert np.array_equal(getattr(nl, f)[:N0], getattr(base, f))
+    assert np.array_equal(nl.arg[:N0], base.arg)
+    assert np.array_equal(nl.reg_next[:R0], base.reg_next)
+    en = nl.reg_en
+    gated = np.flatnonzero(en[:R0] != g.NONE)
+    assert len(gated) == round(0.5 * R0) == nl.meta["gated_regs"]
+    assert (en[R0:] == g.NONE).all()                  # dividers run on the top clock
+    domains = set(int(x) for x in en[gated])
+    assert len(domains) == 4                          # three dividers and one gate
+    for e in domains:
+        assert e >= N0 and nl.width[e] == 1
+        assert nl.op[e] in (g.OPS["EQ"], g.OPS["INPUT"])
+    # deterministic
+    again = g.add_clock_domains(base, seed=5, divisors=(2, 3, 8), n_gated=1, frac=0.5)
+    assert np.array_equal(again.reg_en, en)
+
+
+def test_core_clocks_workload():
+    nl = g.workload("core_clocks")
+    assert nl.n_regs == 20003 and nl.meta["gated_regs"] == 10000
+    assert nl.reg_en is not None and len(nl.reg_en) == nl.n_regs
