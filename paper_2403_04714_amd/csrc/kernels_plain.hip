@@ -395,7 +395,9 @@ __device__ void plain_wave_body(const PlainArgs& A) {
             chn = rfl(w2);
             raw = rn;
             if (TRACE && trace_row) stamp(c);
-          } while (c < n_ch && (ch >> 24) == I_ALU);
+            // the chunk table is zero past the last chunk (kind 0), so the
+            // run also ends at the end of the process
+          } while ((ch >> 24) == I_ALU);
           continue;
         }
         const uint4 rn = first_instr(chn);
