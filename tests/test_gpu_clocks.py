@@ -35,6 +35,15 @@ def test_divided_counter_plain(F, ctx, k):
     assert int(s.regs()[1]) == (1000 // k) % 256
 
 
+def test_multibit_enable_plain_and_batched(F, ctx):
+    """An enable wider than one bit ticks on any non-zero value."""
+    from tests.test_oracle_clocks import wide_enable_counter
+    nl = wide_enable_counter(5)
+    d, s = run_both(F, ctx, nl, 600, F.PACK_FIBERS)
+    assert int(s.regs()[1]) == 600 - (600 + 4) // 5
+    check_batched(F, ctx, nl, 65, 200, full_state={0, 64})
+
+
 def test_gated_counter_plain_and_batched(F, ctx):
     nl = g.gated_counter(12)
     run_both(F, ctx, nl, 700, F.PACK_SINGLE)

@@ -8,7 +8,8 @@ enable of the top clock.
   moved wholesale onto a clock divided by k visits, at cycle t, the state the
   undivided LFSR has at cycle floor(t / k), and holds it in between;
 - special cases: an enable that is constantly 1 is the top clock, one that is
-  constantly 0 freezes the register at its initial value;
+  constantly 0 freezes the register at its initial value, and a multi-bit
+  enable ticks on any non-zero value (not on its low bit);
 - BSP: evaluating every fiber (or a random grouping of fibers) on its own
   gives the monolithic result, so the enable belongs to the register's cone;
   a fiber that left the enable out would miss an operand and fail.
@@ -143,3 +144,28 @@ def test_clock_domains_change_the_trajectory():
     a.step(20)
     b.step(20)
     assert not np.array_equal(a.regs(), b.regs()[: base.n_regs])
+
+
+def wide_enable_counter(k, w=12):
+    """A counter whose enable is an 8-bit divider's whole value (not one bit):
+    it ticks in every cycle whose divider value is non-zero."""
+    b = g.Builder()
+    d = b.add_reg(8, 0)
+    r = b.add_reg(w, 0)
+    wrap = b.op2("EQ", b.reg(d), b.const(8, k - 1))
+    b.set_next(d, b.mux(wrap, b.const(8, 0), b.op2("ADD", b.reg(d), b.const(8, 1)), w=8))
+    b.set_next(r, b.op2("ADD", b.reg(r), b.const(w, 1)))
+    b.set_enable(r, b.reg(d))
+    return b.build(name=f"wide_enable_counter{k}")
+
+
+@pytest.mark.parametrize("k", [2, 5, 9])
+def test_enable_is_any_nonzero_value(k):
+    """The enable is 'non-zero', not 'bit 0': with the divider's value as
+    enable (multi-bit, even values included) the counter misses exactly the
+    cycles whose divider value is 0, i.e. t - ceil(t / k) ticks in t cycles."""
+    nl = wide_enable_counter(k)
+    s = O.Sim(nl)
+    for t in range(1, 4 * k + 100):
+        s.step(1)
+        assert int(s.regs()[1]) == t - (t + k - 1) // k, t
