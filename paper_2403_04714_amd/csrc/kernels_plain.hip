@@ -281,8 +281,9 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   if (lane == 0) abort_flag = 0;
   __syncthreads();
   // the first instruction of a chunk for this lane; lanes past the chunk's
-  // end get its last instruction (valid slots to read, their results are
-  // not stored).  No condition: the load stays in the basic block of the
+  // end get its last instruction (valid slots to read; an operator chunk
+  // stores their result, the same value to the same slot as the last lane,
+  // other chunks guard by count).  No condition: the load stays in the basic block of the
   // operand reads it overlaps.  For "no chunk" (word 0) it reads entry 0.
   auto first_instr = [&](uint32_t chw) -> uint4 {
     const uint32_t m = (chw >> 16) & 0xFF;
