@@ -72,36 +72,59 @@ __device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uin
 
 static constexpr long kSpinLimit = 1l << 22;
 
-// Grid-wide barrier over G workgroups (see the file comment).  Returns false
-// if the poll exceeded its bound or another workgroup already gave up; the
-// caller then leaves its cycle loop so that every wave exits.
+// Polls n epoch flags (one per lane, strided by 64) until every one has
+// reached `epoch`.  Gives up, returning false, once another workgroup has
+// raised the error word or the poll has exceeded its bound (then it raises
+// the error word itself).
+__device__ __forceinline__ bool poll_flags(const uint32_t* f, uint32_t n, uint32_t epoch, uint32_t* error) {
+  long spins = 0;
+  for (;;) {
+    bool mine = true;
+    for (uint32_t g = threadIdx.x; g < n; g += 64) {
+      const uint32_t v = __hip_atomic_load(&f[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((int32_t)(v - epoch) < 0) mine = false;
+    }
+    if (__all(mine)) return true;
+    __builtin_amdgcn_s_sleep(1);
+    if ((++spins & 1023) == 0) {
+      if (__hip_atomic_load(&error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+      if (spins > kSpinLimit) {
+        if (threadIdx.x == 0) atomicOr(&error[0], 1u);
+        return false;
+      }
+    }
+  }
+}
+
+// Grid-wide barrier over G workgroups (see the file comment), in two levels:
+// each workgroup stores its epoch flag; the first workgroup of every group
+// of 64 waits for its group's flags and then stores the group's flag; every
+// workgroup waits for the group flags.  Returns false if a poll exceeded its
+// bound or another workgroup already gave up; the caller then leaves its
+// cycle loop so that every wave exits.
 __device__ __forceinline__ bool grid_barrier(uint32_t* flags, uint32_t* error, uint32_t G,
                                              uint32_t epoch, int* lds_abort) {
   __syncthreads();
   if (threadIdx.x < 64) {
+    uint32_t* const group_flags = flags + G;
+    const uint32_t grp = blockIdx.x / 64;
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_store(&flags[blockIdx.x], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    long spins = 0;
     bool ok = true;
-    for (;;) {
-      bool mine = true;
-      for (uint32_t g = threadIdx.x; g < G; g += 64) {
-        uint32_t v = __hip_atomic_load(&flags[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((int32_t)(v - epoch) < 0) mine = false;
-      }
-      if (__all(mine)) break;
-      __builtin_amdgcn_s_sleep(1);
-      if ((++spins & 1023) == 0) {
-        if (__hip_atomic_load(&error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = false; break; }
-        if (spins > kSpinLimit) {
-          if (threadIdx.x == 0) atomicOr(&error[0], 1u);
-          ok = false;
-          break;
-        }
+    if (blockIdx.x % 64 == 0) {
+      const uint32_t n = G - 64 * grp < 64 ? G - 64 * grp : 64;
+      ok = poll_flags(flags + 64 * grp, n, epoch, error);
+      // what the group's workgroups wrote before their flags is published
+      // again with the group flag
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (ok && threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&group_flags[grp], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
+    if (ok) ok = poll_flags(group_flags, (G + 63) / 64, epoch, error);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (threadIdx.x == 0) *lds_abort = ok ? 0 : 1;
   }

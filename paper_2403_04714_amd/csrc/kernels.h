@@ -15,6 +15,10 @@ namespace fsim {
 // least kWaveSlots + 1 zero words past a process's last chunk.
 constexpr uint32_t kWaveSlots = 2;
 
+// Words of the grid barrier's flag array for G workgroups: one epoch flag per
+// workgroup, then one per group of 64 workgroups.
+constexpr uint32_t barrier_words(uint32_t G) { return G + (G + 63) / 64; }
+
 struct PlainArgs {
   const Instr* instr;
   const uint32_t* levels;      // per process: chunk index where each level starts

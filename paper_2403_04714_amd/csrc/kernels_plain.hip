@@ -22,11 +22,13 @@
 // the persistent launch once there are more than a few dozen workgroups.
 //
 // The barrier (Sec. 4.1 measures the same cost on the IPU and on x64) uses
-// one epoch flag per workgroup: arrivals are plain stores to distinct words
-// and every workgroup polls all flags, so no read-modify-write serialises
-// the arrivals.  Cross-XCD visibility of the next-state stores comes from an
-// agent-scope release before the flag store and an agent-scope acquire after
-// the poll.
+// one epoch flag per workgroup: arrivals are plain stores to distinct words,
+// so no read-modify-write serialises them.  The first workgroup of every
+// group of 64 polls its group's flags and then stores a group flag; every
+// workgroup polls the group flags, so a poll round reads G / 64 words per
+// workgroup instead of G.  Cross-XCD visibility of the next-state stores
+// comes from agent-scope releases before the flag stores and agent-scope
+// acquires after the polls.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

@@ -228,7 +228,7 @@ Layout layout(const Design& d, uint32_t n_inst, uint32_t G, bool batched) {
   L.outputs = take((size_t)d.O * 8 * n_pad);
   L.mem = take(d.mem_off[d.M] * 8 * n_pad);
   L.keys = take((size_t)d.I * 8 * n_pad);
-  L.flags = take((size_t)std::max(G, 1u) * 4);
+  L.flags = take((size_t)fsim::barrier_words(std::max(G, 1u)) * 4);
   L.error = take(16);
   L.cyc = take(8);
   L.total = off;
@@ -278,7 +278,7 @@ static int sim_reset_state(fsim_sim* s) {
     }
     if (d.O) HIP_TRY(hipMemsetAsync(s->outputs, 0, (size_t)d.O * 8 * NP, st));
   }
-  HIP_TRY(hipMemsetAsync(s->flags, 0, (size_t)s->G * 4, st));
+  HIP_TRY(hipMemsetAsync(s->flags, 0, (size_t)fsim::barrier_words(s->G) * 4, st));
   HIP_TRY(hipMemsetAsync(s->error, 0, 16, st));
   HIP_TRY(hipMemsetAsync(s->cyc_dev, 0, 8, st));
   HIP_TRY(hipStreamSynchronize(st));
