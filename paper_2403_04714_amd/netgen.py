@@ -323,7 +323,8 @@ def gen_core(seed=1, params: CoreParams | None = None) -> Netlist:
     special = set(link_regs) | set(rd_regs)
     mems = []
     for m in range(P.n_mems):
-        init = rng.integers(0, 2**63, P.mem_depth, dtype=np.int64).astype(np.uint64) * np.uint64(2)
+        # every bit of every word is drawn, bit 0 and bit 63 included
+        init = rng.integers(0, 2**64, P.mem_depth, dtype=np.uint64)
         mems.append(b.add_mem(P.mem_depth, P.mem_width, init))
 
     recent = []          # (node, depth) window of recently built operators
@@ -346,7 +347,7 @@ def gen_core(seed=1, params: CoreParams | None = None) -> Netlist:
         # a small pool of constants per width keeps the node count honest
         key = (w, int(rng.integers(0, 4)))
         if key not in consts:
-            consts[key] = b.const(w, int(rng.integers(0, 2**63)) & ((1 << w) - 1))
+            consts[key] = b.const(w, int(rng.integers(0, 2**64, dtype=np.uint64)) & ((1 << w) - 1))
         return consts[key]
 
     def side(r, chain, cw, maxd):
@@ -751,6 +752,33 @@ def prng_array(n, seed=0x5EED) -> Netlist:
         mem_depth=np.zeros(0, np.uint32), mem_width=np.zeros(0, np.uint8), mem_init=np.zeros(0, np.uint64),
         wp_mem=np.zeros(0, np.uint32), wp_en=np.zeros(0, np.uint32), wp_addr=np.zeros(0, np.uint32),
         wp_data=np.zeros(0, np.uint32), name=f"prng{n}", meta=dict(seed=seed))
+
+
+def mul_mix(seed=11, widths=(1, 7, 32, 33, 64), per_width=8) -> Netlist:
+    """Word-level multipliers (the optional MUL operator) at widths 1, 7,
+    32, 33 and 64: per width, per_width registers each take
+    ADD(MUL(MUL(x, y), port), MUL(own, odd constant)) of two other
+    registers x, y of the width and the width's input port, so that products
+    wrap past 64 bits and are masked back to narrow widths every cycle.  A
+    MUL of operands of different widths and one register of every width
+    feeding an output exercise the zero extension."""
+    rng = np.random.default_rng(seed)
+    b = Builder()
+    ports = {w: b.add_input(w) for w in widths}
+    regs = {w: [b.add_reg(w, int(rng.integers(0, 2**64, dtype=np.uint64))) for _ in range(per_width)]
+            for w in widths}
+    for w in widths:
+        rs = regs[w]
+        for k, r in enumerate(rs):
+            x, y = b.reg(rs[(k + 1) % per_width]), b.reg(rs[(k + 3) % per_width])
+            p = b.op2("MUL", b.op2("MUL", x, y, w=w), b.input(ports[w]), w=w)
+            odd = int(rng.integers(0, 2**64, dtype=np.uint64)) | 1
+            b.set_next(r, b.op2("ADD", p, b.op2("MUL", b.reg(r), b.const(w, odd), w=w), w=w))
+        b.output(b.reg(rs[0]))
+    # mixed widths: a 33-bit value times a 64-bit one, kept at 7 bits
+    m = b.op2("MUL", b.reg(regs[33][1]), b.reg(regs[64][2]), w=7)
+    b.output(m)
+    return b.build(name=f"mul_mix(seed={seed})")
 
 
 def swap_pair(w=16, a0=0x1234, b0=0xBEEF) -> Netlist:

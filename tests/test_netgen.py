@@ -108,3 +108,16 @@ def test_core_clocks_workload():
     nl = g.workload("core_clocks")
     assert nl.n_regs == 20003 and nl.meta["gated_regs"] == 10000
     assert nl.reg_en is not None and len(nl.reg_en) == nl.n_regs
+
+
+def test_core_memory_init_draws_every_bit():
+    """Random memory initialisation covers the whole 64-bit word: every bit
+    position, the lowest and the highest included, is set in about half of
+    the words (a bit stuck at zero would hide read-path errors on that bit
+    until the word is first written)."""
+    nl = g.gen_core(1)
+    w = nl.mem_init
+    assert w.size == 2 * 4096
+    bits = (w[:, None] >> np.arange(64, dtype=np.uint64)[None, :]) & np.uint64(1)
+    frac = bits.mean(axis=0)
+    assert frac.min() > 0.45 and frac.max() < 0.55, (frac.min(), frac.max())

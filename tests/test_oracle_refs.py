@@ -1,0 +1,64 @@
+"""The stored oracle results (tests/golden/oracle_refs.json) belong to the
+current generator and to the oracle: every record's netlist fingerprint
+matches what the generator gives now, the digests each record keeps in the
+clear are what the oracle computes for them, and the first block of the
+single core's 100,000-cycle record hashes to the stored value when the
+oracle recomputes it."""
+import numpy as np
+import pytest
+
+import oracle_refs as R
+from oracle import oracle as O
+from paper_2403_04714_amd import netgen as g
+
+WORKLOADS = ("core", "soc8", "soc48")
+
+
+@pytest.fixture(scope="module")
+def refs():
+    import json
+    with open(R.REFS_PATH) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def nets():
+    return {w: g.workload(w) for w in WORKLOADS}
+
+
+def test_every_record_matches_the_generator(refs, nets):
+    assert set(refs) >= {"core_x1_100k", "core_x1024_100", "soc8_x1_2000", "soc8_x256_100",
+                         "soc8_sample_1000", "soc48_x1_500", "soc48_x64_64", "soc48_sample_300"}
+    for name, rec in refs.items():
+        R.check_netlist(rec, nets[rec["workload"]])
+        assert rec["seed_base"] == g.STIM_SEED_BASE
+        for i, r in rec["instances"].items():
+            assert len(r["digest_blocks"]) == -(-rec["cycles"] // rec["block"]), (name, i)
+
+
+def test_clear_digests_are_the_oracles(refs, nets):
+    checked = 0
+    for name, rec in refs.items():
+        for i, r in rec["instances"].items():
+            if "head" not in r:
+                continue
+            sim = O.Sim(nets[rec["workload"]], seed=rec["seed_base"] + int(i))
+            d = sim.step(len(r["head"]), digests=True)
+            assert [f"{int(x):016x}" for x in d] == r["head"], (name, i)
+            checked += 1
+    assert checked >= 8
+
+
+def test_first_block_of_the_long_run_recomputed(refs, nets):
+    rec = refs["core_x1_100k"]
+    sim = O.Sim(nets["core"], seed=rec["seed_base"])
+    d = sim.step(rec["block"], digests=True)
+    assert R.h64(d) == rec["instances"]["0"]["digest_blocks"][0]
+
+
+def test_hash_is_over_little_endian_words():
+    # the stored hashes are SHA-256 over little-endian uint64 words
+    import hashlib
+    a = np.array([1, 2**64 - 1], dtype=np.uint64)
+    want = hashlib.sha256(bytes([1, 0, 0, 0, 0, 0, 0, 0] + [255] * 8)).hexdigest()[:16]
+    assert R.h64(a) == want
