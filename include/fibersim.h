@@ -137,7 +137,11 @@ typedef struct fsim_compile_opts {
                                  limit); 0 = derived from the LDS size       */
 } fsim_compile_opts;
 
-typedef struct fsim_design_info {
+/* Statistics of a compiled design (the fibers of Sec. 3.2, the processes
+ * of Sec. 5.1 and the straggler bound of Sec. 4.3).  The struct and the
+ * query that fills it share the name fsim_design_info, as POSIX's struct stat
+ * and stat() do, so the struct is always written with its tag. */
+struct fsim_design_info {
   uint32_t n_nodes, n_live_ops, n_regs, n_sinks, n_processes, max_depth;
   uint64_t sum_fiber_ops;     /* sum over sinks of combinational cone size  */
   uint64_t sum_process_ops;   /* sum over processes of union cone size      */
@@ -149,7 +153,10 @@ typedef struct fsim_design_info {
   uint32_t max_process_levels;
   uint32_t max_process_nodes;
   double compile_seconds;
-} fsim_design_info;
+  uint32_t plain_max_slots;   /* plain form: LDS value slots (8 B) of the
+                                 largest process, allocated by liveness      */
+  uint32_t plain_max_chunks;  /* plain form: chunks of the longest process   */
+};
 
 typedef struct fsim_ctx fsim_ctx;
 typedef struct fsim_design fsim_design;
@@ -174,7 +181,14 @@ int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_bytes,
 int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl,
                      const fsim_partition* partition,
                      const fsim_compile_opts* opts, fsim_design** out);
-int fsim_design_info_get(const fsim_design* d, fsim_design_info* out);
+/* Fill *out with the design's statistics: fibers (Sec. 3.2), processes and
+ * the duplication they cost (Sec. 3.2: shared nodes are recomputed in every
+ * process that needs them; D_f and D_p below), the straggler bound and the
+ * costliest process (Sec. 4.3), depth and program size.  FSIM_E_ARG on a
+ * NULL argument.  fsim_design_info_get is the same call under another
+ * name. */
+int fsim_design_info(const fsim_design* d, struct fsim_design_info* out);
+int fsim_design_info_get(const fsim_design* d, struct fsim_design_info* out);
 /* The process of every sink (n_sinks entries) and each process's node list
  * (CSR: proc_off[n_processes + 1], proc_nodes[proc_off[n_processes]]), as
  * compiled.  Any pointer may be NULL to skip it.  Every register with an
@@ -235,9 +249,15 @@ typedef struct fsim_sim_opts {
  * one instance it covers both forms. */
 int fsim_sim_footprint(const fsim_design* d, uint32_t n_instances, size_t* device_bytes);
 
-/* workspace: caller-owned device memory of at least fsim_sim_footprint()
+/* Create a sim of n_instances independent state copies of the design.
+ * workspace: caller-owned device memory of at least fsim_sim_footprint()
  * bytes, 256-byte aligned (e.g. a torch uint8 tensor), or NULL to let the
- * library allocate.  opts may be NULL. */
+ * library allocate.  The one workspace region holds every per-sim device
+ * buffer (state halves, memories, outputs, stimulus keys, barrier flags),
+ * so a caller hands over one allocation instead of a table of buffers.
+ * opts may be NULL.  FSIM_E_CAPACITY when the form asked for cannot run the
+ * design (LDS, co-residency of a persistent launch), FSIM_E_ARG for bad
+ * options or a short or misaligned workspace. */
 int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* workspace,
                     size_t workspace_bytes, const fsim_sim_opts* opts, fsim_sim** out);
 void fsim_sim_destroy(fsim_sim* s);
@@ -252,13 +272,33 @@ int fsim_set_stimulus_seed(fsim_sim* s, uint64_t seed_base);
 int fsim_set_inputs(fsim_sim* s, uint64_t first_cycle, uint32_t n_cycles,
                     const uint64_t* vals);
 
-/* Advance n_cycles, asynchronously on the context's stream. */
+/* Advance n_cycles simulated cycles, asynchronously on the context's
+ * stream.  Each cycle is one bulk-synchronous superstep of Sec. 3.2: every
+ * process evaluates its fibers from the current register copy and writes
+ * the next one, memory writes commit after every read, and one barrier (the
+ * kernel boundary, or the grid barrier of the persistent launch) ends the
+ * cycle; the parity swap of the two state halves is the exchange.  Returns
+ * FSIM_E_ARG when explicit inputs do not cover the cycles, FSIM_E_DEVICE when
+ * a launch fails (the sim is then poisoned), FSIM_E_STATE on a poisoned sim.
+ * Errors raised by the device during the cycles are reported by the next
+ * fsim_sync. */
 int fsim_step(fsim_sim* s, uint64_t n_cycles);
+/* Wait for the sim's queued cycles.  FSIM_E_DEVICE (and a poisoned sim) when
+ * the device reported a failure: a grid barrier that exceeded its bounded
+ * wait, or a runtime error; FSIM_E_ARG when a cycle found no explicit
+ * inputs. */
 int fsim_sync(fsim_sim* s);
+/* Cycles simulated so far (the t of Sec. 3.2's R_t); 0 for a NULL sim. */
 uint64_t fsim_cycle(const fsim_sim* s);
 
-/* State access (each synchronises).  out/in hold n_regs, n_outputs or the
- * memory's depth values; outputs are those of the last simulated cycle.
+/* State access, the "read register and output state" of the problem
+ * statement: the current register copy R_t of Sec. 3.2, the outputs of the
+ * last simulated cycle, and the arrays (the memories of Sec. 5.1 stage 1)
+ * as they stand after that cycle's writes.  Each call synchronises first
+ * and returns what fsim_sync would on a device error; FSIM_E_ARG for an
+ * instance or memory out of range or a NULL buffer.  Writes mask every value
+ * to its declared width.  out/in hold n_regs, n_outputs or the memory's
+ * depth values, one uint64_t each, caller-owned host memory.
  * In the batched form one instance's values are gathered (or scattered) on
  * the device through a staging buffer that the sim allocates on first use,
  * sized for the largest column read so far, and frees with the sim. */
@@ -270,8 +310,11 @@ int fsim_write_mem(fsim_sim* s, uint32_t inst, uint32_t mem, const uint64_t* in)
 /* Set the cycle counter (restoring a checkpoint: regs + mems + cycle). */
 int fsim_set_cycle(fsim_sim* s, uint64_t cycle);
 
-/* Verification digests: after every simulated cycle the device adds, per
- * instance, D = sum_r H(r ^ H(R[r])) mod 2^64 into
+/* Verification digests (not part of the paper's method; an order-free
+ * summary of R_{t+1} of Sec. 3.2, so that a run can be compared with the
+ * oracle every cycle without reading the state back): after every
+ * simulated cycle the device adds, per instance, D = sum_r H(r ^ H(R[r]))
+ * mod 2^64, H = SplitMix64's output function, into
  * dev_out[(cycle - first) * n_instances + inst], where first is the cycle
  * at which digests were enabled.  dev_out is caller device memory of
  * max_cycles * n_instances uint64, zeroed by this call; NULL disables. */

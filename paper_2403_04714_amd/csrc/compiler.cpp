@@ -787,15 +787,61 @@ Status encode_plain(Design& d, uint32_t max_slots) {
   d.plain_max_instr = 0;
   d.plain_max_chunks = 0;
   std::vector<uint32_t> slot(d.N, UINT32_MAX);
-  std::vector<uint32_t> lvl_nodes;
+  std::vector<uint32_t> last(d.N, 0);
+  std::vector<uint32_t> lvl_nodes, free_slots;
   for (uint32_t p = 0; p < d.P; ++p) {
     const uint32_t lo = d.proc_off[p], hi = d.proc_off[p + 1];
-    const uint32_t n = hi - lo;
+    // ---- LDS slots by liveness.  The process runs its levels in order and
+    // a level reads only values of earlier levels, so a value's slot can be
+    // taken by a value of any level after the last one that reads it (never
+    // by one of that same level, whose chunks may still be reading).  Sink
+    // values are read by the store level after the last operator level and
+    // write-port operands by the commit after it; constants are loaded once
+    // per launch and keep their slots.
+    const uint32_t top = hi > lo ? d.level[d.proc_nodes[hi - 1]] : 0;
+    const uint32_t l_store = top + 1, l_commit = top + 2;
+    for (uint32_t i = lo; i < hi; ++i) {
+      const uint32_t x = d.proc_nodes[i];
+      for (int k = 0; k < arity(d.op[x]); ++k) {
+        const uint32_t y = d.arg[3ull * x + k];
+        last[y] = std::max(last[y], d.level[x]);
+      }
+    }
+    for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
+      const uint32_t s = d.psinks[k];
+      if (s < d.R) last[d.reg_next[s]] = std::max(last[d.reg_next[s]], l_store);
+      else if (s >= d.R + d.W) last[d.out_node[s - d.R - d.W]] = std::max(last[d.out_node[s - d.R - d.W]], l_store);
+      else {
+        const uint32_t q = s - d.R;
+        for (uint32_t y : {d.wp_en[q], d.wp_addr[q], d.wp_data[q]}) last[y] = l_commit;
+      }
+    }
+    uint32_t n = 0;
+    free_slots.clear();
+    for (uint32_t i = lo; i < hi; ++i)
+      if (d.op[d.proc_nodes[i]] == FSIM_OP_CONST) slot[d.proc_nodes[i]] = n++;
+    // values ordered by last use, released as the sweep passes each level
+    std::vector<std::pair<uint32_t, uint32_t>> by_last;
+    for (uint32_t i = lo; i < hi; ++i)
+      if (d.op[d.proc_nodes[i]] != FSIM_OP_CONST) by_last.push_back({last[d.proc_nodes[i]], d.proc_nodes[i]});
+    std::sort(by_last.begin(), by_last.end());
+    size_t rel = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+      const uint32_t x = d.proc_nodes[i];
+      if (d.op[x] == FSIM_OP_CONST) continue;
+      // every value last read before this node's level is dead by now
+      while (rel < by_last.size() && by_last[rel].first < d.level[x]) free_slots.push_back(slot[by_last[rel++].second]);
+      if (!free_slots.empty()) {
+        slot[x] = free_slots.back();
+        free_slots.pop_back();
+      } else {
+        slot[x] = n++;
+      }
+    }
     // operands are LDS byte offsets in 16 bits: at most 8191 slots
     if (n > max_slots || n > 8191)
       return Status::err(FSIM_E_CAPACITY,
                          fmt("process %llu needs %llu value slots; use more processes", p, n));
-    for (uint32_t i = lo; i < hi; ++i) slot[d.proc_nodes[i]] = i - lo;
     PlainProc& pp = d.plain_procs[p];
     pp.n_slots = n;
     // constant prologue
@@ -906,7 +952,10 @@ Status encode_plain(Design& d, uint32_t max_slots) {
     d.plain_max_instr = std::max(d.plain_max_instr, pp.n_instr + pp.n_wp);
     d.plain_max_chunks = std::max(d.plain_max_chunks, pp.n_chunks);
     d.max_plain_lvls = std::max(d.max_plain_lvls, n_lvls);
-    for (uint32_t j = lo; j < hi; ++j) slot[d.proc_nodes[j]] = UINT32_MAX;
+    for (uint32_t j = lo; j < hi; ++j) {
+      slot[d.proc_nodes[j]] = UINT32_MAX;
+      last[d.proc_nodes[j]] = 0;
+    }
   }
   phase("encode plain");
   return {};

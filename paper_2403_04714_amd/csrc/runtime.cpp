@@ -33,6 +33,7 @@ using fsim::batch_args;
 using fsim::batch_grid;
 using fsim::batched_wave_bytes;
 using fsim::ensure_batched;
+using fsim::check_inst;
 
 extern "C" const char* fsim_last_error(void) { return fsim::g_last_error.c_str(); }
 
@@ -134,7 +135,7 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   dz->max_chunks = d.plain_max_chunks;
   dz->slot_words = (d.plain_max_slots + 1) & ~1u;
   d.compile_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  fsim_design_info& I = dz->info;
+  struct fsim_design_info& I = dz->info;
   I.n_nodes = d.N;
   I.n_live_ops = (uint32_t)d.n_live_ops;
   I.n_regs = d.R;
@@ -153,6 +154,8 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   I.max_process_levels = d.max_process_levels;
   I.max_process_nodes = d.max_process_nodes;
   I.compile_seconds = d.compile_seconds;
+  I.plain_max_slots = d.plain_max_slots;
+  I.plain_max_chunks = d.plain_max_chunks;
   if (ctx) {
     dz->ctx = ctx;
     HIP_TRY(hipSetDevice(ctx->device));
@@ -174,10 +177,14 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   return FSIM_OK;
 }
 
-extern "C" int fsim_design_info_get(const fsim_design* d, fsim_design_info* out) {
+extern "C" int fsim_design_info(const fsim_design* d, struct fsim_design_info* out) {
   if (!d || !out) return fail(FSIM_E_ARG, "NULL argument");
   *out = d->info;
   return FSIM_OK;
+}
+
+extern "C" int fsim_design_info_get(const fsim_design* d, struct fsim_design_info* out) {
+  return fsim_design_info(d, out);
 }
 
 extern "C" int fsim_design_partition(const fsim_design* dd, uint32_t* sink_to_process,
@@ -308,6 +315,7 @@ int fsim::ensure_batched(fsim_design* d) {
   if ((rc = upload(d->b_instr, D.batch_instr, s))) return rc;
   if ((rc = upload(d->b_procs, D.batch_procs, s))) return rc;
   if ((rc = upload(d->b_consts, D.batch_consts, s))) return rc;
+  if ((rc = upload(d->b_regidx, D.reg_cls_idx, s))) return rc;
   HIP_TRY(hipStreamSynchronize(s));
   d->batch_ready = true;
   return FSIM_OK;
@@ -684,7 +692,7 @@ extern "C" int fsim_sync(fsim_sim* s) {
 
 extern "C" uint64_t fsim_cycle(const fsim_sim* s) { return s ? s->cycle : 0; }
 
-static int check_inst(fsim_sim* s, uint32_t inst) {
+int fsim::check_inst(fsim_sim* s, uint32_t inst) {
   if (!s) return fail(FSIM_E_ARG, "sim is NULL");
   if (inst >= s->n_inst) return fail(FSIM_E_ARG, "instance out of range");
   return fsim_sync(s);

@@ -56,7 +56,7 @@ struct fsim_design {
   std::atomic<int> refs{1};
   fsim_ctx* ctx = nullptr;          // null: compiled on the host only
   fsim::Design d;
-  fsim_design_info info{};
+  struct fsim_design_info info{};
   // plain-form program on the device
   fsim::DevBuf instr, levels, chunks, procs, consts, mem_off, mem_depth, in_width;
   uint32_t slot_words = 0, max_proc_instr = 0, max_lvls = 0, max_chunks = 0;
@@ -66,6 +66,7 @@ struct fsim_design {
   std::mutex batch_mu;
   bool batch_ready = false;
   fsim::DevBuf b_instr, b_procs, b_consts;
+  fsim::DevBuf b_regidx;            // per register: class << 30 | index in its class
 };
 
 struct fsim_sim {
@@ -111,6 +112,7 @@ struct fsim_sim {
 
 
 namespace fsim {
+int check_inst(fsim_sim* s, uint32_t inst);
 BatchArgs batch_args(fsim_sim* s);
 uint32_t batch_grid(const fsim_sim* s);
 size_t batched_wave_bytes(const Design& D);

@@ -7,8 +7,11 @@ fails loudly when it is missing: there is no fallback path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -64,6 +67,7 @@ class DesignInfo(C.Structure):
         ("max_fiber_cost", C.c_uint64), ("max_process_cost", C.c_uint64),
         ("program_bytes", C.c_uint64), ("max_process_levels", C.c_uint32),
         ("max_process_nodes", C.c_uint32), ("compile_seconds", C.c_double),
+        ("plain_max_slots", C.c_uint32), ("plain_max_chunks", C.c_uint32),
     ]
 
     def as_dict(self):
@@ -84,6 +88,7 @@ SIGNATURES = {
     "fsim_ctx_destroy": (None, [_P]),
     "fsim_ctx_device": (_I, [_P, _P, _P, _P]),
     "fsim_design_load": (_I, [_P, _P, _P, _P, _P]),
+    "fsim_design_info": (_I, [_P, _P]),
     "fsim_design_info_get": (_I, [_P, _P]),
     "fsim_design_partition": (_I, [_P, _P, _P, _P]),
     "fsim_design_free": (None, [_P]),
@@ -199,6 +204,36 @@ def _netlist_struct(nl):
     return s, keep
 
 
+# Live handles by kind.  They are destroyed in dependency order -- servers,
+# sims, designs, contexts -- by close() or, for whatever is still open, by
+# an exit handler that runs before the interpreter and the HIP runtime shut
+# down.  During interpreter finalization __del__ makes no library call: by
+# then torch may have released a workspace or stream that a handle borrows.
+_LIVE = {k: weakref.WeakSet() for k in ("server", "sim", "design", "ctx")}
+_exit_hook = False
+
+
+def _track(kind, obj):
+    global _exit_hook
+    _LIVE[kind].add(obj)
+    if not _exit_hook:
+        # registered after torch is imported, so it runs before torch's own
+        # exit handlers
+        atexit.register(close_all)
+        _exit_hook = True
+
+
+def close_all():
+    """Destroy every open server, sim, design and context, in that order."""
+    for kind in ("server", "sim", "design", "ctx"):
+        for obj in list(_LIVE[kind]):
+            obj.close()
+
+
+def _finalizing():
+    return sys.is_finalizing()
+
+
 class Context:
     """A HIP device plus the stream every call is ordered on (torch's current
     stream by default, so torch.cuda.Event timing sees the kernels)."""
@@ -212,17 +247,22 @@ class Context:
         _check(lib().fsim_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)), "fsim_ctx_create")
         self._h = h
         self.device = device
+        _track("ctx", self)
 
     def info(self):
         cus, lds, wgs = C.c_uint32(), C.c_uint32(), C.c_uint32()
         _check(lib().fsim_ctx_device(self._h, C.byref(cus), C.byref(lds), C.byref(wgs)), "fsim_ctx_device")
         return dict(n_cus=cus.value, lds_bytes=lds.value, max_coresident_wgs=wgs.value)
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "_h", None)
         if h and _lib is not None:
-            _lib.fsim_ctx_destroy(h)
             self._h = None
+            _lib.fsim_ctx_destroy(h)
+
+    def __del__(self):
+        if not _finalizing():
+            self.close()
 
 
 class Design:
@@ -248,10 +288,11 @@ class Design:
         self.n_regs, self.n_outputs, self.n_inputs = s.n_regs, s.n_outputs, s.n_inputs
         self.mem_depth = keep["mem_depth"].copy()
         self.n_sinks = s.n_regs + s.n_wports + s.n_outputs
+        _track("design", self)
 
     def info(self) -> dict:
         i = DesignInfo()
-        _check(lib().fsim_design_info_get(self._h, C.byref(i)), "fsim_design_info_get")
+        _check(lib().fsim_design_info(self._h, C.byref(i)), "fsim_design_info")
         return i.as_dict()
 
     def batched_info(self) -> dict:
@@ -271,11 +312,17 @@ class Design:
         _check(lib().fsim_design_partition(self._h, None, None, _ptr(nodes)), "fsim_design_partition")
         return stp[: self.n_sinks], off, nodes[: int(off[-1])]
 
-    def __del__(self):
+    def close(self):
+        """Release this handle (sims created from the design keep it alive
+        inside the library until they are destroyed)."""
         h = getattr(self, "_h", None)
         if h and _lib is not None:
-            _lib.fsim_design_free(h)
             self._h = None
+            _lib.fsim_design_free(h)
+
+    def __del__(self):
+        if not _finalizing():
+            self.close()
 
 
 class Sim:
@@ -303,6 +350,7 @@ class Sim:
                "fsim_sim_create")
         self._h = h
         self._digest = None
+        _track("sim", self)
         if seed is not None:
             self.set_seed(seed)
 
@@ -391,11 +439,18 @@ class Sim:
         d = self._digest.cpu().numpy().view(np.uint64)
         return d.reshape(-1, self.n_instances)
 
-    def __del__(self):
+    def close(self):
+        """Destroy the sim (waits for its queued work), then drop the torch
+        buffers it borrowed."""
         h = getattr(self, "_h", None)
         if h and _lib is not None:
-            _lib.fsim_sim_destroy(h)
             self._h = None
+            _lib.fsim_sim_destroy(h)
+        self._ws = self._digest = self._trace = None
+
+    def __del__(self):
+        if not _finalizing():
+            self.close()
 
 
 class Server:
@@ -410,6 +465,7 @@ class Server:
         self._h = h
         self.ctx = ctx
         self._designs = []
+        _track("server", self)
 
     def submit(self, design: Design, n_instances: int, n_cycles: int, seed_base: int) -> int:
         jid = C.c_uint64()
@@ -446,8 +502,9 @@ class Server:
     def close(self):
         h = getattr(self, "_h", None)
         if h and _lib is not None:
-            _lib.fsim_server_destroy(h)
             self._h = None
+            _lib.fsim_server_destroy(h)
 
     def __del__(self):
-        self.close()
+        if not _finalizing():
+            self.close()

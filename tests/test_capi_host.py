@@ -374,3 +374,16 @@ def test_clock_enable_out_of_range_rejected():
     with pytest.raises(F.FsimError) as e:
         host_design(dataclasses.replace(nl, reg_en=en))
     assert e.value.code == F.E_NETLIST
+
+
+def test_plain_slots_follow_liveness():
+    """The plain form gives LDS slots by liveness: a value's slot is reused
+    after the last level that reads it, so a process needs fewer slots than
+    nodes, and never fewer than the next values it keeps for its store
+    level (one per register it owns)."""
+    nl = g.workload("core")
+    d = host_design(nl, pack=F.PACK_HYPER, target_processes=2048)
+    info = d.info()
+    stp, off, nodes = d.partition()
+    regs_per_proc = np.bincount(stp[: nl.n_regs], minlength=info["n_processes"])
+    assert regs_per_proc.max() <= info["plain_max_slots"] < info["max_process_nodes"]

@@ -92,12 +92,13 @@ def test_small_core_with_memories(F, ctx, target, threads):
 
 
 def test_oversized_processes_fall_back_to_batched(F, ctx):
-    """Four processes of the small core exceed the plain form's 8191-node
-    limit: the design loads, a plain sim is refused with FSIM_E_CAPACITY,
-    and the automatic form runs one instance in the batched form, which
-    matches the oracle."""
-    nl = small_core()
-    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=4)
+    """One process holding 9,000 independent fibers keeps 9,000 next values
+    live until its store level, beyond the plain form's 8191 LDS slots: the
+    design loads, a plain sim is refused with FSIM_E_CAPACITY, and the
+    automatic form runs one instance in the batched form (which stores each
+    value right after computing it), matching the oracle."""
+    nl = g.prng_array(9000)
+    d = F.Design(ctx, nl, pack=F.PACK_SINGLE)
     with pytest.raises(F.FsimError) as e:
         F.Sim(d, 1, form=F.FORM_PLAIN)
     assert e.value.code == F.E_CAPACITY

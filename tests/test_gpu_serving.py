@@ -102,3 +102,51 @@ def test_poisson_stream(F, ctx, designs):
     ref.step(r0["cycles"])
     assert np.array_equal(regs, ref.regs())
     srv.close()
+
+
+def test_alone_equals_in_mix_served_designs(F, ctx):
+    """The benchmark's served designs (configs.SERVED: the single core and
+    the 8-tile SoC under hypergraph packing) in one batched_multi launch per
+    tick: a single-core job gives the same registers and outputs alone and
+    in a mix with an 8-tile SoC job and a second single-core job, and both
+    designs' jobs equal the oracle."""
+    from paper_2403_04714_amd import configs
+    nets = {w: g.workload(w) for w, _, _ in configs.SERVED}
+    print("case serving: compile the served designs", flush=True)
+    ds = {w: F.Design(ctx, nets[w], pack=pk, target_processes=t) for w, pk, t in configs.SERVED}
+    core, soc8 = ds["core"], ds["soc8"]
+    insts = [0, 41, 69]
+    print("case serving: single-core job alone", flush=True)
+    srv = F.Server(ctx, 32 << 30, quantum_cycles=64)
+    a = srv.submit(core, 70, 300, SEED)
+    srv.wait(a, 300)
+    alone = results(srv, a, core, insts)
+    srv.close()
+    print("case serving: single-core job in a mix with an 8-tile SoC job", flush=True)
+    srv = F.Server(ctx, 32 << 30, quantum_cycles=64)
+    b = srv.submit(soc8, 16, 100, SEED + 500)
+    a2 = srv.submit(core, 70, 300, SEED)
+    time.sleep(0.01)
+    c = srv.submit(core, 3, 130, SEED + 900)
+    for j in (a2, b, c):
+        srv.wait(j, 300)
+        assert srv.poll(j)["state"] == F.JOB_DONE
+    mix = results(srv, a2, core, insts)
+    for i in insts:
+        assert np.array_equal(alone[i][0], mix[i][0]) and np.array_equal(alone[i][1], mix[i][1]), i
+    for i in (0, 69):
+        ref = O.Sim(nets["core"], seed=SEED + i)
+        ref.step(300)
+        assert np.array_equal(mix[i][0], ref.regs()) and np.array_equal(mix[i][1], ref.outputs()), i
+    for i in (0, 15):
+        ref = O.Sim(nets["soc8"], seed=SEED + 500 + i)
+        ref.step(100)
+        r, o = srv.result(b, i, soc8)
+        assert np.array_equal(r, ref.regs()) and np.array_equal(o, ref.outputs()), f"soc8 instance {i}"
+    ref = O.Sim(nets["core"], seed=SEED + 900 + 2)
+    ref.step(130)
+    r, o = srv.result(c, 2, core)
+    assert np.array_equal(r, ref.regs()) and np.array_equal(o, ref.outputs())
+    srv.close()
+    for d in ds.values():
+        d.close()

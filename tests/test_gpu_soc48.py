@@ -1,21 +1,25 @@
-"""The 48-tile SoC (8 x 6 mesh, about 9.4M operators, 960k registers, 96
-memories of 4096 x 64) at full size on the GPU against the oracle: the plain
-form with one instance and the batched form with 64 instances, every cycle's
-digest, registers and outputs of every instance, and every memory of a fixed
-sample of instances, over a short run (the oracle needs about a tenth of a
-second per cycle at this size; instances run in host threads).  Compilation
-alone takes about a minute on the host."""
+"""The 48-tile SoC (8 x 6 mesh, 9.45M operators, 960,576 registers, 96
+memories of 4096 x 64) at full size on the GPU, at the benchmark's own
+launch configurations (configs.SOC48_PLAIN, the headline, and
+configs.SOC48_BATCHED), against oracle results stored by
+tests/golden/make_oracle_refs.py (the oracle needs about 0.1-0.4 s per cycle
+at this size, so the long runs are computed once on the host):
+
+- plain, one instance: every cycle's digest over 500 cycles, then the
+  registers, outputs and all 96 memories;
+- batched, 64 instances: every instance's per-cycle digests, registers and
+  outputs over the first 64 cycles, then instances {0, 31, 63} over 300
+  cycles with every memory.
+
+Compiling the design takes about a minute on the host."""
 import numpy as np
 import pytest
 
-from oracle import oracle as O
+import oracle_refs as R
 from paper_2403_04714_amd import netgen as g
-
-from oracle_pool import run_instances
 
 pytestmark = pytest.mark.gpu
 
-SEED = g.STIM_SEED_BASE
 SAMPLE = (0, 31, 63)
 
 
@@ -27,49 +31,54 @@ def F():
 
 @pytest.fixture(scope="module")
 def soc48(F):
-    print("case soc48: generate and compile (8192 processes)", flush=True)
+    print("case soc48: generate", flush=True)
     nl = g.workload("soc48")
     ctx = F.Context(0)
-    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=8192)
-    info = d.info()
-    print(f"case soc48: {info['n_processes']} processes, D_f {info['dup_fiber']:.3f}, "
-          f"D_p {info['dup_process']:.3f}, compile {info['compile_seconds']:.1f} s", flush=True)
-    return nl, ctx, d
+    yield nl, ctx
+    F.close_all()
 
 
 @pytest.mark.timeout(900)
-def test_soc48_plain_one_instance(F, soc48):
-    nl, ctx, d = soc48
-    cycles = 6
-    print("case soc48: plain x1, graph launches, 64 threads", flush=True)
-    s = F.Sim(d, 1, launch=F.LAUNCH_GRAPH, wg_threads=64, seed=SEED)
-    s.enable_digest(cycles)
-    s.step(cycles)
-    ref = O.Sim(nl, seed=SEED)
-    rd = ref.step(cycles, digests=True)
-    assert np.array_equal(s.digests()[:, 0], rd)
-    assert np.array_equal(s.regs(), ref.regs())
-    assert np.array_equal(s.outputs(), ref.outputs())
-    for m in (0, 47, 95):
-        assert np.array_equal(s.mem(m), ref.mem(m)), f"memory {m}"
+def test_soc48_plain_headline_config(F, soc48):
+    from paper_2403_04714_amd import configs
+    nl, ctx = soc48
+    rec = R.load("soc48_x1_500")
+    R.check_netlist(rec, nl)
+    cfg = configs.SOC48_PLAIN
+    print(f"case soc48 plain x1: compile ({cfg.label()})", flush=True)
+    d = cfg.design(ctx, nl)
+    s = cfg.sim(d, g.STIM_SEED_BASE)
+    print(f"case soc48 plain x1: {d.info()['n_processes']} processes, {s.layout()}, {rec['cycles']} cycles",
+          flush=True)
+    s.enable_digest(rec["cycles"])
+    s.step(rec["cycles"])
+    R.compare_instance(rec, 0, digests=s.digests()[:, 0], regs=s.regs(), outputs=s.outputs(),
+                       mems={m: s.mem(m) for m in range(nl.n_mems)})
+    s.close()
+    d.close()
 
 
 @pytest.mark.timeout(900)
-def test_soc48_batched_64(F, soc48):
-    nl, ctx, d = soc48
-    cycles = 3
-    print("case soc48: batched x64", flush=True)
-    s = F.Sim(d, 64, launch=F.LAUNCH_GRAPH, seed=SEED)
-    s.enable_digest(cycles)
-    s.step(cycles)
+def test_soc48_batched_64_config(F, soc48):
+    from paper_2403_04714_amd import configs
+    nl, ctx = soc48
+    first, sample = R.load("soc48_x64_64"), R.load("soc48_sample_300")
+    R.check_netlist(first, nl)
+    cfg = configs.SOC48_BATCHED
+    print(f"case soc48 batched x64: compile ({cfg.label()})", flush=True)
+    d = cfg.design(ctx, nl)
+    s = cfg.sim(d, g.STIM_SEED_BASE)
+    print(f"case soc48 batched x64: {d.info()['n_processes']} processes, {s.layout()}", flush=True)
+    s.enable_digest(sample["cycles"])
+    s.step(first["cycles"])
     dg = s.digests()
-    print("case soc48: oracle, 64 instances", flush=True)
-    refs = run_instances(nl, [SEED + i for i in range(64)], cycles)
-    for i, (rd, rr, ro, _) in enumerate(refs):
-        assert np.array_equal(dg[:, i], rd), f"instance {i}"
-        assert np.array_equal(s.regs(i), rr), f"instance {i} registers"
-        assert np.array_equal(s.outputs(i), ro), f"instance {i} outputs"
-    refs = run_instances(nl, [SEED + i for i in SAMPLE], cycles, mems=range(nl.n_mems))
-    for i, (_, _, _, rm) in zip(SAMPLE, refs):
-        for m, v in rm.items():
-            assert np.array_equal(s.mem(m, i), v), f"instance {i} memory {m}"
+    for i in range(cfg.instances):
+        R.compare_instance(first, i, digests=dg[:first["cycles"], i], regs=s.regs(i), outputs=s.outputs(i))
+    print(f"case soc48 batched x64: instances {SAMPLE} to cycle {sample['cycles']}", flush=True)
+    s.step(sample["cycles"] - first["cycles"])
+    dg = s.digests()
+    for i in SAMPLE:
+        R.compare_instance(sample, i, digests=dg[:, i], regs=s.regs(i), outputs=s.outputs(i),
+                           mems={m: s.mem(m, i) for m in range(nl.n_mems)})
+    s.close()
+    d.close()
