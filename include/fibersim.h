@@ -303,6 +303,16 @@ uint64_t fsim_cycle(const fsim_sim* s);
  * the device through a staging buffer that the sim allocates on first use,
  * sized for the largest column read so far, and frees with the sim. */
 int fsim_read_regs(fsim_sim* s, uint32_t inst, uint64_t* out);
+/* fsim_read_regs for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, but a batched instance's column is gathered into a
+ * static device array of 8 MiB that the library holds on every GPU it runs
+ * on until the process ends, so the call makes no allocation (fsim_read_regs
+ * allocates its staging buffer on first use).  FSIM_E_CAPACITY when the
+ * design has more than 1,048,576 registers (use fsim_read_regs then).  The
+ * array is shared by every call on one GPU: calls that overlap on the same
+ * GPU (from two host threads) race on it. */
+int fsim_read_regs_noalloc(fsim_sim* s, uint32_t inst, uint64_t* out);
 int fsim_write_regs(fsim_sim* s, uint32_t inst, const uint64_t* in);
 int fsim_read_outputs(fsim_sim* s, uint32_t inst, uint64_t* out);
 int fsim_read_mem(fsim_sim* s, uint32_t inst, uint32_t mem, uint64_t* out);

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfibersim.so")
-SOURCES = ["compiler.cpp", "runtime.cpp", "serve.cpp", "kernels_plain.hip", "kernels_batched.hip"]
+SOURCES = ["compiler.cpp", "runtime.cpp", "serve.cpp", "kernels_plain.hip", "kernels_batched.hip", "scratch.hip"]
 HEADERS = ["compiler.h", "isa.h", "kernels.h", "device_common.h"]
 ARCH = os.environ.get("FSIM_OFFLOAD_ARCH", "gfx950")
 

@@ -102,6 +102,7 @@ SIGNATURES = {
     "fsim_sync": (_I, [_P]),
     "fsim_cycle": (_U64, [_P]),
     "fsim_read_regs": (_I, [_P, _U32, _P]),
+    "fsim_read_regs_noalloc": (_I, [_P, _U32, _P]),
     "fsim_write_regs": (_I, [_P, _U32, _P]),
     "fsim_read_outputs": (_I, [_P, _U32, _P]),
     "fsim_read_mem": (_I, [_P, _U32, _U32, _P]),
@@ -380,6 +381,13 @@ class Sim:
     def regs(self, inst: int = 0) -> np.ndarray:
         out = np.zeros(max(self.design.n_regs, 1), np.uint64)
         _check(lib().fsim_read_regs(self._h, inst, _ptr(out)), "fsim_read_regs")
+        return out[: self.design.n_regs]
+
+    def regs_noalloc(self, inst: int = 0) -> np.ndarray:
+        """Registers of one instance through fsim_read_regs_noalloc (no device
+        allocation; a static staging array shared by all calls on the GPU)."""
+        out = np.zeros(max(self.design.n_regs, 1), np.uint64)
+        _check(lib().fsim_read_regs_noalloc(self._h, inst, _ptr(out)), "fsim_read_regs_noalloc")
         return out[: self.design.n_regs]
 
     def write_regs(self, vals, inst: int = 0):
