@@ -153,8 +153,10 @@ struct fsim_design_info {
   uint32_t max_process_levels;
   uint32_t max_process_nodes;
   double compile_seconds;
-  uint32_t plain_max_slots;   /* plain form: LDS value slots (8 B) of the
-                                 largest process, allocated by liveness      */
+  uint32_t plain_max_slots;   /* plain form: 4-byte LDS units of live values
+                                 of the largest process (a value of at most
+                                 32 bits takes one, a wider one two),
+                                 allocated by liveness                       */
   uint32_t plain_max_chunks;  /* plain form: chunks of the longest process   */
 };
 

@@ -418,53 +418,85 @@ std::vector<uint32_t> hyper_pack(const Design& d, const std::vector<std::vector<
     return v.empty() ? 0u : v[v.size() / 2];
   };
   std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
-  // ---- 1. runs under a union-cost bound
+  // Register and input leaves cost no operator but each is a value a process
+  // loads and keeps live (an LDS value of the plain form from the first
+  // level on).  Logic of many small fibers that read many registers (a
+  // router, say) is cheap in operators but heavy in leaves, so once a cut
+  // under the cost bound alone is known, a process's leaves are capped at
+  // 1.15 x their mean over that cut, as long as the target count can still be
+  // met.
+  auto is_leaf = [&](uint32_t x) { return d.op[x] == FSIM_OP_REG || d.op[x] == FSIM_OP_INPUT; };
+  std::vector<uint32_t> uleaves(U, 0);
+  uint64_t max_unit_leaves = 0;
+  for (uint32_t u = 0; u < U; ++u) {
+    for (uint32_t x : unit_nodes[u]) uleaves[u] += is_leaf(x);
+    max_unit_leaves = std::max<uint64_t>(max_unit_leaves, uleaves[u]);
+  }
+  // ---- 1. runs under a union-cost bound (and the leaf cap)
   std::vector<uint32_t> stamp(d.N, UINT32_MAX), proc(U, 0);
+  uint64_t max_leaves = UINT64_MAX, leaf_sum = 0;
   auto cut = [&](uint64_t bound, std::vector<uint32_t>* assign) -> uint32_t {
     std::fill(stamp.begin(), stamp.end(), UINT32_MAX);
     uint32_t run = 0;
-    uint64_t tau = 0, nodes = 0;
+    uint64_t tau = 0, nodes = 0, leaves = 0;
+    leaf_sum = 0;
     for (uint32_t u : order) {
-      uint64_t add = 0, addn = 0;
-      for (uint32_t x : unit_nodes[u]) if (stamp[x] != run) { add += d.cost[x]; ++addn; }
-      if (nodes > 0 && (tau + add > bound || nodes + addn > max_nodes)) {
+      uint64_t add = 0, addn = 0, addl = 0;
+      for (uint32_t x : unit_nodes[u])
+        if (stamp[x] != run) { add += d.cost[x]; ++addn; addl += is_leaf(x); }
+      if (nodes > 0 && (tau + add > bound || nodes + addn > max_nodes || leaves + addl > max_leaves)) {
         ++run;
         tau = 0;
         nodes = 0;
+        leaves = 0;
         add = ucost[u];
         addn = unit_nodes[u].size();
+        addl = uleaves[u];
       }
       for (uint32_t x : unit_nodes[u]) stamp[x] = run;
       tau += add;
       nodes += addn;
+      leaves += addl;
+      leaf_sum += addl;
       if (assign) (*assign)[u] = run;
     }
     return run + 1;
   };
   uint64_t total = 0;
   for (uint64_t c : ucost) total += c;
-  uint64_t lo = std::max<uint64_t>(max_unit, 1), hi = 0;
-  for (uint64_t B = lo;; B = std::max<uint64_t>(B + 1, B + B / 8)) {
-    if (cut(B, nullptr) <= target) { hi = B; break; }
-    lo = B + 1;
-    if (B >= total) { hi = total; break; }
+  // the smallest bound that gives at most `target` runs: geometric steps,
+  // then bisection
+  auto search = [&]() -> uint64_t {
+    uint64_t lo = std::max<uint64_t>(max_unit, 1), hi = 0;
+    for (uint64_t B = lo;; B = std::max<uint64_t>(B + 1, B + B / 8)) {
+      if (cut(B, nullptr) <= target) { hi = B; break; }
+      lo = B + 1;
+      if (B >= total) { hi = total; break; }
+    }
+    for (int it = 0; it < 24 && lo < hi; ++it) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (cut(mid, nullptr) <= target) hi = mid; else lo = mid + 1;
+    }
+    return hi;
+  };
+  uint64_t bound = search();
+  {
+    const uint32_t runs = cut(bound, nullptr);
+    max_leaves = std::max<uint64_t>(max_unit_leaves, leaf_sum * 115 / (100ull * runs) + 1);
+    if (cut(total, nullptr) <= target) bound = search();
+    else max_leaves = UINT64_MAX;            // the cap would not let the target be met
   }
-  for (int it = 0; it < 24 && lo < hi; ++it) {
-    const uint64_t mid = lo + (hi - lo) / 2;
-    if (cut(mid, nullptr) <= target) hi = mid; else lo = mid + 1;
-  }
-  const uint64_t bound = hi;
   const uint32_t P = cut(bound, &proc);
   // ---- incidence: for every node, the processes holding it and how many of
   // their units contain it
   struct Inc { uint32_t p, n; };
   std::vector<std::vector<Inc>> inc(d.N);
-  std::vector<uint64_t> tau(P, 0), pnodes(P, 0);
+  std::vector<uint64_t> tau(P, 0), pnodes(P, 0), pleaves(P, 0);
   auto add = [&](uint32_t u, uint32_t p) {
     for (uint32_t x : unit_nodes[u]) {
       bool found = false;
       for (Inc& e : inc[x]) if (e.p == p) { ++e.n; found = true; break; }
-      if (!found) { inc[x].push_back({p, 1}); tau[p] += d.cost[x]; ++pnodes[p]; }
+      if (!found) { inc[x].push_back({p, 1}); tau[p] += d.cost[x]; ++pnodes[p]; pleaves[p] += is_leaf(x); }
     }
   };
   auto remove = [&](uint32_t u, uint32_t p) {
@@ -472,7 +504,7 @@ std::vector<uint32_t> hyper_pack(const Design& d, const std::vector<std::vector<
       auto& v = inc[x];
       for (size_t i = 0; i < v.size(); ++i) {
         if (v[i].p != p) continue;
-        if (--v[i].n == 0) { v[i] = v.back(); v.pop_back(); tau[p] -= d.cost[x]; --pnodes[p]; }
+        if (--v[i].n == 0) { v[i] = v.back(); v.pop_back(); tau[p] -= d.cost[x]; --pnodes[p]; pleaves[p] -= is_leaf(x); }
         break;
       }
     }
@@ -480,7 +512,7 @@ std::vector<uint32_t> hyper_pack(const Design& d, const std::vector<std::vector<
   for (uint32_t u = 0; u < U; ++u) add(u, proc[u]);
   // ---- 2. refinement
   constexpr size_t kWide = 32;             // nodes in more processes than this: left out of the estimate
-  std::vector<uint64_t> shared_c(P, 0), shared_n(P, 0);
+  std::vector<uint64_t> shared_c(P, 0), shared_n(P, 0), shared_l(P, 0);
   std::vector<uint32_t> touched;
   for (int pass = 0; pass < 6; ++pass) {
     uint64_t moved = 0;
@@ -496,19 +528,22 @@ std::vector<uint32_t> hyper_pack(const Design& d, const std::vector<std::vector<
           if (!shared_c[e.p] && !shared_n[e.p]) touched.push_back(e.p);
           shared_c[e.p] += d.cost[x];
           ++shared_n[e.p];
+          shared_l[e.p] += is_leaf(x);
         }
       }
       uint32_t best = UINT32_MAX;
       int64_t best_delta = 0;
       for (uint32_t b : touched) {
         const uint64_t addc = ucost[u] - shared_c[b], addn = unit_nodes[u].size() - shared_n[b];
+        const uint64_t addl = uleaves[u] - shared_l[b];
         const int64_t delta = (int64_t)addc - (int64_t)save;   // change of total replication
-        if (delta < best_delta && tau[b] + addc <= bound && pnodes[b] + addn <= max_nodes) {
+        if (delta < best_delta && tau[b] + addc <= bound && pnodes[b] + addn <= max_nodes &&
+            pleaves[b] + addl <= max_leaves) {
           best_delta = delta;
           best = b;
         }
       }
-      for (uint32_t b : touched) shared_c[b] = shared_n[b] = 0;
+      for (uint32_t b : touched) shared_c[b] = shared_n[b] = shared_l[b] = 0;
       if (best != UINT32_MAX) {
         remove(u, a);
         add(u, best);
@@ -776,7 +811,82 @@ static Instr make(uint8_t op, uint8_t w, uint16_t dst, uint16_t a, uint16_t b, u
   return in;
 }
 
-Status encode_plain(Design& d, uint32_t max_slots) {
+namespace {
+
+// LDS of one plain-form process in 4-byte units: a narrow value (at most 32
+// bits) takes one unit, a wide one an even pair.  Released units are reused;
+// a released unit whose partner is free makes a free pair again.  Free lists
+// may hold stale entries; the unit states decide.
+class UnitAlloc {
+ public:
+  // units below `base` are reserved (never handed out)
+  void reset(uint32_t base) {
+    st_.assign(base, kUsed);
+    one_.clear();
+    two_.clear();
+  }
+  uint32_t top() const { return (uint32_t)st_.size(); }
+  uint32_t take(bool wide) {
+    uint32_t u;
+    if (!wide) {
+      while (!one_.empty()) {
+        u = one_.back();
+        one_.pop_back();
+        if (st_[u] == kFree) { st_[u] = kUsed; return u; }
+      }
+      if (pop_pair(u)) {
+        st_[u] = kUsed;
+        one_.push_back(u + 1);
+        return u;
+      }
+      st_.push_back(kUsed);
+      return top() - 1;
+    }
+    if (pop_pair(u)) {
+      st_[u] = st_[u + 1] = kUsed;
+      return u;
+    }
+    if (top() & 1) {
+      st_.push_back(kFree);
+      one_.push_back(top() - 1);
+    }
+    st_.push_back(kUsed);
+    st_.push_back(kUsed);
+    return top() - 2;
+  }
+  void give(uint32_t u, bool wide) {
+    st_[u] = kFree;
+    if (wide) {
+      st_[u + 1] = kFree;
+      two_.push_back(u);
+      return;
+    }
+    const uint32_t v = u ^ 1;
+    if (v < top() && st_[v] == kFree) two_.push_back(u & ~1u);
+    else one_.push_back(u);
+  }
+
+ private:
+  enum : uint8_t { kUsed = 0, kFree = 1 };
+  bool pop_pair(uint32_t& u) {
+    while (!two_.empty()) {
+      u = two_.back();
+      two_.pop_back();
+      if (st_[u] == kFree && st_[u + 1] == kFree) return true;
+    }
+    return false;
+  }
+  std::vector<uint8_t> st_;
+  std::vector<uint32_t> one_, two_;
+};
+
+// pending register and output stores are written out early, in a store level
+// of their own, once this many have accumulated (one full store chunk)
+constexpr size_t kStoreFlush = 256;
+
+}  // namespace
+
+Status encode_plain(Design& d, uint32_t max_units) {
   phase("process node lists");
   d.plain_procs.assign(d.P, PlainProc{});
   d.plain_levels.clear();
@@ -786,152 +896,195 @@ Status encode_plain(Design& d, uint32_t max_slots) {
   d.plain_max_slots = 0;
   d.plain_max_instr = 0;
   d.plain_max_chunks = 0;
-  std::vector<uint32_t> slot(d.N, UINT32_MAX);
-  std::vector<uint32_t> last(d.N, 0);
-  std::vector<uint32_t> lvl_nodes, free_slots;
+  d.max_plain_lvls = 0;
+  std::vector<uint32_t> unit(d.N, UINT32_MAX), lpos(d.N, 0), loc(d.N, 0);
+  std::vector<uint32_t> lv_start;                       // per local level: first index into the node list
+  std::vector<std::vector<uint32_t>> flush;             // per local level: sinks stored right after it
+  std::vector<std::pair<uint32_t, uint32_t>> by_last;
+  UnitAlloc alloc;
+  auto narrow = [&](uint32_t x) { return d.width[x] <= 32; };
   for (uint32_t p = 0; p < d.P; ++p) {
     const uint32_t lo = d.proc_off[p], hi = d.proc_off[p + 1];
-    // ---- LDS slots by liveness.  The process runs its levels in order and
-    // a level reads only values of earlier levels, so a value's slot can be
-    // taken by a value of any level after the last one that reads it (never
-    // by one of that same level, whose chunks may still be reading).  Sink
-    // values are read by the store level after the last operator level and
-    // write-port operands by the commit after it; constants are loaded once
-    // per launch and keep their slots.
-    const uint32_t top = hi > lo ? d.level[d.proc_nodes[hi - 1]] : 0;
-    const uint32_t l_store = top + 1, l_commit = top + 2;
+    // ---- local levels: 0 holds the leaves, 1..K the operator levels of
+    // this process in order (empty levels dropped)
+    lv_start.clear();
+    lv_start.push_back(lo);
+    for (uint32_t i = lo; i < hi; ++i) {
+      const uint32_t x = d.proc_nodes[i];
+      if (d.level[x] > 0 && (i == lo || d.level[d.proc_nodes[i - 1]] != d.level[x])) lv_start.push_back(i);
+      loc[x] = (uint32_t)lv_start.size() - 1;
+    }
+    const uint32_t K = (uint32_t)lv_start.size() - 1;
+    lv_start.push_back(hi);
+    // ---- where each register and output sink is stored: with the sinks of
+    // its level and earlier ones once kStoreFlush are pending, else in the
+    // final store level after level K
+    flush.assign(K + 1, {});
+    {
+      std::vector<std::vector<uint32_t>> by_level(K + 1);
+      for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
+        const uint32_t s = d.psinks[k];
+        if (s < d.R) by_level[loc[d.reg_next[s]]].push_back(s);
+        else if (s >= d.R + d.W) by_level[loc[d.out_node[s - d.R - d.W]]].push_back(s);
+      }
+      std::vector<uint32_t> pending;
+      for (uint32_t j = 0; j <= K; ++j) {
+        pending.insert(pending.end(), by_level[j].begin(), by_level[j].end());
+        if (j == K || pending.size() >= kStoreFlush) {
+          flush[j].swap(pending);
+          pending.clear();
+        }
+      }
+    }
+    auto root = [&](uint32_t s) { return s < d.R ? d.reg_next[s] : d.out_node[s - d.R - d.W]; };
+    // ---- liveness in positions: local level j runs at 2j, the stores after
+    // it at 2j + 1, the write-port commit at 2K + 2.  A value's units can be
+    // taken by a value defined after the last position that reads it (never
+    // by one of the same level, whose chunks may still be reading).
     for (uint32_t i = lo; i < hi; ++i) {
       const uint32_t x = d.proc_nodes[i];
       for (int k = 0; k < arity(d.op[x]); ++k) {
         const uint32_t y = d.arg[3ull * x + k];
-        last[y] = std::max(last[y], d.level[x]);
+        lpos[y] = std::max(lpos[y], 2 * loc[x]);
       }
     }
+    for (uint32_t j = 0; j <= K; ++j)
+      for (uint32_t s : flush[j]) lpos[root(s)] = std::max(lpos[root(s)], 2 * j + 1);
     for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
       const uint32_t s = d.psinks[k];
-      if (s < d.R) last[d.reg_next[s]] = std::max(last[d.reg_next[s]], l_store);
-      else if (s >= d.R + d.W) last[d.out_node[s - d.R - d.W]] = std::max(last[d.out_node[s - d.R - d.W]], l_store);
-      else {
+      if (s >= d.R && s < d.R + d.W) {
         const uint32_t q = s - d.R;
-        for (uint32_t y : {d.wp_en[q], d.wp_addr[q], d.wp_data[q]}) last[y] = l_commit;
+        for (uint32_t y : {d.wp_en[q], d.wp_addr[q], d.wp_data[q]}) lpos[y] = 2 * K + 2;
       }
     }
-    uint32_t n = 0;
-    free_slots.clear();
+    // ---- units: constants first (loaded once per launch, never released),
+    // then every value in order of definition, after releasing the values
+    // whose last read comes before it
+    alloc.reset(kPlainUnitBase);
     for (uint32_t i = lo; i < hi; ++i)
-      if (d.op[d.proc_nodes[i]] == FSIM_OP_CONST) slot[d.proc_nodes[i]] = n++;
-    // values ordered by last use, released as the sweep passes each level
-    std::vector<std::pair<uint32_t, uint32_t>> by_last;
+      if (d.op[d.proc_nodes[i]] == FSIM_OP_CONST) unit[d.proc_nodes[i]] = alloc.take(!narrow(d.proc_nodes[i]));
+    by_last.clear();
     for (uint32_t i = lo; i < hi; ++i)
-      if (d.op[d.proc_nodes[i]] != FSIM_OP_CONST) by_last.push_back({last[d.proc_nodes[i]], d.proc_nodes[i]});
+      if (d.op[d.proc_nodes[i]] != FSIM_OP_CONST) by_last.push_back({lpos[d.proc_nodes[i]], d.proc_nodes[i]});
     std::sort(by_last.begin(), by_last.end());
     size_t rel = 0;
     for (uint32_t i = lo; i < hi; ++i) {
       const uint32_t x = d.proc_nodes[i];
       if (d.op[x] == FSIM_OP_CONST) continue;
-      // every value last read before this node's level is dead by now
-      while (rel < by_last.size() && by_last[rel].first < d.level[x]) free_slots.push_back(slot[by_last[rel++].second]);
-      if (!free_slots.empty()) {
-        slot[x] = free_slots.back();
-        free_slots.pop_back();
-      } else {
-        slot[x] = n++;
+      while (rel < by_last.size() && by_last[rel].first < 2 * loc[x]) {
+        const uint32_t y = by_last[rel++].second;
+        alloc.give(unit[y], !narrow(y));
       }
+      unit[x] = alloc.take(!narrow(x));
     }
-    // operands are LDS byte offsets in 16 bits: at most 8191 slots
-    if (n > max_slots || n > 8191)
+    const uint32_t n = alloc.top();
+    if (n > max_units || n > kMaxPlainUnits)
       return Status::err(FSIM_E_CAPACITY,
-                         fmt("process %llu needs %llu value slots; use more processes", p, n));
+                         fmt("process %llu needs %llu LDS units of live values; use more processes", p, n));
     PlainProc& pp = d.plain_procs[p];
     pp.n_slots = n;
-    // constant prologue
+    // ---- constant prologue
     pp.const_off = (uint32_t)d.plain_instr.size();
     for (uint32_t i = lo; i < hi; ++i) {
       uint32_t x = d.proc_nodes[i];
       if (d.op[x] != FSIM_OP_CONST) continue;
       uint64_t v = d.imm[x] & (~0ull >> (64 - d.width[x]));
-      d.plain_instr.push_back(make(I_LDCONST, d.width[x], (uint16_t)(8 * slot[x]), 0, 0, 0,
-                                   (uint32_t)d.consts.size()));
+      d.plain_instr.push_back(plain_index(d.width[x], unit[x], d.consts.size(), narrow(x)));
       d.consts.push_back(v);
     }
     pp.n_consts = (uint32_t)d.plain_instr.size() - pp.const_off;
     pp.instr_off = (uint32_t)d.plain_instr.size();
     pp.chunk_off = (uint32_t)d.plain_chunks.size();
     pp.lvl_off = (uint32_t)d.plain_levels.size();
-    // emits one level from a list of instructions sorted by opcode:
-    // operators of any opcode share I_ALU chunks, other opcodes get chunks of
-    // their own
-    auto emit_level = [&](const std::vector<Instr>& ins) {
+    // one level from its instruction words, each with its kind and whether
+    // its sources and its result are narrow; operators of any opcode share
+    // I_ALU chunks, other kinds get chunks of their own
+    struct PI {
+      uint64_t word;
+      uint32_t kind;
+      bool in_narrow, out_narrow;
+    };
+    std::vector<PI> ins;
+    uint32_t n_lvls = 0;
+    // stores written out among the operator levels go one per lane (64 to a
+    // chunk), like the operators around them
+    bool in_ops = false;
+    auto emit_level = [&]() {
       d.plain_levels.push_back((uint32_t)d.plain_chunks.size() - pp.chunk_off);
-      auto kind = [](uint8_t op) -> uint32_t { return (op >= I_AND && op <= I_MUL) ? (uint32_t)I_ALU : op; };
+      std::stable_sort(ins.begin(), ins.end(), [](const PI& a, const PI& b) {
+        return (a.word & 15) != (b.word & 15) ? (a.word & 15) < (b.word & 15) : a.out_narrow > b.out_narrow;
+      });
+      std::stable_sort(ins.begin(), ins.end(), [](const PI& a, const PI& b) { return a.kind < b.kind; });
       size_t k = 0;
       while (k < ins.size()) {
-        const uint32_t kk = kind(ins[k].op), cap = chunk_capacity(kk);
+        const uint32_t kk = ins[k].kind, cap = in_ops ? 64 : chunk_capacity(kk);
         size_t e = k;
-        while (e < ins.size() && e - k < cap && kind(ins[e].op) == kk) ++e;
-        uint32_t start = (uint32_t)d.plain_instr.size() - pp.instr_off;
-        // an operator chunk carries the set of its opcodes in every
-        // instruction's aux field, so the kernel evaluates only those
-        uint32_t present = 0;
-        if (kk == I_ALU)
-          for (size_t j = k; j < e; ++j) present |= 1u << ins[j].op;
+        while (e < ins.size() && e - k < cap && ins[e].kind == kk) ++e;
+        const uint32_t start = (uint32_t)d.plain_instr.size() - pp.instr_off;
+        uint32_t present = 0, flags = kAllNarrowIn | kAllNarrowOut | kAllWideOut;
         for (size_t j = k; j < e; ++j) {
-          d.plain_instr.push_back(ins[j]);
-          if (kk == I_ALU) d.plain_instr.back().aux = present;
+          if (kk == I_ALU) present |= 1u << (ins[j].word & 15);
+          if (!ins[j].in_narrow) flags &= ~kAllNarrowIn;
+          if (!ins[j].out_narrow) flags &= ~kAllNarrowOut;
+          if (ins[j].out_narrow) flags &= ~kAllWideOut;
+          d.plain_instr.push_back(ins[j].word);
         }
-        d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), kk));
+        d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), kk, present, flags));
         k = e;
       }
-    };
-    std::vector<Instr> ins;
-    uint32_t n_lvls = 0;
-    // level 0: register and input loads (always present, possibly empty)
-    uint32_t i = lo;
-    while (i < hi && d.level[d.proc_nodes[i]] == 0) {
-      uint32_t x = d.proc_nodes[i++];
-      if (d.op[x] == FSIM_OP_REG)
-        ins.push_back(make(I_LDREG, d.width[x], (uint16_t)(8 * slot[x]), 0, 0, 0, (uint32_t)d.imm[x]));
-      else if (d.op[x] == FSIM_OP_INPUT)   // the width folds in the port's own width
-        ins.push_back(make(I_LDIN, std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]),
-                           (uint16_t)(8 * slot[x]), 0, 0, 0, (uint32_t)d.imm[x]));
-    }
-    std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
-    emit_level(ins);
-    n_lvls++;
-    // operator levels (empty levels dropped); unused operand slots repeat a
-    while (i < hi) {
-      uint32_t L = d.level[d.proc_nodes[i]];
-      lvl_nodes.clear();
-      while (i < hi && d.level[d.proc_nodes[i]] == L) lvl_nodes.push_back(d.proc_nodes[i++]);
       ins.clear();
-      for (uint32_t x : lvl_nodes) {
-        uint8_t op = d.op[x];
-        const uint32_t* a = &d.arg[3ull * x];
-        uint16_t sa = (uint16_t)(8 * slot[a[0]]);
-        auto s = [&](int k) -> uint16_t { return k < arity(op) ? (uint16_t)(8 * slot[a[k]]) : sa; };
-        if (op == FSIM_OP_MEMRD)
-          ins.push_back(make(I_MEMRD, d.width[x], (uint16_t)(8 * slot[x]), sa, sa, sa, (uint32_t)d.imm[x]));
-        else
-          ins.push_back(make(op, d.width[x], (uint16_t)(8 * slot[x]), sa, s(1), s(2), 0));
-      }
-      std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
-      emit_level(ins);
       n_lvls++;
-    }
-    // store level
-    ins.clear();
-    for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
-      uint32_t s = d.psinks[k];
-      if (s < d.R)
-        ins.push_back(make(I_STREG, d.reg_width[s], 0, (uint16_t)(8 * slot[d.reg_next[s]]), 0, 0, s));
-      else if (s >= d.R + d.W) {
-        uint32_t o = s - d.R - d.W;
-        ins.push_back(make(I_STOUT, d.width[d.out_node[o]], 0, (uint16_t)(8 * slot[d.out_node[o]]), 0, 0, o));
+    };
+    auto emit_stores = [&](const std::vector<uint32_t>& sinks) {
+      for (uint32_t s : sinks) {
+        const uint32_t x = root(s);
+        if (s < d.R)
+          ins.push_back({plain_index(d.reg_width[s], unit[x], s, narrow(x)), I_STREG, narrow(x), true});
+        else
+          ins.push_back({plain_index(d.width[x], unit[x], s - d.R - d.W, narrow(x)), I_STOUT, narrow(x), true});
       }
+      emit_level();
+    };
+    // level 0: register and input loads (always present, possibly empty)
+    for (uint32_t i = lv_start[0]; i < lv_start[1]; ++i) {
+      const uint32_t x = d.proc_nodes[i];
+      // field 0's narrow flag gives the destination's size (an input's width
+      // also folds in the port's own width)
+      if (d.op[x] == FSIM_OP_REG)
+        ins.push_back({plain_index(d.width[x], unit[x], d.imm[x], narrow(x)), I_LDREG, true, narrow(x)});
+      else if (d.op[x] == FSIM_OP_INPUT)
+        ins.push_back({plain_index(std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]), unit[x], d.imm[x], narrow(x)),
+                       I_LDIN, true, narrow(x)});
     }
-    std::stable_sort(ins.begin(), ins.end(), [](const Instr& a, const Instr& b) { return a.op < b.op; });
-    emit_level(ins);
-    n_lvls++;
+    emit_level();
+    pp.c_ops = (uint32_t)d.plain_chunks.size() - pp.chunk_off;
+    in_ops = true;
+    for (uint32_t j = 0; j <= K; ++j) {
+      if (j > 0) {
+        for (uint32_t i = lv_start[j]; i < lv_start[j + 1]; ++i) {
+          const uint32_t x = d.proc_nodes[i];
+          const uint8_t op = d.op[x];
+          const uint32_t* a = &d.arg[3ull * x];
+          if (op == FSIM_OP_MEMRD) {
+            ins.push_back({plain_word(0, d.width[x], narrow(a[0]) ? 1u : 0u, unit[x], unit[a[0]], d.imm[x] & 0xFFF,
+                                      d.imm[x] >> 12),
+                           I_MEMRD, narrow(a[0]), narrow(x)});
+          } else {
+            // an unused operand repeats a
+            auto opnd = [&](int k) { return a[k < arity(op) ? k : 0]; };
+            const uint32_t nf = (narrow(opnd(0)) ? 1u : 0u) | (narrow(opnd(1)) ? 2u : 0u) | (narrow(opnd(2)) ? 4u : 0u);
+            ins.push_back({plain_word(op, d.width[x], nf, unit[x], unit[opnd(0)], unit[opnd(1)], unit[opnd(2)]), I_ALU,
+                           nf == 7, narrow(x)});
+          }
+        }
+        emit_level();
+      }
+      if (j == K) {
+        pp.c_st = (uint32_t)d.plain_chunks.size() - pp.chunk_off;
+        in_ops = false;
+      }
+      if (!flush[j].empty() || j == K) emit_stores(flush[j]);
+    }
     d.plain_levels.push_back((uint32_t)d.plain_chunks.size() - pp.chunk_off);
     pp.n_lvls = n_lvls;
     pp.n_chunks = (uint32_t)d.plain_chunks.size() - pp.chunk_off;
@@ -943,8 +1096,12 @@ Status encode_plain(Design& d, uint32_t max_slots) {
       uint32_t s = d.psinks[k];
       if (s >= d.R && s < d.R + d.W) {
         uint32_t q = s - d.R;
-        d.plain_instr.push_back(make(I_WPORT, d.mem_width[d.wp_mem[q]], 0, (uint16_t)(8 * slot[d.wp_en[q]]),
-                                     (uint16_t)(8 * slot[d.wp_addr[q]]), (uint16_t)(8 * slot[d.wp_data[q]]), d.wp_mem[q]));
+        if (d.wp_mem[q] >= kMaxWportMems)
+          return Status::err(FSIM_E_CAPACITY, fmt("plain form: memory %llu is past the %llu write-port memories "
+                                                  "its encoding holds", d.wp_mem[q], kMaxWportMems));
+        const uint32_t en = d.wp_en[q], ad = d.wp_addr[q], da = d.wp_data[q];
+        d.plain_instr.push_back(plain_word(0, d.mem_width[d.wp_mem[q]], (narrow(ad) ? 1u : 0u) | (narrow(da) ? 2u : 0u),
+                                           unit[en], unit[ad], unit[da], d.wp_mem[q], narrow(en)));
       }
     }
     pp.n_wp = (uint32_t)d.plain_instr.size() - pp.instr_off - pp.n_instr;
@@ -953,11 +1110,23 @@ Status encode_plain(Design& d, uint32_t max_slots) {
     d.plain_max_chunks = std::max(d.plain_max_chunks, pp.n_chunks);
     d.max_plain_lvls = std::max(d.max_plain_lvls, n_lvls);
     for (uint32_t j = lo; j < hi; ++j) {
-      slot[d.proc_nodes[j]] = UINT32_MAX;
-      last[d.proc_nodes[j]] = 0;
+      unit[d.proc_nodes[j]] = UINT32_MAX;
+      lpos[d.proc_nodes[j]] = 0;
     }
   }
   phase("encode plain");
+  if (getenv("FSIM_VERBOSE") && d.P) {
+    std::vector<uint32_t> ns;
+    for (const PlainProc& q : d.plain_procs) ns.push_back(q.n_slots);
+    std::sort(ns.begin(), ns.end());
+    fprintf(stderr, "fsim compile: plain LDS units per process: p50 %u p90 %u p99 %u max %u\n", ns[ns.size() / 2],
+            ns[ns.size() * 9 / 10], ns[ns.size() * 99 / 100], ns.back());
+    for (uint32_t p = 0; p < d.P; ++p)
+      if (d.plain_procs[p].n_slots + 64 > ns.back())
+        fprintf(stderr, "fsim compile:   process %u: %u units, %u nodes, %u sinks, %u levels, %u chunks\n", p,
+                d.plain_procs[p].n_slots, d.proc_off[p + 1] - d.proc_off[p], d.psink_off[p + 1] - d.psink_off[p],
+                d.plain_procs[p].n_lvls, d.plain_procs[p].n_chunks);
+  }
   return {};
 }
 

@@ -132,23 +132,30 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* flags, uint32_t* error, u
   return *lds_abort == 0;
 }
 
-struct Dec {
-  uint32_t op, w, dst, a, b, c, aux;
-};
-
-// one 16-byte instruction as four plain words
-struct IWord { uint32_t x, y, z, w; };
-
-// The 16-byte instruction is read with one 128-bit load and decoded from
-// registers: x = op | w << 8 | cls << 16 | flags << 24, y = dst | a << 16,
-// z = b | c << 16, w = aux.
-__device__ __forceinline__ Dec decode(uint4 r) {
-  Dec d;
-  d.op = r.x & 0xFF; d.w = (r.x >> 8) & 0xFF;
-  d.dst = r.y & 0xFFFF; d.a = r.y >> 16;
-  d.b = r.z & 0xFFFF; d.c = r.z >> 16;
-  d.aux = r.w;
-  return d;
+// Fields of a plain-form instruction word (isa.h), from its low and high
+// halves.  Fields come out as LDS byte offsets (unit x 4).
+__device__ __forceinline__ uint32_t pw_op(uint32_t lo) { return lo & 15; }
+__device__ __forceinline__ uint32_t pw_w(uint32_t lo) { return (lo >> 4) & 127; }
+__device__ __forceinline__ uint32_t pw_f0(uint32_t lo) { return (lo >> 12) & 0x3FFC; }
+__device__ __forceinline__ uint32_t pw_f1(uint32_t lo, uint32_t hi) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> 24) & 0x3FFC;
 }
+__device__ __forceinline__ uint32_t pw_f2(uint32_t hi) { return (hi >> 4) & 0x3FFC; }
+__device__ __forceinline__ uint32_t pw_f3(uint32_t hi) { return (hi >> 16) & 0x3FFC; }
+// narrow flags: field k (1..3) in bit 10 + k of the low half; field 0 in bit
+// 30 of the high half
+__device__ __forceinline__ bool pw_narrow(uint32_t lo, uint32_t k) { return (lo >> (10 + k)) & 1; }
+__device__ __forceinline__ bool pw_narrow0(uint32_t hi) { return (hi >> 30) & 1; }
+// register, port, output or constant index (bits 26..61)
+__device__ __forceinline__ uint64_t pw_index(uint32_t lo, uint32_t hi) {
+  return (((uint64_t)(hi & 0x3FFFFFFFu)) << 6) | (lo >> 26);
+}
+// memory of a MEMRD (bits 38..61) and of a WPORT (bits 50..61)
+__device__ __forceinline__ uint32_t pw_mem38(uint32_t hi) { return (hi >> 6) & 0xFFFFFF; }
+__device__ __forceinline__ uint32_t pw_mem50(uint32_t hi) { return (hi >> 18) & 0xFFF; }
+
+// one 16-byte batched-form instruction as four plain words: x = op | w << 8
+// | cls << 16 | flags << 24, y = dst | a << 16, z = b | c << 16, w = aux
+struct IWord { uint32_t x, y, z, w; };
 
 }  // namespace fsim

@@ -1,5 +1,6 @@
-// isa.h -- the device instruction format shared by the host encoder and the
-// HIP kernels of libfibersim.  One instruction is 16 bytes.
+// isa.h -- the device instruction formats shared by the host encoder and the
+// HIP kernels of libfibersim: 8-byte words in the plain form, 16-byte
+// instructions in the batched form.
 //
 // A process (a set of fibers, Parendi Sec. 3.2) is encoded as a straight-line,
 // call-free stream (Sec. 5.2 "aggressive inline": the device program has no
@@ -46,11 +47,12 @@ static_assert(sizeof(Instr) == 16, "Instr must be 16 bytes");
 // holds up to 64 instructions of any opcodes, one per lane, whose operands
 // are all read before any lane computes; leaf-load and store chunks hold up
 // to 256 instructions of one opcode, four per lane, all issued before the
-// first is used; memory reads come in chunks of up to 64.  A chunk is one
-// u32: start (16 bits, relative to the first level instruction) |
-// (count - 1) << 16 (8 bits) | opcode << 24.  After the levels comes the
-// write-port commit, run in order by one thread after every read of the
-// cycle.
+// first is used; memory reads come in chunks of up to 64.  After the levels
+// comes the write-port commit, run in order by one thread after every read
+// of the cycle.  Chunks [0, c_ops) are the leaf level, [c_ops, c_st) the
+// operator levels (operator and memory-read chunks, and register and output
+// stores written out early, all of them at most 64 instructions, one per
+// lane) and [c_st, n_chunks) the final store level.
 struct PlainProc {
   uint32_t lvl_off;    // index into the level table: n_lvls + 1 chunk indices
   uint32_t n_lvls;
@@ -62,12 +64,54 @@ struct PlainProc {
   uint32_t n_chunks;
   uint32_t n_wp;       // commit instructions
   uint32_t n_slots;    // u64 LDS slots used
-  uint32_t pad[2];
+  uint32_t c_ops;      // first chunk of the operator levels
+  uint32_t c_st;       // first chunk of the store level
 };
 static_assert(sizeof(PlainProc) == 48, "PlainProc must be 48 bytes");
 
-inline uint32_t make_chunk(uint32_t start, uint32_t count, uint32_t op) {
-  return start | ((count - 1) << 16) | (op << 24);
+// A plain-form instruction is one 64-bit word.  Values live in LDS in
+// 4-byte units: a value of at most 32 bits takes one unit, a wider one two
+// (an even pair); a field names a unit (12 bits), and the flags mark the
+// source fields whose value is narrow (its upper half is not stored).
+//   bits  0..3   opcode & 15 (operators 4..15; other instructions take their
+//                kind from the chunk)
+//   bits  4..10  width 1..64 (STREG: the register's; LDIN: the smaller of
+//                the node's and the port's; WPORT: the memory's)
+//   bits 11..13  narrow flags of fields 1, 2, 3
+//   bits 14..25  field 0        bits 26..37  field 1
+//   bits 38..49  field 2        bits 50..61  field 3
+//   bit  62      narrow flag of field 0 (when it is a source)
+// Operators: destination, then operands a, b, c in fields 0..3 (an unused
+// operand repeats a).  Leaf loads (LDREG, LDIN) and the prologue (LDCONST):
+// the destination in field 0 (its narrow flag gives the destination's size),
+// the register, port or constant index in bits 26..61.  Stores (STREG, STOUT): the source in field 0, the register or
+// output index in bits 26..61.  MEMRD: destination and address, the memory
+// in bits 38..61.  WPORT: enable, address and data, the memory in bits
+// 50..61.
+constexpr uint32_t kUnitBits = 12;
+// units 0 and 1 (the first 8 bytes of a process's LDS) hold no value: the
+// one-wave kernel keeps its barrier abort flag there
+constexpr uint32_t kPlainUnitBase = 2;
+constexpr uint32_t kMaxPlainUnits = (1u << kUnitBits) - 1;
+constexpr uint32_t kMaxWportMems = 1u << 12;
+inline uint64_t plain_word(uint32_t op, uint32_t w, uint32_t narrow123, uint64_t f0, uint64_t f1, uint64_t f2,
+                           uint64_t f3, bool narrow0 = false) {
+  return (op & 15) | (uint64_t)w << 4 | (uint64_t)narrow123 << 11 | f0 << 14 | f1 << 26 | f2 << 38 | f3 << 50 |
+         (uint64_t)narrow0 << 62;
+}
+inline uint64_t plain_index(uint32_t w, uint64_t f0, uint64_t index, bool narrow0 = false) {
+  return (uint64_t)w << 4 | f0 << 14 | index << 26 | (uint64_t)narrow0 << 62;
+}
+
+// A chunk word: start (16 bits, relative to the first level instruction) |
+// (count - 1) << 16 | kind << 24 | the set of opcodes in an operator chunk
+// (bit k for opcode k) << 32 | flags << 48: kAllNarrowIn (every source field
+// of every instruction is narrow), kAllNarrowOut (every result is narrow),
+// kAllWideOut (every result is wide).
+constexpr uint32_t kAllNarrowIn = 1, kAllNarrowOut = 2, kAllWideOut = 4;
+inline uint64_t make_chunk(uint32_t start, uint32_t count, uint32_t kind, uint32_t present = 0, uint32_t flags = 0) {
+  return start | ((uint64_t)(count - 1) << 16) | ((uint64_t)kind << 24) | ((uint64_t)present << 32) |
+         ((uint64_t)flags << 48);
 }
 inline uint32_t chunk_capacity(uint32_t op) {
   return (op == I_LDREG || op == I_LDIN || op == I_STREG || op == I_STOUT) ? 256 : 64;

@@ -9,20 +9,20 @@
 
 namespace fsim {
 
-// One-wave plain kernel reading instructions from global memory: the first
-// instructions of this many chunks are in flight at once (a chunk's load is
-// issued this many chunks before it runs).  The LDS chunk table holds at
-// least kWaveSlots + 1 zero words past a process's last chunk.
-constexpr uint32_t kWaveSlots = 2;
+// One-wave plain kernel: the operator levels run in groups of this many
+// chunks, and the instructions of the next group are fetched when a group
+// starts, so a fetch has a whole group's time to land.  The LDS chunk table
+// holds 2 kGroup zero words past a process's last chunk.
+constexpr uint32_t kGroup = 2;
 
 // Words of the grid barrier's flag array for G workgroups: one epoch flag per
 // workgroup, then one per group of 64 workgroups.
 constexpr uint32_t barrier_words(uint32_t G) { return G + (G + 63) / 64; }
 
 struct PlainArgs {
-  const Instr* instr;
+  const uint64_t* code;        // instruction words (isa.h)
   const uint32_t* levels;      // per process: chunk index where each level starts
-  const uint32_t* chunks;      // opcode-uniform chunks
+  const uint64_t* chunks;      // chunk words
   const PlainProc* procs;
   const uint64_t* consts;
   uint64_t* state;            // [2][R]: cur = cycle & 1
@@ -30,6 +30,7 @@ struct PlainArgs {
   uint64_t* mem;              // all memories, back to back
   const uint64_t* mem_off;    // [M]
   const uint32_t* mem_depth;  // [M]
+  const uint64_t* mem_magic;  // [M]: floor((2^64 - 1) / depth)
   const uint8_t* in_width;    // [I]
   const uint64_t* in_keys;    // [I]: H(H(seed) ^ p)
   const uint64_t* in_vals;    // explicit inputs [n][I], or null
@@ -44,15 +45,14 @@ struct PlainArgs {
   uint32_t R, I;
   uint32_t stage_instr;       // instructions staged in LDS
   uint32_t slot_words;        // u64 words of LDS reserved for slots
-  uint32_t ctab_words;        // one-wave kernel: u32 entries of the LDS chunk table after the slots
-                              // (the most chunks of any process + 3 zero entries, rounded up to 4)
-  uint32_t instr_words;       // 16-byte instruction slots staged in LDS
-  uint32_t chunk_words;       // u32 chunk words reserved in LDS
+  uint32_t ctab_words;        // one-wave kernel: u64 entries of the LDS chunk table after the slots
+                              // (the most chunks of any process + 2 kGroup zero entries)
+  uint32_t instr_words;       // instruction words staged in LDS (after the chunk table)
   uint64_t cycle0;            // absolute cycle at the first cycle of this launch
   uint32_t n_cycles;
   uint32_t epoch0;            // barrier epoch before this launch
   const uint64_t* cycle_ptr;  // graph mode: absolute base cycle in device memory
-  uint32_t single_wave;       // 64-thread workgroups, staged, <= 256 chunks: flat chunk loop
+  uint32_t single_wave;       // 64-thread workgroups: the one-wave kernel
 };
 
 // Batched form: one wave per (process, tile of 64 instances).  State is kept

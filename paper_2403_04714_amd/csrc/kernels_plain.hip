@@ -37,6 +37,194 @@
 
 namespace fsim {
 
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint64_t rfl64(uint64_t v) {
+  return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
+}
+
+// LDS value access by byte offset.  A narrow value (at most 32 bits) is one
+// 4-byte unit and the unit after it belongs to another value, so a read
+// takes 8 bytes and drops the upper half of a narrow value; a wide value is
+// an 8-byte aligned pair.
+__device__ __forceinline__ uint64_t ld_raw(const char* base, uint32_t off) {
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(base + off);
+  return (uint64_t)p[0] | ((uint64_t)p[1] << 32);
+}
+__device__ __forceinline__ uint64_t ld_val(const char* base, uint32_t off, bool narrow) {
+  const uint64_t v = ld_raw(base, off);
+  return narrow ? (uint32_t)v : v;
+}
+// A store of either size without a branch: the low half goes to its unit,
+// the high half to the next unit for a wide value and to the spare unit at
+// `trash` (never read as a value) for a narrow one.
+__device__ __forceinline__ void st_val(char* base, uint32_t off, uint64_t v, bool narrow, uint32_t trash) {
+  *reinterpret_cast<uint32_t*>(base + off) = (uint32_t)v;
+  *reinterpret_cast<uint32_t*>(base + (narrow ? trash : off + 4)) = (uint32_t)(v >> 32);
+}
+// the spare unit: the last 4 bytes of the value area
+__device__ __forceinline__ uint32_t trash_off(const PlainArgs& A) { return A.slot_words * 8 - 4; }
+
+// Per-cycle state shared by the chunk handlers of both plain kernels.
+struct PlainCycle {
+  const uint64_t* cur;     // current register values
+  uint64_t* nxt;           // next register values
+  uint64_t cyc;            // absolute cycle
+  uint64_t dacc;           // this lane's digest terms
+};
+
+// A leaf-load or sink-store chunk: up to four instructions per lane (lane +
+// 64 q), every load issued before the first result is used.  `raw` is the
+// lane's first instruction (already fetched); Is the process's
+// instructions; base the LDS value area.
+__device__ __forceinline__ void plain_wide_chunk(const PlainArgs& A, PlainCycle& C, const uint64_t* Is,
+                                                 uint64_t cw, uint64_t raw, uint32_t lane, char* base) {
+  const uint32_t start = (uint32_t)cw & 0xFFFF, cnt = ((uint32_t)(cw >> 16) & 0xFF) + 1;
+  const uint32_t op = (uint32_t)(cw >> 24) & 0xFF;
+  uint64_t rq[4], v[4];
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t e = lane + 64 * q;
+    if (e < cnt) {
+      rq[q] = q == 0 ? raw : Is[start + e];
+      const uint32_t lo = (uint32_t)rq[q], hi = (uint32_t)(rq[q] >> 32);
+      const uint64_t ix = pw_index(lo, hi);
+      if (op == I_LDREG) {
+        v[q] = C.cur[ix];
+      } else if (op == I_LDIN) {
+        if (A.in_vals) {
+          if (C.cyc < A.in_first || C.cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v[q] = 0; }
+          else v[q] = A.in_vals[(C.cyc - A.in_first) * A.I + ix];
+        } else {
+          v[q] = hmix(A.in_keys[ix] ^ C.cyc);
+        }
+      } else {
+        v[q] = ld_val(base, pw_f0(lo), pw_narrow0(hi));
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint32_t e = lane + 64 * q;
+    if (e < cnt) {
+      const uint32_t lo = (uint32_t)rq[q], hi = (uint32_t)(rq[q] >> 32);
+      const uint64_t x = v[q] & wmask(pw_w(lo));   // LDIN widths fold in the port width
+      if (op == I_LDREG || op == I_LDIN) {
+        st_val(base, pw_f0(lo), x, pw_narrow0(hi), trash_off(A));
+      } else if (op == I_STREG) {
+        const uint64_t r = pw_index(lo, hi);
+        C.nxt[r] = x;
+        if (A.digest_part) C.dacc += hmix(r ^ hmix(x));
+      } else {
+        A.outputs[pw_index(lo, hi)] = x;
+      }
+    }
+  }
+}
+
+// An operator chunk: one instruction per lane, every operand read before any
+// lane computes.  Lanes past the chunk's end hold its last instruction: they
+// read the same operands and store the same value to the same place, so the
+// store needs no guard.  `cw` is the chunk word (wave-uniform).
+__device__ __forceinline__ void plain_alu_chunk(uint64_t cw, uint64_t raw, char* base, uint32_t trash) {
+  const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
+  const uint32_t flags = (uint32_t)(cw >> 48);
+  uint64_t a = ld_raw(base, pw_f1(lo, hi)), b = ld_raw(base, pw_f2(hi)), c = ld_raw(base, pw_f3(hi));
+  asm volatile("; operands of an operator chunk ready" : "+v"(a), "+v"(b), "+v"(c));
+  if (flags & kAllNarrowIn) {
+    a = (uint32_t)a; b = (uint32_t)b; c = (uint32_t)c;
+  } else {
+    if (pw_narrow(lo, 1)) a = (uint32_t)a;
+    if (pw_narrow(lo, 2)) b = (uint32_t)b;
+    if (pw_narrow(lo, 3)) c = (uint32_t)c;
+  }
+  const uint32_t w = pw_w(lo);
+  const uint64_t r = alu_mixed((uint32_t)(cw >> 32), pw_op(lo), w, a, b, c);
+  if (flags & kAllNarrowOut) *reinterpret_cast<uint32_t*>(base + pw_f0(lo)) = (uint32_t)r;
+  else if (flags & kAllWideOut) *reinterpret_cast<uint64_t*>(base + pw_f0(lo)) = r;
+  else st_val(base, pw_f0(lo), r, w <= 32, trash);
+}
+
+// A memory-read chunk.  Lanes past the chunk's end repeat its last read.
+__device__ __forceinline__ void plain_memrd(const PlainArgs& A, uint64_t raw, char* base) {
+  const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
+  const uint64_t addr_v = ld_val(base, pw_f1(lo, hi), pw_narrow(lo, 1));
+  const uint32_t m = pw_mem38(hi);
+  // addr_v mod depth without a branch (lanes may read different memories):
+  // q = floor(addr_v * magic / 2^64) is at most two below the quotient
+  const uint64_t depth = A.mem_depth[m];
+  const uint64_t q = __umul64hi(addr_v, A.mem_magic[m]);
+  uint64_t addr = addr_v - q * depth;
+  addr = addr >= depth ? addr - depth : addr;
+  addr = addr >= depth ? addr - depth : addr;
+  const uint32_t w = pw_w(lo);
+  st_val(base, pw_f0(lo), A.mem[A.mem_off[m] + addr] & wmask(w), w <= 32, trash_off(A));
+}
+
+// Register or output stores written out among the operator levels: one per
+// lane.  Lanes past the chunk's end repeat its last store (the same value to
+// the same place) and add nothing to the digest.
+__device__ __forceinline__ void plain_store64(const PlainArgs& A, PlainCycle& C, uint64_t cw, uint64_t raw,
+                                              uint32_t lane, const char* base) {
+  const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
+  const uint64_t x = ld_val(base, pw_f0(lo), pw_narrow0(hi)) & wmask(pw_w(lo));
+  const uint64_t ix = pw_index(lo, hi);
+  if (((uint32_t)(cw >> 24) & 0xFF) == I_STREG) {
+    C.nxt[ix] = x;
+    if (A.digest_part) C.dacc += lane <= ((uint32_t)(cw >> 16) & 0xFF) ? hmix(ix ^ hmix(x)) : 0;
+  } else {
+    A.outputs[ix] = x;
+  }
+}
+
+// A chunk of the operator levels: operators, memory reads, and register
+// and output stores written out before the last level; one instruction per
+// lane and no branch that differs between lanes.
+__device__ __forceinline__ void plain_op_level_chunk(const PlainArgs& A, PlainCycle& C, uint64_t cw, uint64_t raw,
+                                                     uint32_t lane, char* base) {
+  const uint32_t kind = (uint32_t)(cw >> 24) & 0xFF;
+  if (kind == I_ALU) plain_alu_chunk(cw, raw, base, trash_off(A));
+  else if (kind == I_MEMRD) plain_memrd(A, raw, base);
+  else plain_store64(A, C, cw, raw, lane, base);
+}
+
+// Any chunk (the multi-wave kernel, which runs every level alike).
+__device__ __forceinline__ void plain_level_chunk(const PlainArgs& A, PlainCycle& C, const uint64_t* Is, uint64_t cw,
+                                                  uint64_t raw, uint32_t lane, char* base) {
+  const uint32_t kind = (uint32_t)(cw >> 24) & 0xFF;
+  if (kind == I_ALU) plain_alu_chunk(cw, raw, base, trash_off(A));
+  else if (kind == I_MEMRD) plain_memrd(A, raw, base);
+  else plain_wide_chunk(A, C, Is, cw, raw, lane, base);
+}
+
+// The write-port commit: after every read of the cycle, in port order, by
+// one lane.
+__device__ __forceinline__ void plain_commit(const PlainArgs& A, const uint64_t* Is, const PlainProc& pp, char* base) {
+  for (uint32_t k = 0; k < pp.n_wp; ++k) {
+    const uint64_t w = Is[pp.n_instr + k];
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    if (ld_val(base, pw_f0(lo), pw_narrow0(hi)) != 0) {
+      const uint32_t m = pw_mem50(hi);
+      const uint64_t depth = A.mem_depth[m], av = ld_val(base, pw_f1(lo, hi), pw_narrow(lo, 1));
+      const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
+      A.mem[A.mem_off[m] + addr] = ld_val(base, pw_f2(hi), pw_narrow(lo, 2)) & wmask(pw_w(lo));
+    }
+  }
+}
+
+// The constant prologue: every constant into its LDS place, once per launch.
+__device__ __forceinline__ void plain_consts(const PlainArgs& A, const PlainProc& pp, uint32_t tid, uint32_t nthr,
+                                             char* base) {
+  for (uint32_t i = tid; i < pp.n_consts; i += nthr) {
+    const uint64_t w = A.code[pp.const_off + i];
+    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
+    st_val(base, pw_f0(lo), A.consts[pw_index(lo, hi)], pw_narrow0(hi), trash_off(A));
+  }
+}
+
+// Multi-wave workgroups: the chunks of a level are spread over the waves,
+// with a workgroup barrier between levels.  Chunk words are read from
+// global memory; the instructions from global memory or (STAGED) from an
+// LDS copy made at launch.
 template <bool PERSISTENT, bool STAGED>
 __device__ void plain_body(const PlainArgs& A) {
   extern __shared__ uint64_t lds[];
@@ -45,169 +233,52 @@ __device__ void plain_body(const PlainArgs& A) {
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
   const uint32_t lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
   const PlainProc pp = A.procs[blockIdx.x];
-  // value slots: instruction operands are byte offsets into the slot area
-  char* const slot_base = reinterpret_cast<char*>(lds);
-  auto at = [slot_base](uint32_t off) -> uint64_t& { return *reinterpret_cast<uint64_t*>(slot_base + off); };
+  char* const base = reinterpret_cast<char*>(lds);
   const uint32_t n_all = pp.n_instr + pp.n_wp;
-  const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
-  uint4* Is = reinterpret_cast<uint4*>(lds + A.slot_words);
-  uint32_t* chunks = reinterpret_cast<uint32_t*>(Is + (STAGED ? A.instr_words : 0));
-  uint32_t* lvs = chunks + A.chunk_words;
+  const uint64_t* const Ig = A.code + pp.instr_off;
+  uint64_t* const Ist = lds + A.slot_words;
   if (STAGED)
-    for (uint32_t i = tid; i < n_all; i += nthr) Is[i] = Ig[i];
-  for (uint32_t i = tid; i < pp.n_chunks; i += nthr) chunks[i] = A.chunks[pp.chunk_off + i];
-  for (uint32_t L = tid; L <= pp.n_lvls; L += nthr) lvs[L] = A.levels[pp.lvl_off + L];
-  for (uint32_t i = tid; i < pp.n_consts; i += nthr) {
-    const Instr in = A.instr[pp.const_off + i];
-    at(in.dst) = A.consts[in.aux];
-  }
+    for (uint32_t i = tid; i < n_all; i += nthr) Ist[i] = Ig[i];
+  const uint64_t* const Is = STAGED ? Ist : Ig;
+  plain_consts(A, pp, tid, nthr, base);
   if (tid == 0) abort_flag = 0;
   __syncthreads();
-  auto fetch = [&](uint32_t i) -> uint4 { return STAGED ? Is[i] : Ig[i]; };
-  const uint32_t n_lvls = pp.n_lvls;
-  // the level table (chunk index where each level starts) lives in the lanes
-  // of two registers and is read with v_readlane; deeper processes fall back
-  // to the LDS copy
-  const uint32_t lv_lo = lane <= n_lvls ? lvs[lane] : 0;
-  const uint32_t lv_hi = lane + 64 <= n_lvls ? lvs[lane + 64] : 0;
-  auto lvl = [&](uint32_t L) -> uint32_t {
-    if (L < 64) return (uint32_t)__builtin_amdgcn_readlane((int)lv_lo, (int)L);
-    if (L < 128) return (uint32_t)__builtin_amdgcn_readlane((int)lv_hi, (int)(L - 64));
-    return lvs[L];
-  };
-  // one wave: LDS operations of a wave complete in order, so a level needs no
-  // s_barrier, only a compiler barrier
-  const bool one_wave = nthr <= 64;
+  const uint64_t* const chunks = A.chunks + pp.chunk_off;
+  const uint32_t* const lv = A.levels + pp.lvl_off;
   const uint64_t cyc0 = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
-  // phase timestamps: [cycle][workgroup][trace_stride] of the 100 MHz
-  // realtime counter: cycle start, end of every level, commit, barrier
   uint64_t* trace_row = nullptr;
   for (uint32_t t = 0; t < A.n_cycles; ++t) {
-    const uint64_t cyc = cyc0 + t;
-    const uint64_t* cur = A.state + (cyc & 1) * A.R;
-    uint64_t* nxt = A.state + ((cyc + 1) & 1) * A.R;
-    uint64_t dacc = 0;
+    PlainCycle C;
+    C.cyc = cyc0 + t;
+    C.cur = A.state + (C.cyc & 1) * A.R;
+    C.nxt = A.state + ((C.cyc + 1) & 1) * A.R;
+    C.dacc = 0;
     if (A.trace && tid == 0) {
-      const uint64_t k = cyc - A.trace_first;
+      const uint64_t k = C.cyc - A.trace_first;
       trace_row = k < A.trace_max ? A.trace + (k * gridDim.x + blockIdx.x) * A.trace_stride : nullptr;
       if (trace_row) trace_row[0] = __builtin_amdgcn_s_memrealtime();
     }
-    // this wave's first chunk of level 0 and its instruction, and the first
-    // chunk word of level 1 (a level always exists after the leaf level)
-    uint32_t c_lo = lvl(0), c_hi = lvl(1);
-    uint32_t ch_first = c_lo + wave < c_hi ? chunks[c_lo + wave] : 0;
-    ch_first = __builtin_amdgcn_readfirstlane(ch_first);
-    uint4 raw_first = make_uint4(0, 0, 0, 0);
-    if (c_lo + wave < c_hi && lane <= ((ch_first >> 16) & 0xFF)) raw_first = fetch((ch_first & 0xFFFF) + lane);
-    uint32_t n_lo = c_hi, n_hi = n_lvls > 1 ? lvl(2) : c_hi;
-    uint32_t ch_next = __builtin_amdgcn_readfirstlane(n_lo + wave < n_hi ? chunks[n_lo + wave] : 0);
-    for (uint32_t L = 0; L < n_lvls; ++L) {
-      // Prefetch, issued with this level's operand reads so that the
-      // latencies overlap: the next level's first instruction for this wave
-      // and the first chunk word two levels ahead.  Instructions and chunk
-      // words never change during the launch.
-      const bool have_next = n_lo + wave < n_hi;
-      uint4 raw_next = make_uint4(0, 0, 0, 0);
-      if (have_next && lane <= ((ch_next >> 16) & 0xFF)) raw_next = fetch((ch_next & 0xFFFF) + lane);
-      const uint32_t m_lo = n_hi, m_hi = L + 2 < n_lvls ? lvl(L + 3) : n_hi;
-      const uint32_t ch_after = m_lo + wave < m_hi ? chunks[m_lo + wave] : 0;
-      bool first = true;
-      for (uint32_t c = c_lo + wave; c < c_hi; c += nwaves) {
-        uint32_t ch = first ? ch_first : __builtin_amdgcn_readfirstlane(chunks[c]);
-        const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 0xFF) + 1, op = ch >> 24;
-        if (op == I_ALU) {
-          // operators of mixed opcodes: every operand is read before any lane
-          // computes, so the level costs one LDS round trip; the opcode
-          // switch then runs on registers only
-          if (lane < cnt) {
-            const Dec in = decode(first ? raw_first : fetch(start + lane));
-            uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
-            asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
-            const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
-            at(in.dst) = alu_mixed(present, in.op, in.w, a, b, cc);
-          }
-        } else if (op == I_LDREG || op == I_LDIN || op == I_STREG || op == I_STOUT) {
-          // up to four instructions per lane; all loads are issued before the
-          // first result is used
-          Dec in[4];
-          uint64_t v[4];
-#pragma unroll
-          for (uint32_t q = 0; q < 4; ++q) {
-            const uint32_t e = lane + 64 * q;
-            if (e < cnt) {
-              in[q] = decode(q == 0 && first ? raw_first : fetch(start + e));
-              if (op == I_LDREG) {
-                v[q] = cur[in[q].aux];
-              } else if (op == I_LDIN) {
-                if (A.in_vals) {
-                  if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v[q] = 0; }
-                  else v[q] = A.in_vals[(cyc - A.in_first) * A.I + in[q].aux];
-                } else {
-                  v[q] = hmix(A.in_keys[in[q].aux] ^ cyc);
-                }
-              } else {
-                v[q] = at(in[q].a);
-              }
-            }
-          }
-#pragma unroll
-          for (uint32_t q = 0; q < 4; ++q) {
-            const uint32_t e = lane + 64 * q;
-            if (e < cnt) {
-              const uint64_t x = v[q] & wmask(in[q].w);   // LDIN widths fold in the port width
-              if (op == I_LDREG || op == I_LDIN) {
-                at(in[q].dst) = x;
-              } else if (op == I_STREG) {
-                nxt[in[q].aux] = x;
-                if (A.digest_part) dacc += hmix((uint64_t)in[q].aux ^ hmix(x));
-              } else {
-                A.outputs[in[q].aux] = x;
-              }
-            }
-          }
-        } else if (op == I_MEMRD) {
-          if (lane < cnt) {
-            const Dec in = decode(first ? raw_first : fetch(start + lane));
-            const uint64_t a = at(in.a);
-            const uint64_t depth = A.mem_depth[in.aux];
-            const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-            at(in.dst) = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
-          }
-        }
-        first = false;
+    for (uint32_t L = 0; L < pp.n_lvls; ++L) {
+      const uint32_t c_hi = lv[L + 1];
+      for (uint32_t c = rfl(lv[L] + wave); c < c_hi; c += nwaves) {
+        const uint64_t cw = rfl64(chunks[c]);
+        const uint32_t m = (uint32_t)(cw >> 16) & 0xFF;
+        const uint64_t raw = Is[((uint32_t)cw & 0xFFFF) + (lane < m ? lane : m)];
+        plain_level_chunk(A, C, Is, cw, raw, lane, base);
       }
-      ch_first = ch_next;
-      raw_first = raw_next;
-      ch_next = __builtin_amdgcn_readfirstlane(ch_after);
-      c_lo = n_lo;
-      c_hi = n_hi;
-      n_lo = m_lo;
-      n_hi = m_hi;
-      if (one_wave) asm volatile("" ::: "memory");
-      else __syncthreads();
+      __syncthreads();
       if (trace_row && L + 2 < A.trace_stride) trace_row[L + 1] = __builtin_amdgcn_s_memrealtime();
     }
-    // memory commit after every read of this cycle, in port order
-    if (tid == 0) {
-      for (uint32_t k = 0; k < pp.n_wp; ++k) {
-        const Dec in = decode(fetch(pp.n_instr + k));
-        if (at(in.a) != 0) {
-          const uint32_t m = in.aux;
-          const uint64_t depth = A.mem_depth[m], av = at(in.b);
-          const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
-          A.mem[A.mem_off[m] + addr] = at(in.c) & wmask(in.w);
-        }
-      }
-    }
+    if (tid == 0) plain_commit(A, Is, pp, base);
     if (A.digest_part) {
-      // workgroup reduction of the digest terms; partial per workgroup
+      uint64_t dacc = C.dacc;
       for (int off = 32; off > 0; off >>= 1) dacc += __shfl_xor(dacc, off);
       if (lane == 0) red[wave] = dacc;
       __syncthreads();
       if (tid == 0) {
         uint64_t s = 0;
         for (uint32_t k = 0; k < nwaves; ++k) s += red[k];
-        const uint64_t k = cyc - A.digest_first;
+        const uint64_t k = C.cyc - A.digest_first;
         if (k < A.digest_max) A.digest_part[k * gridDim.x + blockIdx.x] = s;
       }
     }
@@ -218,88 +289,79 @@ __device__ void plain_body(const PlainArgs& A) {
       } else {
         __syncthreads();
       }
+    } else {
+      __syncthreads();
     }
     if (trace_row) trace_row[A.trace_stride - 1] = __builtin_amdgcn_s_memrealtime();
   }
 }
 
-// Single-wave processes (64 threads): LDS operations of one wave complete in
-// order, so the levels need no barrier and the chunks of all levels run as
-// one flat sequence.  The chunk words sit in an LDS table after the value
-// slots, each read with one broadcast LDS read a few chunks ahead, and the
-// first instruction of a later chunk is fetched while the current one runs.
-// STAGED: the process's instructions are copied into LDS at launch and read
-// from there.  Otherwise they are read from global memory, the first
-// instruction of each chunk kWaveSlots chunks ahead, and the workgroup's LDS
-// holds only the value slots and the chunk table, so that many more
-// workgroups are resident at once (large designs) and nothing is copied per
-// launch.
+// Single-wave processes (64 threads).  LDS operations of one wave complete
+// in order, so the levels need no barrier.  LDS holds the values, the chunk
+// table (zero past the last chunk) and, when STAGED, a copy of the process's
+// instructions made at launch; otherwise the instructions are read from
+// global memory.  A cycle runs in three phases: the leaf level (register and
+// input loads), the operator levels, the final store level.
+//   STAGED: the operator levels run chunk by chunk, the next chunk's
+//   instruction read from LDS while the current chunk's operands are read.
+//   Otherwise: in groups of kGroup chunks, and when a group starts the first
+//   instruction of every chunk of the next group is fetched, so that each
+//   global fetch has a whole group's time to land.  The first group is
+//   fetched before the leaf level.
 template <bool PERSISTENT, bool STAGED, bool TRACE>
 __device__ void plain_wave_body(const PlainArgs& A) {
+  // no static LDS: the value area starts at address 0, so value offsets are
+  // LDS addresses; its first 8 bytes (reserved units) hold the abort flag of
+  // the grid barrier
   extern __shared__ uint64_t lds[];
-  __shared__ int abort_flag;
+  int* const abort_flag = reinterpret_cast<int*>(lds);
   const uint32_t lane = threadIdx.x;
   const PlainProc pp = A.procs[blockIdx.x];
-  // value slots: instruction operands are byte offsets into the slot area
-  char* const slot_base = reinterpret_cast<char*>(lds);
-  auto at = [slot_base](uint32_t off) -> uint64_t& { return *reinterpret_cast<uint64_t*>(slot_base + off); };
+  char* const base = reinterpret_cast<char*>(lds);
   const uint32_t n_all = pp.n_instr + pp.n_wp;
-  const uint4* Ig = reinterpret_cast<const uint4*>(A.instr) + pp.instr_off;
-  // after the slots: the process's chunk words (zero past the last chunk,
-  // read a few chunks ahead with one broadcast LDS read each), then the
-  // staged instructions
-  uint32_t* const ctab = reinterpret_cast<uint32_t*>(lds + A.slot_words);
-  char* const ibase = reinterpret_cast<char*>(ctab) + 4 * A.ctab_words;
-  // instruction i of the process (LDS copy or global memory)
-  const uint4* const Is = STAGED ? reinterpret_cast<const uint4*>(ibase) : Ig;
-  // staging, eight loads in flight per lane (one memory latency per 512
-  // instructions; the per-cycle launch modes stage on every launch)
-  // (plain 16-byte words, not uint4: an array of the vector type is kept in
-  // scratch memory by the compiler)
-  const IWord* Igw = reinterpret_cast<const IWord*>(Ig);
-  IWord* Isw = reinterpret_cast<IWord*>(ibase);
-  for (uint32_t base = 0; STAGED && base < n_all; base += 512) {
-    IWord t[8];
+  const uint64_t* const Ig = A.code + pp.instr_off;
+  uint64_t* const ctab = lds + A.slot_words;
+  uint64_t* const Ist = ctab + A.ctab_words;
+  // staging, eight loads in flight per lane
+  for (uint32_t b0 = 0; STAGED && b0 < n_all; b0 += 512) {
+    uint64_t t[8];
 #pragma unroll
     for (uint32_t q = 0; q < 8; ++q) {
-      const uint32_t i = base + lane + 64 * q;
-      t[q] = i < n_all ? Igw[i] : IWord{0, 0, 0, 0};
+      const uint32_t i = b0 + lane + 64 * q;
+      t[q] = i < n_all ? Ig[i] : 0;
     }
 #pragma unroll
     for (uint32_t q = 0; q < 8; ++q) {
-      const uint32_t i = base + lane + 64 * q;
-      if (i < n_all) Isw[i] = t[q];
+      const uint32_t i = b0 + lane + 64 * q;
+      if (i < n_all) Ist[i] = t[q];
     }
   }
-  for (uint32_t i = lane; i < pp.n_consts; i += 64) {
-    const Instr in = A.instr[pp.const_off + i];
-    at(in.dst) = A.consts[in.aux];
-  }
+  const uint64_t* const Is = STAGED ? Ist : Ig;
+  plain_consts(A, pp, lane, 64, base);
   const uint32_t n_ch = pp.n_chunks;
   for (uint32_t i = lane; i < A.ctab_words; i += 64) ctab[i] = i < n_ch ? A.chunks[pp.chunk_off + i] : 0;
   // level starts, for the phase timestamps only
   const uint32_t n_lvls = pp.n_lvls;
   const uint32_t lv_lo = TRACE && lane <= n_lvls ? A.levels[pp.lvl_off + lane] : 0;
-  if (lane == 0) abort_flag = 0;
+  if (lane == 0) *abort_flag = 0;
   __syncthreads();
-  // the first instruction of a chunk for this lane; lanes past the chunk's
-  // end get its last instruction (valid slots to read; an operator chunk
-  // stores their result, the same value to the same slot as the last lane,
-  // other chunks guard by count).  No condition: the load stays in the basic block of the
-  // operand reads it overlaps.  For "no chunk" (word 0) it reads entry 0.
-  auto first_instr = [&](uint32_t chw) -> uint4 {
-    const uint32_t m = (chw >> 16) & 0xFF;
-    return Is[(chw & 0xFFFF) + (lane < m ? lane : m)];
+  // the lane's instruction of a chunk; lanes past the end take the last one
+  // (a zero word, past the last chunk, reads instruction 0)
+  auto first_instr = [&](uint64_t cw) -> uint64_t {
+    const uint32_t m = (uint32_t)(cw >> 16) & 0xFF;
+    return Is[((uint32_t)cw & 0xFFFF) + (lane < m ? lane : m)];
   };
   const uint64_t cyc0 = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
   uint64_t* trace_row = nullptr;
+  const uint32_t c_ops = pp.c_ops, c_st = pp.c_st;
   for (uint32_t t = 0; t < A.n_cycles; ++t) {
-    const uint64_t cyc = cyc0 + t;
-    const uint64_t* cur = A.state + (cyc & 1) * A.R;
-    uint64_t* nxt = A.state + ((cyc + 1) & 1) * A.R;
-    uint64_t dacc = 0;
+    PlainCycle C;
+    C.cyc = cyc0 + t;
+    C.cur = A.state + (C.cyc & 1) * A.R;
+    C.nxt = A.state + ((C.cyc + 1) & 1) * A.R;
+    C.dacc = 0;
     if (TRACE && A.trace) {
-      const uint64_t k = cyc - A.trace_first;
+      const uint64_t k = C.cyc - A.trace_first;
       trace_row = k < A.trace_max ? A.trace + (k * gridDim.x + blockIdx.x) * A.trace_stride : nullptr;
       if (trace_row && lane == 0) trace_row[0] = __builtin_amdgcn_s_memrealtime();
     }
@@ -313,199 +375,99 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         ++L_next;
       }
     };
-    uint32_t c = 0;
-    // chunk word cc, as a wave-uniform value (the read is issued where the
-    // word is loaded, the scalar copy taken where it is needed)
-    auto rfl = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
-    // a leaf-load, sink-store or memory-read chunk whose first instruction
-    // for this lane is `raw`
-    auto other_chunk = [&](const uint4 raw, const uint32_t ch) {
-      const uint32_t start = ch & 0xFFFF, cnt = ((ch >> 16) & 0xFF) + 1, op = ch >> 24;
-      if (op == I_MEMRD) {
-        if (lane < cnt) {
-          const Dec in = decode(raw);
-          const uint64_t a = at(in.a);
-          const uint64_t depth = A.mem_depth[in.aux];
-          const uint64_t addr = (depth & (depth - 1)) ? a % depth : (a & (depth - 1));
-          at(in.dst) = A.mem[A.mem_off[in.aux] + addr] & wmask(in.w);
-        }
-      } else {
-        // leaf loads and sink stores, up to four per lane, loads all issued
-        // before the first is used (the raw instructions are kept, not their
-        // decoded fields, to spare registers)
-        uint4 rq[4];
-        uint64_t v[4];
-#pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
-          const uint32_t e = lane + 64 * q;
-          if (e < cnt) {
-            rq[q] = q == 0 ? raw : Is[start + e];
-            const Dec in = decode(rq[q]);
-            if (op == I_LDREG) {
-              v[q] = cur[in.aux];
-            } else if (op == I_LDIN) {
-              if (A.in_vals) {
-                if (cyc < A.in_first || cyc >= A.in_first + A.in_count) { atomicOr(&A.error[1], 1u); v[q] = 0; }
-                else v[q] = A.in_vals[(cyc - A.in_first) * A.I + in.aux];
-              } else {
-                v[q] = hmix(A.in_keys[in.aux] ^ cyc);
-              }
-            } else {
-              v[q] = at(in.a);
-            }
-          }
-        }
-#pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
-          const uint32_t e = lane + 64 * q;
-          if (e < cnt) {
-            const Dec in = decode(rq[q]);
-            const uint64_t x = v[q] & wmask(in.w);
-            if (op == I_LDREG || op == I_LDIN) {
-              at(in.dst) = x;
-            } else if (op == I_STREG) {
-              nxt[in.aux] = x;
-              if (A.digest_part) dacc += hmix((uint64_t)in.aux ^ hmix(x));
-            } else {
-              A.outputs[in.aux] = x;
-            }
-          }
-        }
-      }
-    };
     if (STAGED) {
-      // the next chunk's first instruction is read while this one runs, and
-      // the chunk word two ahead
-      uint32_t ch = rfl(ctab[0]), chn = rfl(ctab[1]);
-      uint4 raw = first_instr(ch);
-      while (c < n_ch) {
-        if ((ch >> 24) == I_ALU) {
-          // a run of operator chunks: operand reads, then the next chunk's
-          // first instruction; only the operands are waited for
-          do {
-            const Dec in = decode(raw);
-            uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
-            const uint4 rn = first_instr(chn);
-            const uint32_t w2 = ctab[c + 2];
-            asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
-            const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
-            // lanes past the chunk's end repeat its last instruction on the
-            // same operands, so their store writes the same value to the
-            // same slot and needs no guard
-            at(in.dst) = alu_mixed(present, in.op, in.w, a, b, cc);
-            ++c;
-            ch = chn;
-            chn = rfl(w2);
-            raw = rn;
-            if (TRACE && trace_row) stamp(c);
-            // the chunk table is zero past the last chunk (kind 0), so the
-            // run also ends at the end of the process
-          } while ((ch >> 24) == I_ALU);
-          continue;
-        }
-        const uint4 rn = first_instr(chn);
-        const uint32_t w2 = ctab[c + 2];
-        other_chunk(raw, ch);
-        ++c;
-        ch = chn;
-        chn = rfl(w2);
-        raw = rn;
-        if (TRACE && trace_row) stamp(c);
+      for (uint32_t c = 0; c < c_ops; ++c) {
+        const uint64_t w = rfl64(ctab[c]);
+        plain_wide_chunk(A, C, Is, w, first_instr(w), lane, base);
+        if (TRACE && trace_row) stamp(c + 1);
+      }
+      // the next chunk's instruction and the chunk word after it are read
+      // while a chunk runs
+      uint64_t cw = rfl64(ctab[c_ops]), cwn = ctab[c_ops + 1];
+      uint64_t ins = first_instr(cw);
+      for (uint32_t c = c_ops; c < c_st; ++c) {
+        const uint64_t nins = first_instr(cwn);
+        const uint64_t cwnn = ctab[c + 2];
+        plain_op_level_chunk(A, C, cw, ins, lane, base);
+        cw = rfl64(cwn);
+        cwn = cwnn;
+        ins = nins;
+        if (TRACE && trace_row) stamp(c + 1);
       }
     } else {
-      // instructions from global memory: kWaveSlots slots hold the first
-      // instructions of chunks c .. c + kWaveSlots - 1; a chunk decodes its
-      // slot and refills it with chunk c + kWaveSlots's, so every load has
-      // kWaveSlots chunks' time to land.  The loop is unrolled by kWaveSlots
-      // so that no slot is ever copied while its load is in flight (a copy
-      // would wait for it at once).  cw holds the wave-uniform chunk words
-      // c .. c + kWaveSlots.
-      constexpr uint32_t K = kWaveSlots;
-      static_assert(K >= 2 && K <= 4, "two to four slots");
-      uint32_t cw[K + 1];
+      // the first group of operator chunks, fetched before the leaf level.
+      // The chunk words of a group stay in vector registers (every lane
+      // holds the same value); a scalar copy is taken where it is used.
+      uint64_t cw[kGroup], ins[kGroup];
 #pragma unroll
-      for (uint32_t k = 0; k <= K; ++k) cw[k] = rfl(ctab[k]);
-      uint4 s0 = first_instr(cw[0]), s1 = first_instr(cw[1]);
-      uint4 s2 = K > 2 ? first_instr(cw[2]) : uint4{0, 0, 0, 0};
-      uint4 s3 = K > 3 ? first_instr(cw[3]) : uint4{0, 0, 0, 0};
-      auto one = [&](uint4& slot) {
-        const uint32_t wn = ctab[c + K + 1];
-        const uint32_t ch = cw[0];
-        if ((ch >> 24) == I_ALU) {
-          const Dec in = decode(slot);
-          uint64_t a = at(in.a), b = at(in.b), cc = at(in.c);
-          slot = first_instr(cw[K]);
-          asm volatile("; operands of a mixed chunk ready" : "+v"(a), "+v"(b), "+v"(cc));
-          const uint32_t present = __builtin_amdgcn_readfirstlane(in.aux);
-          // unguarded store: lanes past the chunk's end repeat its last
-          // instruction (same operands, same slot, same value)
-          at(in.dst) = alu_mixed(present, in.op, in.w, a, b, cc);
-        } else {
-          const uint4 raw = slot;
-          slot = first_instr(cw[K]);
-          other_chunk(raw, ch);
-        }
-        ++c;
+      for (uint32_t k = 0; k < kGroup; ++k) {
+        cw[k] = ctab[c_ops + k];
+        ins[k] = first_instr(cw[k]);
+      }
+      for (uint32_t c = 0; c < c_ops; ++c) {
+        const uint64_t w = rfl64(ctab[c]);
+        plain_wide_chunk(A, C, Is, w, first_instr(w), lane, base);
+        if (TRACE && trace_row) stamp(c + 1);
+      }
+      for (uint32_t c = c_ops; c < c_st; c += kGroup) {
+        uint64_t nw[kGroup], nins[kGroup];
 #pragma unroll
-        for (uint32_t k = 0; k < K; ++k) cw[k] = cw[k + 1];
-        cw[K] = rfl(wn);
-        if (TRACE && trace_row) stamp(c);
-      };
-      while (c < n_ch) {
-        one(s0);
-        if (c >= n_ch) break;
-        one(s1);
-        if (c >= n_ch) break;
-        if constexpr (K > 2) {
-          one(s2);
-          if (c >= n_ch) break;
+        for (uint32_t k = 0; k < kGroup; ++k) {
+          nw[k] = ctab[c + kGroup + k];
+          nins[k] = first_instr(nw[k]);
         }
-        if constexpr (K > 3) {
-          one(s3);
-          if (c >= n_ch) break;
+#pragma unroll
+        for (uint32_t k = 0; k < kGroup; ++k) {
+          if (c + k < c_st) {
+            plain_op_level_chunk(A, C, rfl64(cw[k]), ins[k], lane, base);
+            if (TRACE && trace_row) stamp(c + k + 1);
+          }
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kGroup; ++k) {
+          cw[k] = nw[k];
+          ins[k] = nins[k];
         }
       }
     }
-    if (lane == 0) {
-      for (uint32_t k = 0; k < pp.n_wp; ++k) {
-        const Dec in = decode(Is[pp.n_instr + k]);
-        if (at(in.a) != 0) {
-          const uint32_t m = in.aux;
-          const uint64_t depth = A.mem_depth[m], av = at(in.b);
-          const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
-          A.mem[A.mem_off[m] + addr] = at(in.c) & wmask(in.w);
-        }
-      }
+    for (uint32_t c = c_st; c < n_ch; ++c) {
+      const uint64_t w = rfl64(ctab[c]);
+      plain_wide_chunk(A, C, Is, w, first_instr(w), lane, base);
+      if (TRACE && trace_row) stamp(c + 1);
     }
+    if (lane == 0) plain_commit(A, Is, pp, base);
     if (A.digest_part) {
+      uint64_t dacc = C.dacc;
       for (int off = 32; off > 0; off >>= 1) dacc += __shfl_xor(dacc, off);
-      const uint64_t k = cyc - A.digest_first;
+      const uint64_t k = C.cyc - A.digest_first;
       if (lane == 0 && k < A.digest_max) A.digest_part[k * gridDim.x + blockIdx.x] = dacc;
     }
     if (trace_row && lane == 0) trace_row[A.trace_stride - 2] = __builtin_amdgcn_s_memrealtime();
     if (PERSISTENT) {
       if (gridDim.x > 1) {
-        if (!grid_barrier(A.flags, A.error, gridDim.x, A.epoch0 + t + 1, &abort_flag)) return;
+        if (!grid_barrier(A.flags, A.error, gridDim.x, A.epoch0 + t + 1, abort_flag)) return;
       } else {
         asm volatile("" ::: "memory");
       }
+    } else {
+      asm volatile("" ::: "memory");
     }
     if (trace_row && lane == 0) trace_row[A.trace_stride - 1] = __builtin_amdgcn_s_memrealtime();
   }
 }
 
-__global__ void __launch_bounds__(64) plain_wave_persistent(PlainArgs A) { plain_wave_body<true, true, false>(A); }
-__global__ void __launch_bounds__(64) plain_wave_cycle(PlainArgs A) { plain_wave_body<false, true, false>(A); }
-__global__ void __launch_bounds__(64) plain_wave_persistent_g(PlainArgs A) { plain_wave_body<true, false, false>(A); }
-__global__ void __launch_bounds__(64) plain_wave_cycle_g(PlainArgs A) { plain_wave_body<false, false, false>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_persistent(PlainArgs A) { plain_wave_body<true, true, false>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_cycle(PlainArgs A) { plain_wave_body<false, true, false>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_persistent_g(PlainArgs A) { plain_wave_body<true, false, false>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_cycle_g(PlainArgs A) { plain_wave_body<false, false, false>(A); }
 // the same with phase timestamps (a sim with tracing enabled): the untraced
 // kernels carry no per-chunk test for it
-__global__ void __launch_bounds__(64) plain_wave_persistent_trace(PlainArgs A) { plain_wave_body<true, true, true>(A); }
-__global__ void __launch_bounds__(64) plain_wave_cycle_trace(PlainArgs A) { plain_wave_body<false, true, true>(A); }
-__global__ void __launch_bounds__(64) plain_wave_persistent_g_trace(PlainArgs A) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_persistent_trace(PlainArgs A) { plain_wave_body<true, true, true>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_cycle_trace(PlainArgs A) { plain_wave_body<false, true, true>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_persistent_g_trace(PlainArgs A) {
   plain_wave_body<true, false, true>(A);
 }
-__global__ void __launch_bounds__(64) plain_wave_cycle_g_trace(PlainArgs A) { plain_wave_body<false, false, true>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_cycle_g_trace(PlainArgs A) { plain_wave_body<false, false, true>(A); }
 
 __global__ void __launch_bounds__(1024) plain_persistent(PlainArgs A) { plain_body<true, true>(A); }
 __global__ void __launch_bounds__(1024) plain_cycle(PlainArgs A) { plain_body<false, true>(A); }

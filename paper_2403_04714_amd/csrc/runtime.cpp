@@ -75,11 +75,9 @@ extern "C" int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_byt
 // ------------------------------------------------------------------- design
 static constexpr uint32_t kDefaultLds = 160 * 1024;
 static constexpr uint32_t kStaticLds = 1024;     // abort flag, reduction scratch
-// u32 entries of the one-wave kernel's LDS chunk table: every chunk of the
-// largest process, three zero entries for the words it reads ahead, rounded
-// up to a multiple of 4 so that the staged instructions after it stay
-// 16-byte aligned
-static uint32_t wave_ctab_words(const fsim_design* d) { return (d->max_chunks + fsim::kWaveSlots + 1 + 3) & ~3u; }
+// u64 entries of the one-wave kernel's LDS chunk table: every chunk of the
+// largest process and the zero entries of the two groups it reads ahead
+static uint32_t wave_ctab_words(const fsim_design* d) { return d->max_chunks + 2 * fsim::kGroup; }
 
 template <class T>
 static int upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
@@ -103,9 +101,10 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   const uint32_t lds = ctx ? ctx->lds_bytes : kDefaultLds;
   const uint32_t max_slots = (lds - kStaticLds) / 8;
   const uint32_t default_target = ctx ? ctx->n_cus : 256;
-  // default node cap of a process: its slots (8 B per node) and its staged
-  // instructions (16 B each, about 1.25 per node counting the stores) fit in
-  // LDS together, so every process runs from LDS-staged instructions
+  // default node cap of a process: its slots (at most 8 B per node) and its
+  // staged instructions (8 B each, about 1.25 per node counting the stores)
+  // fit in LDS together with room to spare, so every process can run from
+  // LDS-staged instructions
   const uint32_t default_nodes = std::min<uint32_t>((lds - kStaticLds) / 28, 0xFFFE);
   s = fsim::partition_design(d, part, o, default_target, default_nodes);
   if (s.code == FSIM_E_CAPACITY && o.max_process_nodes == 0 && !part) {
@@ -117,7 +116,7 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
       s = fsim::partition_design(d, part, o, default_target, 1u << 30);
   }
   if (!s.ok()) return fail(s);
-  s = fsim::encode_plain(d, std::min<uint32_t>(max_slots, 0xFFFE));
+  s = fsim::encode_plain(d, std::min<uint32_t>(2 * max_slots, fsim::kMaxPlainUnits));
   if (s.code == FSIM_E_CAPACITY) {
     // the design still loads: the batched form has no such limit, and a
     // plain sim asked for later reports this error
@@ -133,7 +132,9 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   dz->max_proc_instr = d.plain_max_instr;
   dz->max_lvls = d.max_plain_lvls;
   dz->max_chunks = d.plain_max_chunks;
-  dz->slot_words = (d.plain_max_slots + 1) & ~1u;
+  // 4-byte units as u64 words, and one unit to spare: a narrow value's
+  // operand read takes 8 bytes (the upper half is dropped)
+  dz->slot_words = d.plain_max_slots / 2 + 1;
   d.compile_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   struct fsim_design_info& I = dz->info;
   I.n_nodes = d.N;
@@ -148,8 +149,7 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   I.dup_process = d.n_live_ops ? (double)d.sum_process_ops / (double)d.n_live_ops : 1.0;
   I.max_fiber_cost = d.max_fiber_cost;
   I.max_process_cost = d.max_process_cost;
-  I.program_bytes = d.plain_instr.size() * sizeof(fsim::Instr) + d.plain_levels.size() * 4 +
-                    d.plain_chunks.size() * 4 +
+  I.program_bytes = d.plain_instr.size() * 8 + d.plain_levels.size() * 4 + d.plain_chunks.size() * 8 +
                     d.plain_procs.size() * sizeof(fsim::PlainProc) + d.consts.size() * 8;
   I.max_process_levels = d.max_process_levels;
   I.max_process_nodes = d.max_process_nodes;
@@ -170,6 +170,11 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
     if (d.M == 0) moff.clear();
     if ((rc = upload(dz->mem_off, moff, st))) return rc;
     if ((rc = upload(dz->mem_depth, d.mem_depth, st))) return rc;
+    // per memory, floor((2^64 - 1) / depth): the plain kernel reduces an
+    // address mod depth with it, without a division
+    std::vector<uint64_t> magic(d.M);
+    for (uint32_t m = 0; m < d.M; ++m) magic[m] = ~0ull / d.mem_depth[m];
+    if ((rc = upload(dz->mem_magic, magic, st))) return rc;
     if ((rc = upload(dz->in_width, d.in_width, st))) return rc;
     HIP_TRY(hipStreamSynchronize(st));
   }
@@ -418,34 +423,19 @@ extern "C" int fsim_sim_create(fsim_design* d, uint32_t n_instances, void* works
   s->graph_cycles = o.graph_cycles ? o.graph_cycles : 64;
   if (s->graph_cycles % 2) s->graph_cycles++;      // keeps the state parity of the base cycle even
   HIP_TRY(hipSetDevice(d->ctx->device));
-  // LDS: slots, plus the process's instructions when they fit
+  // LDS: the value slots; the one-wave kernel adds its chunk table; the
+  // process's instructions follow when they are staged (and fit)
   const size_t lds_limit = d->ctx->lds_bytes - kStaticLds;
-  // slots, then (when they fit) the process's instructions, then the level table
-  const size_t lvl_bytes = ((size_t)d->max_lvls + 1) * 4 + (size_t)d->max_chunks * 4;
   if (o.stage > FSIM_STAGE_GLOBAL) return fail(FSIM_E_ARG, "unknown stage mode");
-  size_t lds = (size_t)d->slot_words * 8 + lvl_bytes;
-  const bool fits = lds + (size_t)d->max_proc_instr * sizeof(fsim::Instr) <= lds_limit;
+  s->single_wave = s->threads == 64;
+  const size_t base = (size_t)d->slot_words * 8 + (s->single_wave ? (size_t)wave_ctab_words(d) * 8 : 0);
+  const size_t instr = (size_t)d->max_proc_instr * 8;
+  const bool fits = base + instr <= lds_limit;
   if (o.stage == FSIM_STAGE_LDS && !fits)
     return fail(FSIM_E_CAPACITY, "plain form: a process's instructions do not fit in LDS beside its slots");
-  if (fits && o.stage != FSIM_STAGE_GLOBAL) {
-    s->stage_instr = true;
-    lds += (size_t)d->max_proc_instr * sizeof(fsim::Instr);
-  }
+  s->stage_instr = fits && o.stage != FSIM_STAGE_GLOBAL;
+  const size_t lds = base + (s->stage_instr ? instr : 0);
   if (lds > lds_limit) return fail(FSIM_E_CAPACITY, "process does not fit in LDS");
-  // one wave per process: the flat chunk loop; its LDS holds the slots, the
-  // chunk table and, when staged, the instructions
-  s->single_wave = s->threads == 64 && d->max_chunks <= 256;
-  if (s->single_wave) {
-    const size_t base = (size_t)d->slot_words * 8 + (size_t)wave_ctab_words(d) * 4;
-    const size_t instr = (size_t)d->max_proc_instr * sizeof(fsim::Instr);
-    if (s->stage_instr && base + instr > lds_limit) {
-      if (o.stage == FSIM_STAGE_LDS)
-        return fail(FSIM_E_CAPACITY, "plain form: a process's instructions do not fit in LDS beside its slots");
-      s->stage_instr = false;
-    }
-    lds = base + (s->stage_instr ? instr : 0);
-    if (lds > lds_limit) return fail(FSIM_E_CAPACITY, "process does not fit in LDS");
-  }
   s->lds_bytes = lds;
   if (s->launch == FSIM_LAUNCH_PERSISTENT) {
     int b = 0;
@@ -506,9 +496,9 @@ extern "C" int fsim_set_inputs(fsim_sim* s, uint64_t first_cycle, uint32_t n_cyc
 static fsim::PlainArgs plain_args(fsim_sim* s) {
   const fsim_design* dd = s->d;
   fsim::PlainArgs a{};
-  a.instr = (const fsim::Instr*)dd->instr.p;
+  a.code = (const uint64_t*)dd->instr.p;
   a.levels = (const uint32_t*)dd->levels.p;
-  a.chunks = (const uint32_t*)dd->chunks.p;
+  a.chunks = (const uint64_t*)dd->chunks.p;
   a.procs = (const fsim::PlainProc*)dd->procs.p;
   a.consts = (const uint64_t*)dd->consts.p;
   a.state = s->state;
@@ -516,6 +506,7 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   a.mem = s->mem;
   a.mem_off = (const uint64_t*)dd->mem_off.p;
   a.mem_depth = (const uint32_t*)dd->mem_depth.p;
+  a.mem_magic = (const uint64_t*)dd->mem_magic.p;
   a.in_width = (const uint8_t*)dd->in_width.p;
   a.in_keys = s->keys;
   a.in_vals = s->explicit_inputs ? (const uint64_t*)s->in_vals.p : nullptr;
@@ -536,7 +527,6 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   a.slot_words = dd->slot_words;
   a.ctab_words = wave_ctab_words(dd);
   a.instr_words = dd->max_proc_instr;
-  a.chunk_words = dd->max_chunks;
   a.single_wave = s->single_wave ? 1 : 0;
   a.cycle_ptr = nullptr;
   return a;

@@ -126,8 +126,8 @@ def test_core_full_size_2000_cycles(F, ctx):
 
 @pytest.mark.parametrize("launch", [1, 2, 3])
 def test_single_wave_instructions_from_global(F, ctx, launch):
-    """The one-wave kernel reading its instructions from global memory (two
-    chunks ahead) instead of an LDS copy."""
+    """The one-wave kernel reading its instructions from global memory (a
+    group of chunks ahead) instead of an LDS copy."""
     run_both(F, ctx, g.gen_tiny(7), 600, 0, 9, launch=launch, threads=64, chunks=(1, 130, None), stage=2)
 
 
