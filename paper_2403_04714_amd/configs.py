@@ -66,7 +66,7 @@ LAUNCH_NAMES = {F.LAUNCH_PERSISTENT: "persistent", F.LAUNCH_PER_CYCLE: "per-cycl
 STAGE_NAMES = {F.STAGE_AUTO: "auto", F.STAGE_LDS: "staged in LDS", F.STAGE_GLOBAL: "from global memory"}
 
 # the 48-tile SoC, one instance: the headline
-SOC48_PLAIN = Plain("soc48", F.PACK_HYPER, 8192, stage=F.STAGE_GLOBAL)
+SOC48_PLAIN = Plain("soc48", F.PACK_HYPER, 4096, stage=F.STAGE_GLOBAL)
 # the 48-tile SoC, 64 instances
 SOC48_BATCHED = Batched("soc48", 64, F.PACK_HYPER, 32768)
 # the single core, one instance

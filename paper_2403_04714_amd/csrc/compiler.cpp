@@ -886,36 +886,117 @@ constexpr size_t kStoreFlush = 256;
 
 }  // namespace
 
+// Operator steps of one plain-form process, by list scheduling: a step
+// holds at most 64 operators and 64 memory reads, every one of them after the
+// steps of its operands, so a step is one chunk of each kind.  Ready
+// operators go to the earliest step with room, the longest remaining path
+// first; a process takes max(depth, operators / 64) steps or close to it
+// instead of one chunk per level and per 64 operators of a level.  Sets
+// loc[x] (0 for leaves and constants, 1..K for operators); returns K.
+struct StepScratch {
+  explicit StepScratch(size_t n) : lid(n, UINT32_MAX) {}
+  std::vector<uint32_t> lid;                 // node -> index among the process's operators
+  std::vector<uint32_t> ops, height, indeg, succ_off, succ, take;
+  std::vector<uint64_t> heap, heap_rd;
+};
+
+static uint32_t steps_of(const Design& d, uint32_t lo, uint32_t hi, std::vector<uint32_t>& loc, StepScratch& S) {
+  auto is_op = [&](uint32_t x) { return d.op[x] >= FSIM_OP_MEMRD; };
+  S.ops.clear();
+  for (uint32_t i = lo; i < hi; ++i) {
+    const uint32_t x = d.proc_nodes[i];
+    if (is_op(x)) { S.lid[x] = (uint32_t)S.ops.size(); S.ops.push_back(x); }
+    else loc[x] = 0;
+  }
+  const uint32_t n = (uint32_t)S.ops.size();
+  S.height.assign(n, 0);
+  S.indeg.assign(n, 0);
+  S.succ_off.assign(n + 1, 0);
+  // the process's nodes are in level order, so a reverse pass sees every
+  // user of an operator before the operator
+  for (uint32_t k = n; k-- > 0;) {
+    const uint32_t x = S.ops[k];
+    for (int a = 0; a < arity(d.op[x]); ++a) {
+      const uint32_t y = d.arg[3ull * x + a];
+      if (!is_op(y)) continue;
+      S.height[S.lid[y]] = std::max(S.height[S.lid[y]], S.height[k] + 1);
+      S.indeg[k]++;
+      S.succ_off[S.lid[y] + 1]++;
+    }
+  }
+  for (uint32_t k = 0; k < n; ++k) S.succ_off[k + 1] += S.succ_off[k];
+  S.succ.assign(S.succ_off[n], 0);
+  {
+    std::vector<uint32_t> f(S.succ_off.begin(), S.succ_off.end() - 1);
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint32_t x = S.ops[k];
+      for (int a = 0; a < arity(d.op[x]); ++a) {
+        const uint32_t y = d.arg[3ull * x + a];
+        if (is_op(y)) S.succ[f[S.lid[y]]++] = k;
+      }
+    }
+  }
+  // max-heaps on (height, lower index first), operators and memory reads
+  auto key = [&](uint32_t k) { return ((uint64_t)S.height[k] << 32) | (uint32_t)~k; };
+  auto push = [&](uint32_t k) {
+    std::vector<uint64_t>& h = d.op[S.ops[k]] == FSIM_OP_MEMRD ? S.heap_rd : S.heap;
+    h.push_back(key(k));
+    std::push_heap(h.begin(), h.end());
+  };
+  S.heap.clear();
+  S.heap_rd.clear();
+  for (uint32_t k = 0; k < n; ++k)
+    if (S.indeg[k] == 0) push(k);
+  uint32_t step = 0, done = 0;
+  while (done < n) {
+    ++step;
+    S.take.clear();
+    for (std::vector<uint64_t>* h : {&S.heap, &S.heap_rd})
+      for (uint32_t c = 0; c < 64 && !h->empty(); ++c) {
+        std::pop_heap(h->begin(), h->end());
+        S.take.push_back(~(uint32_t)h->back());
+        h->pop_back();
+      }
+    for (uint32_t k : S.take) {
+      loc[S.ops[k]] = step;
+      done++;
+      for (uint32_t e = S.succ_off[k]; e < S.succ_off[k + 1]; ++e)
+        if (--S.indeg[S.succ[e]] == 0) push(S.succ[e]);
+    }
+  }
+  for (uint32_t x : S.ops) S.lid[x] = UINT32_MAX;
+  return step;
+}
+
 Status encode_plain(Design& d, uint32_t max_units) {
   phase("process node lists");
   d.plain_procs.assign(d.P, PlainProc{});
   d.plain_levels.clear();
   d.plain_instr.clear();
   d.plain_chunks.clear();
-  d.consts.clear();
   d.plain_max_slots = 0;
   d.plain_max_instr = 0;
   d.plain_max_chunks = 0;
   d.max_plain_lvls = 0;
   std::vector<uint32_t> unit(d.N, UINT32_MAX), lpos(d.N, 0), loc(d.N, 0);
-  std::vector<uint32_t> lv_start;                       // per local level: first index into the node list
+  std::vector<uint8_t> zx(d.N, 0);                      // narrow value kept zero-extended in two units
+  std::vector<uint32_t> lv_start;                       // per local level: first index into ord
+  std::vector<uint32_t> ord;                            // the process's nodes by local level
+  StepScratch sched(d.N);
   std::vector<std::vector<uint32_t>> flush;             // per local level: sinks stored right after it
   std::vector<std::pair<uint32_t, uint32_t>> by_last;
   UnitAlloc alloc;
   auto narrow = [&](uint32_t x) { return d.width[x] <= 32; };
   for (uint32_t p = 0; p < d.P; ++p) {
     const uint32_t lo = d.proc_off[p], hi = d.proc_off[p + 1];
-    // ---- local levels: 0 holds the leaves, 1..K the operator levels of
-    // this process in order (empty levels dropped)
-    lv_start.clear();
-    lv_start.push_back(lo);
-    for (uint32_t i = lo; i < hi; ++i) {
-      const uint32_t x = d.proc_nodes[i];
-      if (d.level[x] > 0 && (i == lo || d.level[d.proc_nodes[i - 1]] != d.level[x])) lv_start.push_back(i);
-      loc[x] = (uint32_t)lv_start.size() - 1;
-    }
-    const uint32_t K = (uint32_t)lv_start.size() - 1;
-    lv_start.push_back(hi);
+    // ---- local levels: 0 holds the leaves and constants, 1..K the steps of
+    // the operators (steps_of); ord lists the nodes by level
+    const uint32_t K = steps_of(d, lo, hi, loc, sched);
+    ord.assign(d.proc_nodes.begin() + lo, d.proc_nodes.begin() + hi);
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return loc[a] < loc[b]; });
+    lv_start.assign(K + 2, 0);
+    for (uint32_t x : ord) lv_start[loc[x] + 1]++;
+    for (uint32_t j = 0; j <= K; ++j) lv_start[j + 1] += lv_start[j];
     // ---- where each register and output sink is stored: with the sinks of
     // its level and earlier ones once kStoreFlush are pending, else in the
     // final store level after level K
@@ -957,25 +1038,59 @@ Status encode_plain(Design& d, uint32_t max_units) {
         for (uint32_t y : {d.wp_en[q], d.wp_addr[q], d.wp_data[q]}) lpos[y] = 2 * K + 2;
       }
     }
+    // ---- which narrow values are kept zero-extended (two units): those
+    // read by an instruction whose result depends on their upper half.  A
+    // narrow value in one unit is read as 8 bytes whose upper half belongs
+    // to another value; that is harmless where only the low 32 bits of the
+    // operand reach a result of at most 32 bits (bitwise operators, adds,
+    // subtracts, multiplies, the shifted operand of a left shift, the data
+    // inputs of a multiplexer) and for stores of at most 32 bits.
+    auto need_zext = [&](uint32_t y) { if (narrow(y)) zx[y] = 1; };
+    for (uint32_t x : ord) {
+      const uint8_t op = d.op[x];
+      if (op < FSIM_OP_MEMRD) continue;
+      const bool small = d.width[x] <= 32;
+      for (int k = 0; k < arity(op); ++k) {
+        const uint32_t y = d.arg[3ull * x + k];
+        bool tolerant;
+        switch (op) {
+          case FSIM_OP_AND: case FSIM_OP_OR: case FSIM_OP_XOR: case FSIM_OP_NOT:
+          case FSIM_OP_ADD: case FSIM_OP_SUB: case FSIM_OP_MUL: tolerant = small; break;
+          case FSIM_OP_SHL: tolerant = small && k == 0; break;
+          case FSIM_OP_MUX: tolerant = small && k > 0; break;
+          default: tolerant = false;   // SHR, EQ, LT, the address of a memory read
+        }
+        if (!tolerant) need_zext(y);
+      }
+    }
+    for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
+      const uint32_t s = d.psinks[k];
+      if (s < d.R) {
+        if (d.reg_width[s] > 32) need_zext(d.reg_next[s]);
+      } else if (s < d.R + d.W) {
+        const uint32_t q = s - d.R;
+        for (uint32_t y : {d.wp_en[q], d.wp_addr[q], d.wp_data[q]}) need_zext(y);
+      }
+    }
+    auto one = [&](uint32_t x) { return narrow(x) && !zx[x]; };
     // ---- units: constants first (loaded once per launch, never released),
     // then every value in order of definition, after releasing the values
     // whose last read comes before it
     alloc.reset(kPlainUnitBase);
-    for (uint32_t i = lo; i < hi; ++i)
-      if (d.op[d.proc_nodes[i]] == FSIM_OP_CONST) unit[d.proc_nodes[i]] = alloc.take(!narrow(d.proc_nodes[i]));
+    for (uint32_t x : ord)
+      if (d.op[x] == FSIM_OP_CONST) unit[x] = alloc.take(!one(x));
     by_last.clear();
-    for (uint32_t i = lo; i < hi; ++i)
-      if (d.op[d.proc_nodes[i]] != FSIM_OP_CONST) by_last.push_back({lpos[d.proc_nodes[i]], d.proc_nodes[i]});
+    for (uint32_t x : ord)
+      if (d.op[x] != FSIM_OP_CONST) by_last.push_back({lpos[x], x});
     std::sort(by_last.begin(), by_last.end());
     size_t rel = 0;
-    for (uint32_t i = lo; i < hi; ++i) {
-      const uint32_t x = d.proc_nodes[i];
+    for (uint32_t x : ord) {
       if (d.op[x] == FSIM_OP_CONST) continue;
       while (rel < by_last.size() && by_last[rel].first < 2 * loc[x]) {
         const uint32_t y = by_last[rel++].second;
-        alloc.give(unit[y], !narrow(y));
+        alloc.give(unit[y], !one(y));
       }
-      unit[x] = alloc.take(!narrow(x));
+      unit[x] = alloc.take(!one(x));
     }
     const uint32_t n = alloc.top();
     if (n > max_units || n > kMaxPlainUnits)
@@ -983,26 +1098,25 @@ Status encode_plain(Design& d, uint32_t max_units) {
                          fmt("process %llu needs %llu LDS units of live values; use more processes", p, n));
     PlainProc& pp = d.plain_procs[p];
     pp.n_slots = n;
-    // ---- constant prologue
+    // ---- constant prologue: destination word, value
     pp.const_off = (uint32_t)d.plain_instr.size();
     for (uint32_t i = lo; i < hi; ++i) {
       uint32_t x = d.proc_nodes[i];
       if (d.op[x] != FSIM_OP_CONST) continue;
-      uint64_t v = d.imm[x] & (~0ull >> (64 - d.width[x]));
-      d.plain_instr.push_back(plain_index(d.width[x], unit[x], d.consts.size(), narrow(x)));
-      d.consts.push_back(v);
+      d.plain_instr.push_back(plain_index(d.width[x], unit[x], 0, one(x)));
+      d.plain_instr.push_back(d.imm[x] & (~0ull >> (64 - d.width[x])));
     }
-    pp.n_consts = (uint32_t)d.plain_instr.size() - pp.const_off;
+    pp.n_consts = ((uint32_t)d.plain_instr.size() - pp.const_off) / 2;
     pp.instr_off = (uint32_t)d.plain_instr.size();
     pp.chunk_off = (uint32_t)d.plain_chunks.size();
     pp.lvl_off = (uint32_t)d.plain_levels.size();
     // one level from its instruction words, each with its kind and whether
-    // its sources and its result are narrow; operators of any opcode share
-    // I_ALU chunks, other kinds get chunks of their own
+    // its result takes one unit; operators of any opcode share I_ALU chunks,
+    // other kinds get chunks of their own
     struct PI {
       uint64_t word;
       uint32_t kind;
-      bool in_narrow, out_narrow;
+      bool out_narrow;
     };
     std::vector<PI> ins;
     uint32_t n_lvls = 0;
@@ -1021,10 +1135,9 @@ Status encode_plain(Design& d, uint32_t max_units) {
         size_t e = k;
         while (e < ins.size() && e - k < cap && ins[e].kind == kk) ++e;
         const uint32_t start = (uint32_t)d.plain_instr.size() - pp.instr_off;
-        uint32_t present = 0, flags = kAllNarrowIn | kAllNarrowOut | kAllWideOut;
+        uint32_t present = 0, flags = kAllNarrowOut | kAllWideOut;
         for (size_t j = k; j < e; ++j) {
           if (kk == I_ALU) present |= 1u << (ins[j].word & 15);
-          if (!ins[j].in_narrow) flags &= ~kAllNarrowIn;
           if (!ins[j].out_narrow) flags &= ~kAllNarrowOut;
           if (ins[j].out_narrow) flags &= ~kAllWideOut;
           d.plain_instr.push_back(ins[j].word);
@@ -1039,48 +1152,48 @@ Status encode_plain(Design& d, uint32_t max_units) {
       for (uint32_t s : sinks) {
         const uint32_t x = root(s);
         if (s < d.R)
-          ins.push_back({plain_index(d.reg_width[s], unit[x], s, narrow(x)), I_STREG, narrow(x), true});
+          ins.push_back({plain_index(d.reg_width[s], unit[x], s), I_STREG, true});
         else
-          ins.push_back({plain_index(d.width[x], unit[x], s - d.R - d.W, narrow(x)), I_STOUT, narrow(x), true});
+          ins.push_back({plain_index(d.width[x], unit[x], s - d.R - d.W) | 1, I_STOUT, true});
       }
       emit_level();
     };
     // level 0: register and input loads (always present, possibly empty)
     for (uint32_t i = lv_start[0]; i < lv_start[1]; ++i) {
-      const uint32_t x = d.proc_nodes[i];
+      const uint32_t x = ord[i];
       // field 0's narrow flag gives the destination's size (an input's width
       // also folds in the port's own width)
       if (d.op[x] == FSIM_OP_REG)
-        ins.push_back({plain_index(d.width[x], unit[x], d.imm[x], narrow(x)), I_LDREG, true, narrow(x)});
+        ins.push_back({plain_index(d.width[x], unit[x], d.imm[x], one(x)), I_LDREG, one(x)});
       else if (d.op[x] == FSIM_OP_INPUT)
-        ins.push_back({plain_index(std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]), unit[x], d.imm[x], narrow(x)),
-                       I_LDIN, true, narrow(x)});
+        ins.push_back({plain_index(std::min<uint8_t>(d.width[x], d.in_width[d.imm[x]]), unit[x], d.imm[x], one(x)) | 1,
+                       I_LDIN, one(x)});
     }
     emit_level();
+    pp.n_leaf = (uint32_t)d.plain_instr.size() - pp.instr_off;
     pp.c_ops = (uint32_t)d.plain_chunks.size() - pp.chunk_off;
     in_ops = true;
     for (uint32_t j = 0; j <= K; ++j) {
       if (j > 0) {
         for (uint32_t i = lv_start[j]; i < lv_start[j + 1]; ++i) {
-          const uint32_t x = d.proc_nodes[i];
+          const uint32_t x = ord[i];
           const uint8_t op = d.op[x];
           const uint32_t* a = &d.arg[3ull * x];
           if (op == FSIM_OP_MEMRD) {
-            ins.push_back({plain_word(0, d.width[x], narrow(a[0]) ? 1u : 0u, unit[x], unit[a[0]], d.imm[x] & 0xFFF,
-                                      d.imm[x] >> 12),
-                           I_MEMRD, narrow(a[0]), narrow(x)});
+            ins.push_back({plain_word(0, d.width[x], unit[x], unit[a[0]], d.imm[x] & 0xFFF, d.imm[x] >> 12, one(x)),
+                           I_MEMRD, one(x)});
           } else {
             // an unused operand repeats a
             auto opnd = [&](int k) { return a[k < arity(op) ? k : 0]; };
-            const uint32_t nf = (narrow(opnd(0)) ? 1u : 0u) | (narrow(opnd(1)) ? 2u : 0u) | (narrow(opnd(2)) ? 4u : 0u);
-            ins.push_back({plain_word(op, d.width[x], nf, unit[x], unit[opnd(0)], unit[opnd(1)], unit[opnd(2)]), I_ALU,
-                           nf == 7, narrow(x)});
+            ins.push_back({plain_word(op, d.width[x], unit[x], unit[opnd(0)], unit[opnd(1)], unit[opnd(2)], one(x)),
+                           I_ALU, one(x)});
           }
         }
         emit_level();
       }
       if (j == K) {
         pp.c_st = (uint32_t)d.plain_chunks.size() - pp.chunk_off;
+        pp.st_first = (uint32_t)d.plain_instr.size() - pp.instr_off;
         in_ops = false;
       }
       if (!flush[j].empty() || j == K) emit_stores(flush[j]);
@@ -1100,8 +1213,7 @@ Status encode_plain(Design& d, uint32_t max_units) {
           return Status::err(FSIM_E_CAPACITY, fmt("plain form: memory %llu is past the %llu write-port memories "
                                                   "its encoding holds", d.wp_mem[q], kMaxWportMems));
         const uint32_t en = d.wp_en[q], ad = d.wp_addr[q], da = d.wp_data[q];
-        d.plain_instr.push_back(plain_word(0, d.mem_width[d.wp_mem[q]], (narrow(ad) ? 1u : 0u) | (narrow(da) ? 2u : 0u),
-                                           unit[en], unit[ad], unit[da], d.wp_mem[q], narrow(en)));
+        d.plain_instr.push_back(plain_word(0, d.mem_width[d.wp_mem[q]], unit[en], unit[ad], unit[da], d.wp_mem[q]));
       }
     }
     pp.n_wp = (uint32_t)d.plain_instr.size() - pp.instr_off - pp.n_instr;
@@ -1112,6 +1224,7 @@ Status encode_plain(Design& d, uint32_t max_units) {
     for (uint32_t j = lo; j < hi; ++j) {
       unit[d.proc_nodes[j]] = UINT32_MAX;
       lpos[d.proc_nodes[j]] = 0;
+      zx[d.proc_nodes[j]] = 0;
     }
   }
   phase("encode plain");
@@ -1121,6 +1234,40 @@ Status encode_plain(Design& d, uint32_t max_units) {
     std::sort(ns.begin(), ns.end());
     fprintf(stderr, "fsim compile: plain LDS units per process: p50 %u p90 %u p99 %u max %u\n", ns[ns.size() / 2],
             ns[ns.size() * 9 / 10], ns[ns.size() * 99 / 100], ns.back());
+    uint64_t n_alu = 0, lanes_alu = 0, distinct = 0, all_narrow = 0, narrow_out = 0, n_memrd = 0, n_flush = 0;
+    for (const PlainProc& q : d.plain_procs)
+      for (uint32_t c = q.c_ops; c < q.c_st; ++c) {
+        const uint64_t cw = d.plain_chunks[q.chunk_off + c];
+        const uint32_t kind = (uint32_t)(cw >> 24) & 0xFF, fl = (uint32_t)(cw >> 48);
+        if (kind == I_ALU) {
+          n_alu++;
+          lanes_alu += ((cw >> 16) & 0xFF) + 1;
+          distinct += __builtin_popcount((uint32_t)(cw >> 32) & 0xFFFF);
+          if (fl & kAllWideOut) all_narrow++;
+          if (fl & kAllNarrowOut) narrow_out++;
+        } else if (kind == I_MEMRD) n_memrd++;
+        else n_flush++;
+      }
+    fprintf(stderr, "fsim compile: plain operator chunks %llu: lanes/chunk %.1f, opcodes/chunk %.2f, all results in two units %.1f%%, "
+            "in one unit %.1f%%; memory-read chunks %llu, early store chunks %llu\n", (unsigned long long)n_alu,
+            n_alu ? (double)lanes_alu / n_alu : 0.0, n_alu ? (double)distinct / n_alu : 0.0,
+            n_alu ? 100.0 * all_narrow / n_alu : 0.0, n_alu ? 100.0 * narrow_out / n_alu : 0.0,
+            (unsigned long long)n_memrd, (unsigned long long)n_flush);
+    uint64_t wc = 0, wl = 0, ws = 0, ww = 0, cl = 0, cs = 0;
+    for (const PlainProc& q : d.plain_procs) {
+      wc += 2 * q.n_consts;
+      ww += q.n_wp;
+      for (uint32_t c = 0; c < q.n_chunks; ++c) {
+        const uint64_t cw = d.plain_chunks[q.chunk_off + c];
+        const uint32_t cnt = (uint32_t)((cw >> 16) & 0xFF) + 1;
+        if (c < q.c_ops) { wl += cnt; cl++; }
+        else if (c >= q.c_st) { ws += cnt; cs++; }
+      }
+    }
+    fprintf(stderr, "fsim compile: plain words: consts %llu leaves %llu (%llu chunks) ops+flushes %llu "
+            "final stores %llu (%llu chunks) write ports %llu; chunks %zu\n", (unsigned long long)wc,
+            (unsigned long long)wl, (unsigned long long)cl, (unsigned long long)(d.plain_instr.size() - wc - wl - ws - ww),
+            (unsigned long long)ws, (unsigned long long)cs, (unsigned long long)ww, d.plain_chunks.size());
     for (uint32_t p = 0; p < d.P; ++p)
       if (d.plain_procs[p].n_slots + 64 > ns.back())
         fprintf(stderr, "fsim compile:   process %u: %u units, %u nodes, %u sinks, %u levels, %u chunks\n", p,

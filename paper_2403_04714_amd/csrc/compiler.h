@@ -53,7 +53,6 @@ struct Design {
   std::vector<uint32_t> plain_levels;   // per process: chunk index where each level starts
   std::vector<uint64_t> plain_chunks;   // chunk words (make_chunk)
   std::vector<uint64_t> plain_instr;    // 64-bit instruction words (plain_op, plain_aux, ...)
-  std::vector<uint64_t> consts;         // constant pool (LD_CONST aux index)
   uint32_t plain_max_slots = 0;
   uint32_t plain_max_instr = 0;
   uint32_t plain_max_chunks = 0;

@@ -26,8 +26,9 @@ __device__ __forceinline__ uint64_t wmask(uint32_t w) { return ~0ull >> (64u - w
 // uniform) holds the opcodes that occur in the chunk.  A chunk of a single
 // opcode (most chunks of deep, narrow processes) dispatches once on it with
 // scalar branches and evaluates it alone.  Otherwise each opcode present is
-// evaluated for every lane and kept where it is the lane's own, a few vector
-// instructions per opcode present, without divergent branches.
+// evaluated under an execution mask of the lanes that hold it and written
+// to the result directly (one compare and the operator's own vector
+// instructions; the masks are scalar work).
 __device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uint32_t w, uint64_t a,
                                               uint64_t b, uint64_t c) {
   uint64_t r = 0;
@@ -50,10 +51,10 @@ __device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uin
     }
     return r & wmask(w);
   }
-  // the empty asm keeps each test a real (scalar) branch, so opcodes absent
-  // from the chunk cost two scalar instructions instead of being computed
+  // the outer test is a scalar branch on the chunk's opcode set; the empty
+  // asm inside keeps the inner test a masked region (not a select)
 #define FSIM_MIXED(OPC, EXPR) \
-  if (present & (1u << (OPC))) { asm volatile(""); r = op == (OPC) ? (uint64_t)(EXPR) : r; }
+  if (present & (1u << (OPC))) { asm volatile(""); if (op == (OPC)) { asm volatile(""); r = (uint64_t)(EXPR); } }
   FSIM_MIXED(I_AND, a & b)
   FSIM_MIXED(I_OR, a | b)
   FSIM_MIXED(I_XOR, a ^ b)
@@ -142,10 +143,8 @@ __device__ __forceinline__ uint32_t pw_f1(uint32_t lo, uint32_t hi) {
 }
 __device__ __forceinline__ uint32_t pw_f2(uint32_t hi) { return (hi >> 4) & 0x3FFC; }
 __device__ __forceinline__ uint32_t pw_f3(uint32_t hi) { return (hi >> 16) & 0x3FFC; }
-// narrow flags: field k (1..3) in bit 10 + k of the low half; field 0 in bit
-// 30 of the high half
-__device__ __forceinline__ bool pw_narrow(uint32_t lo, uint32_t k) { return (lo >> (10 + k)) & 1; }
-__device__ __forceinline__ bool pw_narrow0(uint32_t hi) { return (hi >> 30) & 1; }
+// whether the destination in field 0 takes one unit (bit 30 of the high half)
+__device__ __forceinline__ bool pw_one0(uint32_t hi) { return (hi >> 30) & 1; }
 // register, port, output or constant index (bits 26..61)
 __device__ __forceinline__ uint64_t pw_index(uint32_t lo, uint32_t hi) {
   return (((uint64_t)(hi & 0x3FFFFFFFu)) << 6) | (lo >> 26);

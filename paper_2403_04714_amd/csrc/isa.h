@@ -41,7 +41,8 @@ struct Instr {
 };
 static_assert(sizeof(Instr) == 16, "Instr must be 16 bytes");
 
-// Plain form: per process, a constant prologue (run once per launch), then
+// Plain form: per process, a constant prologue (run once per launch: pairs
+// of a destination word and the constant's value), then
 // levels 0..n_lvls-1 (leaf loads, operator levels, the store level).  The
 // instructions of a level are cut into chunks: a chunk of operators (I_ALU)
 // holds up to 64 instructions of any opcodes, one per lane, whose operands
@@ -56,7 +57,7 @@ static_assert(sizeof(Instr) == 16, "Instr must be 16 bytes");
 struct PlainProc {
   uint32_t lvl_off;    // index into the level table: n_lvls + 1 chunk indices
   uint32_t n_lvls;
-  uint32_t const_off;  // prologue instructions
+  uint32_t const_off;  // prologue: n_consts pairs (destination word, value)
   uint32_t n_consts;
   uint32_t instr_off;  // first level instruction
   uint32_t n_instr;    // level instructions; the commit follows them
@@ -66,8 +67,10 @@ struct PlainProc {
   uint32_t n_slots;    // u64 LDS slots used
   uint32_t c_ops;      // first chunk of the operator levels
   uint32_t c_st;       // first chunk of the store level
+  uint32_t n_leaf;     // leaf-load instructions: level instructions [0, n_leaf)
+  uint32_t st_first;   // final-store instructions: level instructions [st_first, n_instr)
 };
-static_assert(sizeof(PlainProc) == 48, "PlainProc must be 48 bytes");
+static_assert(sizeof(PlainProc) == 56, "PlainProc must be 56 bytes");
 
 // A plain-form instruction is one 64-bit word.  Values live in LDS in
 // 4-byte units: a value of at most 32 bits takes one unit, a wider one two
@@ -84,8 +87,9 @@ static_assert(sizeof(PlainProc) == 48, "PlainProc must be 48 bytes");
 // Operators: destination, then operands a, b, c in fields 0..3 (an unused
 // operand repeats a).  Leaf loads (LDREG, LDIN) and the prologue (LDCONST):
 // the destination in field 0 (its narrow flag gives the destination's size),
-// the register, port or constant index in bits 26..61.  Stores (STREG, STOUT): the source in field 0, the register or
-// output index in bits 26..61.  MEMRD: destination and address, the memory
+// the register or port index in bits 26..61, and bit 0 set for an input port.
+// Stores (STREG, STOUT): the source in field 0, the register or output index
+// in bits 26..61, and bit 0 set for an output.  MEMRD: destination and address, the memory
 // in bits 38..61.  WPORT: enable, address and data, the memory in bits
 // 50..61.
 constexpr uint32_t kUnitBits = 12;
@@ -94,13 +98,12 @@ constexpr uint32_t kUnitBits = 12;
 constexpr uint32_t kPlainUnitBase = 2;
 constexpr uint32_t kMaxPlainUnits = (1u << kUnitBits) - 1;
 constexpr uint32_t kMaxWportMems = 1u << 12;
-inline uint64_t plain_word(uint32_t op, uint32_t w, uint32_t narrow123, uint64_t f0, uint64_t f1, uint64_t f2,
-                           uint64_t f3, bool narrow0 = false) {
-  return (op & 15) | (uint64_t)w << 4 | (uint64_t)narrow123 << 11 | f0 << 14 | f1 << 26 | f2 << 38 | f3 << 50 |
-         (uint64_t)narrow0 << 62;
+inline uint64_t plain_word(uint32_t op, uint32_t w, uint64_t f0, uint64_t f1, uint64_t f2, uint64_t f3,
+                           bool one0 = false) {
+  return (op & 15) | (uint64_t)w << 4 | f0 << 14 | f1 << 26 | f2 << 38 | f3 << 50 | (uint64_t)one0 << 62;
 }
-inline uint64_t plain_index(uint32_t w, uint64_t f0, uint64_t index, bool narrow0 = false) {
-  return (uint64_t)w << 4 | f0 << 14 | index << 26 | (uint64_t)narrow0 << 62;
+inline uint64_t plain_index(uint32_t w, uint64_t f0, uint64_t index, bool one0 = false) {
+  return (uint64_t)w << 4 | f0 << 14 | index << 26 | (uint64_t)one0 << 62;
 }
 
 // A chunk word: start (16 bits, relative to the first level instruction) |

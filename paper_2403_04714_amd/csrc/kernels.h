@@ -24,7 +24,6 @@ struct PlainArgs {
   const uint32_t* levels;      // per process: chunk index where each level starts
   const uint64_t* chunks;      // chunk words
   const PlainProc* procs;
-  const uint64_t* consts;
   uint64_t* state;            // [2][R]: cur = cycle & 1
   uint64_t* outputs;          // [O]
   uint64_t* mem;              // all memories, back to back

@@ -42,24 +42,21 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
   return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
 }
 
-// LDS value access by byte offset.  A narrow value (at most 32 bits) is one
-// 4-byte unit and the unit after it belongs to another value, so a read
-// takes 8 bytes and drops the upper half of a narrow value; a wide value is
-// an 8-byte aligned pair.
+// LDS value access by byte offset.  A value is read as 8 bytes.  A value in
+// one 4-byte unit (at most 32 bits, read only where its upper half does not
+// matter) then comes with the next unit, which belongs to another value, as
+// its upper half; a value in two units (wide, or narrow and kept
+// zero-extended) is an 8-byte aligned pair.
 __device__ __forceinline__ uint64_t ld_raw(const char* base, uint32_t off) {
   const uint32_t* p = reinterpret_cast<const uint32_t*>(base + off);
   return (uint64_t)p[0] | ((uint64_t)p[1] << 32);
 }
-__device__ __forceinline__ uint64_t ld_val(const char* base, uint32_t off, bool narrow) {
-  const uint64_t v = ld_raw(base, off);
-  return narrow ? (uint32_t)v : v;
-}
 // A store of either size without a branch: the low half goes to its unit,
-// the high half to the next unit for a wide value and to the spare unit at
-// `trash` (never read as a value) for a narrow one.
-__device__ __forceinline__ void st_val(char* base, uint32_t off, uint64_t v, bool narrow, uint32_t trash) {
+// the high half to the next unit for a two-unit value and to the spare unit
+// at `trash` (never read as a value) for a one-unit one.
+__device__ __forceinline__ void st_val(char* base, uint32_t off, uint64_t v, bool one, uint32_t trash) {
   *reinterpret_cast<uint32_t*>(base + off) = (uint32_t)v;
-  *reinterpret_cast<uint32_t*>(base + (narrow ? trash : off + 4)) = (uint32_t)(v >> 32);
+  *reinterpret_cast<uint32_t*>(base + (one ? trash : off + 4)) = (uint32_t)(v >> 32);
 }
 // the spare unit: the last 4 bytes of the value area
 __device__ __forceinline__ uint32_t trash_off(const PlainArgs& A) { return A.slot_words * 8 - 4; }
@@ -98,7 +95,7 @@ __device__ __forceinline__ void plain_wide_chunk(const PlainArgs& A, PlainCycle&
           v[q] = hmix(A.in_keys[ix] ^ C.cyc);
         }
       } else {
-        v[q] = ld_val(base, pw_f0(lo), pw_narrow0(hi));
+        v[q] = ld_raw(base, pw_f0(lo));
       }
     }
   }
@@ -109,7 +106,7 @@ __device__ __forceinline__ void plain_wide_chunk(const PlainArgs& A, PlainCycle&
       const uint32_t lo = (uint32_t)rq[q], hi = (uint32_t)(rq[q] >> 32);
       const uint64_t x = v[q] & wmask(pw_w(lo));   // LDIN widths fold in the port width
       if (op == I_LDREG || op == I_LDIN) {
-        st_val(base, pw_f0(lo), x, pw_narrow0(hi), trash_off(A));
+        st_val(base, pw_f0(lo), x, pw_one0(hi), trash_off(A));
       } else if (op == I_STREG) {
         const uint64_t r = pw_index(lo, hi);
         C.nxt[r] = x;
@@ -130,24 +127,16 @@ __device__ __forceinline__ void plain_alu_chunk(uint64_t cw, uint64_t raw, char*
   const uint32_t flags = (uint32_t)(cw >> 48);
   uint64_t a = ld_raw(base, pw_f1(lo, hi)), b = ld_raw(base, pw_f2(hi)), c = ld_raw(base, pw_f3(hi));
   asm volatile("; operands of an operator chunk ready" : "+v"(a), "+v"(b), "+v"(c));
-  if (flags & kAllNarrowIn) {
-    a = (uint32_t)a; b = (uint32_t)b; c = (uint32_t)c;
-  } else {
-    if (pw_narrow(lo, 1)) a = (uint32_t)a;
-    if (pw_narrow(lo, 2)) b = (uint32_t)b;
-    if (pw_narrow(lo, 3)) c = (uint32_t)c;
-  }
-  const uint32_t w = pw_w(lo);
-  const uint64_t r = alu_mixed((uint32_t)(cw >> 32), pw_op(lo), w, a, b, c);
+  const uint64_t r = alu_mixed((uint32_t)(cw >> 32), pw_op(lo), pw_w(lo), a, b, c);
   if (flags & kAllNarrowOut) *reinterpret_cast<uint32_t*>(base + pw_f0(lo)) = (uint32_t)r;
   else if (flags & kAllWideOut) *reinterpret_cast<uint64_t*>(base + pw_f0(lo)) = r;
-  else st_val(base, pw_f0(lo), r, w <= 32, trash);
+  else st_val(base, pw_f0(lo), r, pw_one0(hi), trash);
 }
 
 // A memory-read chunk.  Lanes past the chunk's end repeat its last read.
 __device__ __forceinline__ void plain_memrd(const PlainArgs& A, uint64_t raw, char* base) {
   const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
-  const uint64_t addr_v = ld_val(base, pw_f1(lo, hi), pw_narrow(lo, 1));
+  const uint64_t addr_v = ld_raw(base, pw_f1(lo, hi));
   const uint32_t m = pw_mem38(hi);
   // addr_v mod depth without a branch (lanes may read different memories):
   // q = floor(addr_v * magic / 2^64) is at most two below the quotient
@@ -157,7 +146,7 @@ __device__ __forceinline__ void plain_memrd(const PlainArgs& A, uint64_t raw, ch
   addr = addr >= depth ? addr - depth : addr;
   addr = addr >= depth ? addr - depth : addr;
   const uint32_t w = pw_w(lo);
-  st_val(base, pw_f0(lo), A.mem[A.mem_off[m] + addr] & wmask(w), w <= 32, trash_off(A));
+  st_val(base, pw_f0(lo), A.mem[A.mem_off[m] + addr] & wmask(w), pw_one0(hi), trash_off(A));
 }
 
 // Register or output stores written out among the operator levels: one per
@@ -166,7 +155,7 @@ __device__ __forceinline__ void plain_memrd(const PlainArgs& A, uint64_t raw, ch
 __device__ __forceinline__ void plain_store64(const PlainArgs& A, PlainCycle& C, uint64_t cw, uint64_t raw,
                                               uint32_t lane, const char* base) {
   const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
-  const uint64_t x = ld_val(base, pw_f0(lo), pw_narrow0(hi)) & wmask(pw_w(lo));
+  const uint64_t x = ld_raw(base, pw_f0(lo)) & wmask(pw_w(lo));
   const uint64_t ix = pw_index(lo, hi);
   if (((uint32_t)(cw >> 24) & 0xFF) == I_STREG) {
     C.nxt[ix] = x;
@@ -202,22 +191,99 @@ __device__ __forceinline__ void plain_commit(const PlainArgs& A, const uint64_t*
   for (uint32_t k = 0; k < pp.n_wp; ++k) {
     const uint64_t w = Is[pp.n_instr + k];
     const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-    if (ld_val(base, pw_f0(lo), pw_narrow0(hi)) != 0) {
+    if (ld_raw(base, pw_f0(lo)) != 0) {
       const uint32_t m = pw_mem50(hi);
-      const uint64_t depth = A.mem_depth[m], av = ld_val(base, pw_f1(lo, hi), pw_narrow(lo, 1));
+      const uint64_t depth = A.mem_depth[m], av = ld_raw(base, pw_f1(lo, hi));
       const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
-      A.mem[A.mem_off[m] + addr] = ld_val(base, pw_f2(hi), pw_narrow(lo, 2)) & wmask(pw_w(lo));
+      A.mem[A.mem_off[m] + addr] = ld_raw(base, pw_f2(hi)) & wmask(pw_w(lo));
     }
   }
 }
 
 // The constant prologue: every constant into its LDS place, once per launch.
+// A constant is a destination word followed by its value.
 __device__ __forceinline__ void plain_consts(const PlainArgs& A, const PlainProc& pp, uint32_t tid, uint32_t nthr,
                                              char* base) {
   for (uint32_t i = tid; i < pp.n_consts; i += nthr) {
-    const uint64_t w = A.code[pp.const_off + i];
-    const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
-    st_val(base, pw_f0(lo), A.consts[pw_index(lo, hi)], pw_narrow0(hi), trash_off(A));
+    const uint64_t w = A.code[pp.const_off + 2 * i], v = A.code[pp.const_off + 2 * i + 1];
+    st_val(base, pw_f0((uint32_t)w), v, pw_one0((uint32_t)(w >> 32)), trash_off(A));
+  }
+}
+
+// One-wave leaf level, in batches of kLeafQ leaf loads per lane (lane +
+// 64 q): a batch's gathers are issued together, and the next batch's words
+// are fetched while they are in flight.
+constexpr uint32_t kLeafQ = 4;
+__device__ __forceinline__ void leaf_words(const uint64_t* Ig, uint32_t b0, uint32_t n, uint32_t lane,
+                                           uint64_t (&w)[kLeafQ]) {
+#pragma unroll
+  for (uint32_t q = 0; q < kLeafQ; ++q) {
+    const uint32_t i = b0 + lane + 64 * q;
+    w[q] = i < n ? Ig[i] : 0;
+  }
+}
+// `w` holds the first batch's words on entry
+__device__ __forceinline__ void leaf_level(const PlainArgs& A, const PlainCycle& C, const uint64_t* Ig,
+                                           uint64_t (&w)[kLeafQ], uint32_t n, uint32_t lane, char* base) {
+  // inputs: the stimulus hash of the port's key (the key is gathered like a
+  // register), or a row of caller-supplied values
+  const bool expl = A.in_vals != nullptr;
+  const bool in_window = C.cyc >= A.in_first && C.cyc < A.in_first + A.in_count;
+  const uint64_t* const in_src = expl ? (in_window ? A.in_vals + (C.cyc - A.in_first) * A.I : C.cur) : A.in_keys;
+  for (uint32_t b0 = 0; b0 < n; b0 += 64 * kLeafQ) {
+    uint64_t v[kLeafQ];
+    bool any_in = false;
+#pragma unroll
+    for (uint32_t q = 0; q < kLeafQ; ++q) {
+      const uint32_t lo = (uint32_t)w[q], hi = (uint32_t)(w[q] >> 32);
+      const bool live = b0 + lane + 64 * q < n, inp = lo & 1;
+      any_in |= inp && live;
+      v[q] = live ? (inp ? in_src : C.cur)[pw_index(lo, hi)] : 0;
+    }
+    uint64_t wn[kLeafQ];
+    leaf_words(Ig, b0 + 64 * kLeafQ, n, lane, wn);
+    if (__any(any_in)) {
+      if (expl && !in_window && any_in) atomicOr(&A.error[1], 1u);
+#pragma unroll
+      for (uint32_t q = 0; q < kLeafQ; ++q)
+        if ((uint32_t)w[q] & 1) v[q] = expl ? (in_window ? v[q] : 0) : hmix(v[q] ^ C.cyc);
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kLeafQ; ++q) {
+      const uint32_t lo = (uint32_t)w[q], hi = (uint32_t)(w[q] >> 32);
+      // LDIN widths fold in the port width
+      if (b0 + lane + 64 * q < n) st_val(base, pw_f0(lo), v[q] & wmask(pw_w(lo)), pw_one0(hi), trash_off(A));
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kLeafQ; ++q) w[q] = wn[q];
+  }
+}
+
+// One-wave final store level: kStQ store words per lane in flight.
+constexpr uint32_t kStQ = 4;
+__device__ __forceinline__ void final_stores(const PlainArgs& A, PlainCycle& C, const uint64_t* Is, uint32_t first,
+                                             uint32_t n, uint32_t lane, const char* base) {
+  for (uint32_t b0 = first; b0 < n; b0 += 64 * kStQ) {
+    uint64_t w[kStQ];
+#pragma unroll
+    for (uint32_t q = 0; q < kStQ; ++q) {
+      const uint32_t i = b0 + lane + 64 * q;
+      w[q] = i < n ? Is[i] : 0;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kStQ; ++q) {
+      if (b0 + lane + 64 * q < n) {
+        const uint32_t lo = (uint32_t)w[q], hi = (uint32_t)(w[q] >> 32);
+        const uint64_t x = ld_raw(base, pw_f0(lo)) & wmask(pw_w(lo));
+        const uint64_t ix = pw_index(lo, hi);
+        if (lo & 1) {
+          A.outputs[ix] = x;
+        } else {
+          C.nxt[ix] = x;
+          if (A.digest_part) C.dacc += hmix(ix ^ hmix(x));
+        }
+      }
+    }
   }
 }
 
@@ -301,7 +367,9 @@ __device__ void plain_body(const PlainArgs& A) {
 // table (zero past the last chunk) and, when STAGED, a copy of the process's
 // instructions made at launch; otherwise the instructions are read from
 // global memory.  A cycle runs in three phases: the leaf level (register and
-// input loads), the operator levels, the final store level.
+// input loads, kLeafQ per lane in flight, their words always read from
+// global memory), the operator levels, the final store level (kStQ per lane
+// in flight).
 //   STAGED: the operator levels run chunk by chunk, the next chunk's
 //   instruction read from LDS while the current chunk's operands are read.
 //   Otherwise: in groups of kGroup chunks, and when a group starts the first
@@ -322,6 +390,16 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   const uint64_t* const Ig = A.code + pp.instr_off;
   uint64_t* const ctab = lds + A.slot_words;
   uint64_t* const Ist = ctab + A.ctab_words;
+  // set-up in one round trip: the first leaf batch (read from global memory
+  // also when staged), the lane's first chunk word and constant, and the
+  // first staging block are all in flight together; tables longer than 64
+  // entries take more rounds
+  const uint32_t n_leaf = pp.n_leaf, n_ch = pp.n_chunks, n_k = pp.n_consts;
+  uint64_t lw[kLeafQ];
+  leaf_words(Ig, 0, n_leaf, lane, lw);
+  const uint64_t* const K = A.code + pp.const_off;
+  const uint64_t cw0 = lane < n_ch ? A.chunks[pp.chunk_off + lane] : 0;
+  const uint64_t kw0 = lane < n_k ? K[2 * lane] : 0, kv0 = lane < n_k ? K[2 * lane + 1] : 0;
   // staging, eight loads in flight per lane
   for (uint32_t b0 = 0; STAGED && b0 < n_all; b0 += 512) {
     uint64_t t[8];
@@ -337,14 +415,17 @@ __device__ void plain_wave_body(const PlainArgs& A) {
     }
   }
   const uint64_t* const Is = STAGED ? Ist : Ig;
-  plain_consts(A, pp, lane, 64, base);
-  const uint32_t n_ch = pp.n_chunks;
-  for (uint32_t i = lane; i < A.ctab_words; i += 64) ctab[i] = i < n_ch ? A.chunks[pp.chunk_off + i] : 0;
+  if (lane < A.ctab_words) ctab[lane] = cw0;
+  for (uint32_t i = lane + 64; i < A.ctab_words; i += 64) ctab[i] = i < n_ch ? A.chunks[pp.chunk_off + i] : 0;
+  if (lane < n_k) st_val(base, pw_f0((uint32_t)kw0), kv0, pw_one0((uint32_t)(kw0 >> 32)), trash_off(A));
+  for (uint32_t i = lane + 64; i < n_k; i += 64)
+    st_val(base, pw_f0((uint32_t)K[2 * i]), K[2 * i + 1], pw_one0((uint32_t)(K[2 * i] >> 32)), trash_off(A));
   // level starts, for the phase timestamps only
   const uint32_t n_lvls = pp.n_lvls;
   const uint32_t lv_lo = TRACE && lane <= n_lvls ? A.levels[pp.lvl_off + lane] : 0;
+  // one wave: its LDS operations complete in order, so the set-up's stores
+  // need no barrier before the reads below
   if (lane == 0) *abort_flag = 0;
-  __syncthreads();
   // the lane's instruction of a chunk; lanes past the end take the last one
   // (a zero word, past the last chunk, reads instruction 0)
   auto first_instr = [&](uint64_t cw) -> uint64_t {
@@ -375,40 +456,37 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         ++L_next;
       }
     };
-    if (STAGED) {
-      for (uint32_t c = 0; c < c_ops; ++c) {
-        const uint64_t w = rfl64(ctab[c]);
-        plain_wide_chunk(A, C, Is, w, first_instr(w), lane, base);
-        if (TRACE && trace_row) stamp(c + 1);
-      }
-      // the next chunk's instruction and the chunk word after it are read
-      // while a chunk runs
-      uint64_t cw = rfl64(ctab[c_ops]), cwn = ctab[c_ops + 1];
-      uint64_t ins = first_instr(cw);
-      for (uint32_t c = c_ops; c < c_st; ++c) {
-        const uint64_t nins = first_instr(cwn);
-        const uint64_t cwnn = ctab[c + 2];
-        plain_op_level_chunk(A, C, cw, ins, lane, base);
-        cw = rfl64(cwn);
-        cwn = cwnn;
-        ins = nins;
-        if (TRACE && trace_row) stamp(c + 1);
-      }
-    } else {
-      // the first group of operator chunks, fetched before the leaf level.
-      // The chunk words of a group stay in vector registers (every lane
-      // holds the same value); a scalar copy is taken where it is used.
-      uint64_t cw[kGroup], ins[kGroup];
+    // global instructions: the first group of operator chunks is fetched
+    // before the leaf level.  The chunk words of a group stay in vector
+    // registers (every lane holds the same value); a scalar copy is taken
+    // where it is used.
+    uint64_t cw[kGroup], ins[kGroup];
+    if (!STAGED) {
 #pragma unroll
       for (uint32_t k = 0; k < kGroup; ++k) {
         cw[k] = ctab[c_ops + k];
         ins[k] = first_instr(cw[k]);
       }
-      for (uint32_t c = 0; c < c_ops; ++c) {
-        const uint64_t w = rfl64(ctab[c]);
-        plain_wide_chunk(A, C, Is, w, first_instr(w), lane, base);
+    }
+    // the leaf level
+    if (t > 0) leaf_words(Ig, 0, n_leaf, lane, lw);
+    leaf_level(A, C, Ig, lw, n_leaf, lane, base);
+    if (TRACE && trace_row) stamp(c_ops);
+    if (STAGED) {
+      // the next chunk's instruction and the chunk word after it are read
+      // while a chunk runs
+      uint64_t sw = rfl64(ctab[c_ops]), swn = ctab[c_ops + 1];
+      uint64_t sins = first_instr(sw);
+      for (uint32_t c = c_ops; c < c_st; ++c) {
+        const uint64_t nins = first_instr(swn);
+        const uint64_t swnn = ctab[c + 2];
+        plain_op_level_chunk(A, C, sw, sins, lane, base);
+        sw = rfl64(swn);
+        swn = swnn;
+        sins = nins;
         if (TRACE && trace_row) stamp(c + 1);
       }
+    } else {
       for (uint32_t c = c_ops; c < c_st; c += kGroup) {
         uint64_t nw[kGroup], nins[kGroup];
 #pragma unroll
@@ -430,11 +508,8 @@ __device__ void plain_wave_body(const PlainArgs& A) {
         }
       }
     }
-    for (uint32_t c = c_st; c < n_ch; ++c) {
-      const uint64_t w = rfl64(ctab[c]);
-      plain_wide_chunk(A, C, Is, w, first_instr(w), lane, base);
-      if (TRACE && trace_row) stamp(c + 1);
-    }
+    final_stores(A, C, Is, pp.st_first, pp.n_instr, lane, base);
+    if (TRACE && trace_row) stamp(n_ch);
     if (lane == 0) plain_commit(A, Is, pp, base);
     if (A.digest_part) {
       uint64_t dacc = C.dacc;

@@ -123,7 +123,6 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
     dz->plain_ok = false;
     dz->plain_error = "plain form: " + s.msg;
     d.plain_procs.clear(); d.plain_levels.clear(); d.plain_chunks.clear(); d.plain_instr.clear();
-    d.consts.clear();
     d.plain_max_slots = d.plain_max_instr = d.plain_max_chunks = d.max_plain_lvls = 0;
   } else if (!s.ok()) {
     return fail(s);
@@ -150,7 +149,7 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
   I.max_fiber_cost = d.max_fiber_cost;
   I.max_process_cost = d.max_process_cost;
   I.program_bytes = d.plain_instr.size() * 8 + d.plain_levels.size() * 4 + d.plain_chunks.size() * 8 +
-                    d.plain_procs.size() * sizeof(fsim::PlainProc) + d.consts.size() * 8;
+                    d.plain_procs.size() * sizeof(fsim::PlainProc);
   I.max_process_levels = d.max_process_levels;
   I.max_process_nodes = d.max_process_nodes;
   I.compile_seconds = d.compile_seconds;
@@ -165,7 +164,6 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
     if ((rc = upload(dz->levels, d.plain_levels, st))) return rc;
     if ((rc = upload(dz->chunks, d.plain_chunks, st))) return rc;
     if ((rc = upload(dz->procs, d.plain_procs, st))) return rc;
-    if ((rc = upload(dz->consts, d.consts, st))) return rc;
     std::vector<uint64_t> moff(d.mem_off.begin(), d.mem_off.end() - (d.M ? 1 : 0));
     if (d.M == 0) moff.clear();
     if ((rc = upload(dz->mem_off, moff, st))) return rc;
@@ -500,7 +498,6 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   a.levels = (const uint32_t*)dd->levels.p;
   a.chunks = (const uint64_t*)dd->chunks.p;
   a.procs = (const fsim::PlainProc*)dd->procs.p;
-  a.consts = (const uint64_t*)dd->consts.p;
   a.state = s->state;
   a.outputs = s->outputs;
   a.mem = s->mem;

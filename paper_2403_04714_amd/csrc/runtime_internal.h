@@ -58,7 +58,7 @@ struct fsim_design {
   fsim::Design d;
   struct fsim_design_info info{};
   // plain-form program on the device
-  fsim::DevBuf instr, levels, chunks, procs, consts, mem_off, mem_depth, mem_magic, in_width;
+  fsim::DevBuf instr, levels, chunks, procs, mem_off, mem_depth, mem_magic, in_width;
   uint32_t slot_words = 0, max_proc_instr = 0, max_lvls = 0, max_chunks = 0;
   bool plain_ok = true;             // false: a process exceeds the plain form's limits
   std::string plain_error;          // why (reported when a plain sim is asked for)
