@@ -19,6 +19,7 @@
 #include "compiler.h"
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -896,8 +897,8 @@ constexpr size_t kStoreFlush = 256;
 struct StepScratch {
   explicit StepScratch(size_t n) : lid(n, UINT32_MAX) {}
   std::vector<uint32_t> lid;                 // node -> index among the process's operators
-  std::vector<uint32_t> ops, height, indeg, succ_off, succ, take;
-  std::vector<uint64_t> heap, heap_rd;
+  std::vector<uint32_t> ops, height, indeg, succ_off, succ, take, ready;
+  std::vector<uint8_t> picked;
 };
 
 static uint32_t steps_of(const Design& d, uint32_t lo, uint32_t hi, std::vector<uint32_t>& loc, StepScratch& S) {
@@ -936,32 +937,81 @@ static uint32_t steps_of(const Design& d, uint32_t lo, uint32_t hi, std::vector<
       }
     }
   }
-  // max-heaps on (height, lower index first), operators and memory reads
-  auto key = [&](uint32_t k) { return ((uint64_t)S.height[k] << 32) | (uint32_t)~k; };
-  auto push = [&](uint32_t k) {
-    std::vector<uint64_t>& h = d.op[S.ops[k]] == FSIM_OP_MEMRD ? S.heap_rd : S.heap;
-    h.push_back(key(k));
-    std::push_heap(h.begin(), h.end());
-  };
-  S.heap.clear();
-  S.heap_rd.clear();
+  // steps: at least the depth, and enough for 64 operators a step; an
+  // operator of height h must run by step K - h (its latest step)
+  uint32_t n_alu = 0, depth = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    if (d.op[S.ops[k]] != FSIM_OP_MEMRD) n_alu++;
+    depth = std::max(depth, S.height[k] + 1);
+  }
+  const uint32_t K = std::max(depth, (n_alu + 63) / 64);
+  S.ready.clear();
   for (uint32_t k = 0; k < n; ++k)
-    if (S.indeg[k] == 0) push(k);
+    if (S.indeg[k] == 0) S.ready.push_back(k);
   uint32_t step = 0, done = 0;
   while (done < n) {
     ++step;
+    // ready operators by latest step, then opcode, then index
+    auto latest = [&](uint32_t k) { return K > S.height[k] ? K - S.height[k] : 1u; };
+    std::sort(S.ready.begin(), S.ready.end(), [&](uint32_t a, uint32_t b) {
+      const uint32_t la = latest(a), lb = latest(b);
+      if (la != lb) return la < lb;
+      if (d.op[S.ops[a]] != d.op[S.ops[b]]) return d.op[S.ops[a]] < d.op[S.ops[b]];
+      return a < b;
+    });
     S.take.clear();
-    for (std::vector<uint64_t>* h : {&S.heap, &S.heap_rd})
-      for (uint32_t c = 0; c < 64 && !h->empty(); ++c) {
-        std::pop_heap(h->begin(), h->end());
-        S.take.push_back(~(uint32_t)h->back());
-        h->pop_back();
+    uint32_t used = 0, cnt_rd = 0, ops_in = 0;
+    uint32_t cnt[16] = {0};
+    S.picked.assign(S.ready.size(), 0);
+    // every memory read that is ready, and the operators due by this step
+    // (the longest remaining paths first)
+    for (size_t i = 0; i < S.ready.size(); ++i) {
+      const uint32_t k = S.ready[i], op = d.op[S.ops[k]];
+      if (op == FSIM_OP_MEMRD) {
+        if (cnt_rd < 64) { cnt_rd++; S.take.push_back(k); S.picked[i] = 1; }
+      } else if (latest(k) <= step && used < 64) {
+        used++;
+        if (!(ops_in & (1u << op))) ops_in |= 1u << op;
+        S.take.push_back(k);
+        S.picked[i] = 1;
       }
+    }
+    // fill the step with operators that have slack, preferring opcodes
+    // already in it, then the opcodes with the most ready operators, so a
+    // step holds few distinct opcodes
+    if (used < 64) {
+      for (size_t i = 0; i < S.ready.size(); ++i)
+        if (!S.picked[i] && d.op[S.ops[S.ready[i]]] != FSIM_OP_MEMRD) cnt[d.op[S.ops[S.ready[i]]]]++;
+      while (used < 64) {
+        int best = -1;
+        for (int op = 0; op < 16; ++op) {
+          if (!cnt[op]) continue;
+          if (best < 0) { best = op; continue; }
+          const bool in_b = ops_in & (1u << best), in_o = ops_in & (1u << op);
+          if (in_o != in_b ? in_o : cnt[op] > cnt[best]) best = op;
+        }
+        if (best < 0) break;
+        for (size_t i = 0; i < S.ready.size() && used < 64; ++i) {
+          if (S.picked[i] || d.op[S.ops[S.ready[i]]] != (uint32_t)best) continue;
+          S.picked[i] = 1;
+          S.take.push_back(S.ready[i]);
+          used++;
+          cnt[best]--;
+        }
+        ops_in |= 1u << best;
+        cnt[best] = 0;
+      }
+    }
+    // the rest stays ready
+    size_t w = 0;
+    for (size_t i = 0; i < S.ready.size(); ++i)
+      if (!S.picked[i]) S.ready[w++] = S.ready[i];
+    S.ready.resize(w);
     for (uint32_t k : S.take) {
       loc[S.ops[k]] = step;
       done++;
       for (uint32_t e = S.succ_off[k]; e < S.succ_off[k + 1]; ++e)
-        if (--S.indeg[S.succ[e]] == 0) push(S.succ[e]);
+        if (--S.indeg[S.succ[e]] == 0) S.ready.push_back(S.succ[e]);
     }
   }
   for (uint32_t x : S.ops) S.lid[x] = UINT32_MAX;
@@ -1373,8 +1423,17 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
       }
       flush_sorted();
       order.swap(out);
-      for (uint32_t i = 0; i < (uint32_t)order.size(); ++i) emitted[order[i]] = i;
     }
+    // ---- loads of 1-bit registers into 1-bit values lead the stream: the
+    // kernel takes up to 64 of them (a block of the stream) with one vector
+    // load, one lane per leaf, and each holds only an 8-byte mask slot
+    auto is_bleaf = [&](uint32_t x) {
+      return d.op[x] == FSIM_OP_REG && d.width[x] == 1 && d.reg_width[d.imm[x]] == 1;
+    };
+    std::stable_partition(order.begin(), order.end(), is_bleaf);
+    uint32_t n_bleaf = 0;
+    while (n_bleaf < order.size() && is_bleaf(order[n_bleaf])) ++n_bleaf;
+    for (uint32_t i = 0; i < (uint32_t)order.size(); ++i) emitted[order[i]] = i;
     // ---- liveness (positions in order; sinks read at the end)
     const uint32_t n_ord = (uint32_t)order.size();
     for (uint32_t i = 0; i < n_ord; ++i) last_use[order[i]] = i;
@@ -1519,7 +1578,12 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
     // kernel executes the run as one group.  A run of register loads of one
     // class whose slot class and width match the register's gets its own
     // opcode (K_LDREG_*), executed without per-load class tests.
-    for (uint32_t i = bp.instr_off; i < bp.instr_off + bp.n_instr;) {
+    for (uint32_t j0 = 0; j0 < n_bleaf; j0 += 64) {
+      const uint32_t n = std::min<uint32_t>(64, n_bleaf - j0);
+      for (uint32_t k = 0; k < n; ++k) d.batch_instr[bp.instr_off + j0 + k].op = K_LDB_BATCH;
+      d.batch_instr[bp.instr_off + j0].flags = (uint8_t)n;
+    }
+    for (uint32_t i = bp.instr_off + n_bleaf; i < bp.instr_off + bp.n_instr;) {
       auto is_leaf = [&](uint32_t j) { return d.batch_instr[j].op == I_LDREG || d.batch_instr[j].op == I_LDIN; };
       auto fast_kind = [&](uint32_t j) -> uint32_t {   // 0: not a plain same-class register load
         const Instr& in = d.batch_instr[j];
@@ -1580,22 +1644,36 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
         return off(cls, idx);
       };
       const uint8_t op = in.op;
-      if (op == I_LDREG || op == I_LDIN || (op >= K_LDREG_B && op <= K_LDREG_D)) { in.dst = off(cd, in.dst); }
+      if (op == I_LDREG || op == I_LDIN || (op >= K_LDREG_B && op <= K_LDB_BATCH)) { in.dst = off(cd, in.dst); }
       else if (op == I_MEMRD) { in.dst = off(cd, in.dst); in.a = off(ca, in.a); }
       else if (op == I_STREG || op == I_STOUT) { in.a = off(ca, in.a); }
       else if (op == I_WPORT) { in.a = off(ca, in.a); in.b = off(cb, in.b); in.c = off(cc, in.c); }
       else {
         const bool bk_a = ca == C_B || ca == C_K, bk_b = cb == C_B || cb == C_K, bk_c = cc == C_B || cc == C_K;
+        // a constant whose whole value is 0 or 1 (where more than bit 0 of
+        // the operand decides the result)
+        auto bit_k = [&](uint8_t cls, uint16_t idx) {
+          return cls == C_B || (cls == C_K && d.batch_consts[bp.const_off + idx] <= 1);
+        };
+        // 1-bit results of 1-bit operands: a product is an AND; a shift by a
+        // 1-bit amount keeps a only when the amount is 0 (a AND NOT b; a
+        // right shift needs all of a to be bit 0, a left shift only bit 0)
         const bool mask_ok = cd == C_B &&
-            (((op == I_AND || op == I_OR || op == I_XOR || op == I_ADD || op == I_SUB) && bk_a && bk_b) ||
+            (((op == I_AND || op == I_OR || op == I_XOR || op == I_ADD || op == I_SUB || op == I_MUL) && bk_a &&
+              bk_b) ||
              (op == I_NOT && bk_a) ||
-             ((op == I_EQ || op == I_LT) && ca == C_B && cb == C_B) ||
+             ((op == I_EQ || op == I_LT) && bit_k(ca, in.a) && bit_k(cb, in.b)) ||
+             (op == I_SHL && bk_a && bit_k(cb, in.b)) ||
+             (op == I_SHR && bit_k(ca, in.a) && bit_k(cb, in.b)) ||
              (op == I_MUX && ca == C_B && bk_b && bk_c));
         if (mask_ok) {
-          in.op = op == I_AND ? K_MASK_AND : op == I_OR ? K_MASK_OR
+          in.op = (op == I_AND || op == I_MUL) ? K_MASK_AND : op == I_OR ? K_MASK_OR
                 : (op == I_XOR || op == I_ADD || op == I_SUB) ? K_MASK_XOR
-                : op == I_NOT ? K_MASK_NOT : op == I_EQ ? K_MASK_EQ : op == I_LT ? K_MASK_LT : K_MASK_MUX;
+                : op == I_NOT ? K_MASK_NOT : op == I_EQ ? K_MASK_EQ
+                : (op == I_LT || op == I_SHL || op == I_SHR) ? K_MASK_LT : K_MASK_MUX;
           in.a = moff(ca, in.a); in.b = moff(cb, in.b); in.c = moff(cc, in.c);
+          // NOT b AND a is the LT handler (NOT first operand AND second)
+          if (op == I_SHL || op == I_SHR) std::swap(in.a, in.b);
           in.dst = off(C_B, in.dst);
         } else {
           in.a = off(ca, in.a); in.b = off(cb, in.b); in.c = off(cc, in.c);
@@ -1603,6 +1681,28 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
         }
       }
     }
+  }
+  if (getenv("FSIM_VERBOSE")) {
+    std::map<uint32_t, uint64_t> kinds;
+    for (const Instr& in : d.batch_instr) {
+      uint32_t k = in.op;
+      if (in.op >= I_AND && in.op <= I_MUL) k = 1000 + (uint32_t)in.cls;    // per-lane operator by classes
+      kinds[k]++;
+    }
+    std::vector<std::pair<uint64_t, uint32_t>> v;
+    for (auto& kv : kinds) v.push_back({kv.second, kv.first});
+    std::sort(v.rbegin(), v.rend());
+    fprintf(stderr, "fsim compile: batched instructions %zu; top kinds:", d.batch_instr.size());
+    for (size_t i = 0; i < v.size() && i < 24; ++i) {
+      if (v[i].second >= 1000) {
+        const uint32_t c = v[i].second - 1000;
+        fprintf(stderr, " alu[%c%c%c>%c]=%llu", "BWDK"[(c >> 2) & 3], "BWDK"[(c >> 4) & 3], "BWDK"[c >> 6],
+                "BWDK"[c & 3], (unsigned long long)v[i].first);
+      } else {
+        fprintf(stderr, " op%u=%llu", v[i].second, (unsigned long long)v[i].first);
+      }
+    }
+    fprintf(stderr, "\n");
   }
   // one trailing instruction: the kernel fetches instruction i + 1 while it
   // executes instruction i

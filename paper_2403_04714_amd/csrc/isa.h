@@ -141,7 +141,11 @@ enum : uint8_t {
   // a run of register loads of one class whose slot class and width match
   // the register's (run length in flags, never crossing a 64-instruction
   // block of the process's stream)
-  K_LDREG_B = 40, K_LDREG_W = 41, K_LDREG_D = 42
+  K_LDREG_B = 40, K_LDREG_W = 41, K_LDREG_D = 42,
+  // up to 64 loads of 1-bit registers into 1-bit values, starting at a
+  // 64-instruction block boundary of the process's stream (count in the
+  // first one's flags): one lane per load
+  K_LDB_BATCH = 43
 };
 struct BatchProc {
   uint32_t instr_off;

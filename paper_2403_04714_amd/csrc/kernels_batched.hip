@@ -282,6 +282,19 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
         const uint32_t cd = cls & 3, dst = y & 0xFFFF;
 #pragma unroll
         for (uint32_t t = 0; t < TW; ++t) vstore(base[t], cd, dst, r[t], lane4, lane8, lane);
+      } else if (op == K_LDB_BATCH) {
+        // loads of 1-bit registers, one lane per load: lane k takes
+        // instruction k of the block (its register and mask slot)
+        const uint32_t n = (x >> 24) & 0xFF;
+        if (lane >= l && lane < l + n) {
+          const uint32_t r = bc.w, o = bc.y & 0xFFFF;
+          uint64_t m[TW];
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) m[t] = A.stB[(size_t)cur * A.nB * A.n_tiles + (size_t)r * A.n_tiles + tile[t]];
+#pragma unroll
+          for (uint32_t t = 0; t < TW; ++t) *reinterpret_cast<uint64_t*>(base[t] + o) = m[t];
+        }
+        step = n;
       } else if (op >= K_LDREG_B) {
         // a run of same-class register loads inside the current block: the
         // register index (aux) and the slot offset (dst) of each load come
