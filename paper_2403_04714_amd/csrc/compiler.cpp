@@ -41,10 +41,6 @@ static void phase(const char* what) {
   t0 = t;
 }
 
-// leaf loads the batched kernel issues back to back before waiting: more
-// hide more memory latency, fewer keep fewer values live (LDS per wave)
-static constexpr uint32_t kLeafRun = 2;
-
 static inline int arity(uint8_t op) {
   switch (op) {
     case FSIM_OP_CONST: case FSIM_OP_INPUT: case FSIM_OP_REG: return 0;

@@ -135,6 +135,10 @@ inline uint32_t chunk_capacity(uint32_t op) {
 // Operators on per-lane values keep their opcode (I_AND .. I_MUL, with the
 // operand classes in cls); operators whose operands and result are all 1-bit
 // become whole-mask handlers.
+// longest run of leaf loads (other than 1-bit register loads) the batched
+// encoder forms and the kernel issues back to back before waiting: longer
+// runs hide more memory latency, shorter ones keep fewer values live
+constexpr uint32_t kLeafRun = 2;
 enum : uint8_t {
   K_MASK_AND = 24, K_MASK_OR = 25, K_MASK_XOR = 26, K_MASK_NOT = 27,
   K_MASK_EQ = 28, K_MASK_LT = 29, K_MASK_MUX = 30,

@@ -9,8 +9,6 @@
 
 namespace fsim {
 
-// longest run of leaf loads the encoder emits (issued back to back)
-static constexpr uint32_t kLeafRun = 2;
 
 // ------------------------------------------------------------ batched form
 //
