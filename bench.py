@@ -294,7 +294,8 @@ def study_serving(F, g, configs, ctx, n_jobs=24, lams=(1.0, 2.0, 4.0, 8.0, 16.0,
     rows = []
     for lam in lams:
         srv = F.Server(ctx, 64 << 30, quantum_cycles=256)
-        recs, summ = serve.run(srv, designs, jobs, serve.arrivals(n_jobs, lam=lam), timeout_s=1800)
+        recs, summ = serve.run(srv, designs, jobs, serve.arrivals(n_jobs, lam=lam), timeout_s=1800,
+                               progress=sys.stderr)
         st = srv.stats()
         srv.close()
         waits = sorted(r["queue_wait"] for r in recs if r["queue_wait"] is not None)
@@ -539,7 +540,7 @@ def main():
             res = {"study": "serving sweep", **study_serving(F, g, configs, ctx)}
         elif args.study == "serving-c3":
             res = {"study": "serving sweep from the 10k-cycle floor",
-                   **study_serving(F, g, configs, ctx, n_jobs=24, lams=(0.05, 0.1, 0.2, 0.5), cyc_lo=10_000,
+                   **study_serving(F, g, configs, ctx, n_jobs=24, lams=(0.2, 0.5, 1.0), cyc_lo=10_000,
                                    cyc_hi=100_000)}
         elif args.study == "packing":
             res = {"study": "packing: SLB vs hypergraph (Sec. 6.6)", **study_packing(F, g, tune, ctx)}

@@ -1438,16 +1438,25 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
       for (int k = 0; k < arity(d.op[x]); ++k) last_use[d.arg[3ull * x + k]] = std::max(last_use[d.arg[3ull * x + k]], i);
     }
     // register and output stores follow the instruction that produces the
-    // value (short live ranges); write ports need their values until the end
+    // value (short live ranges); write ports need their values until the end.
+    // A store of a 1-bit register load from the leading batch follows the
+    // whole batch (the batch must stay contiguous), and the value lives until
+    // then.
     std::vector<std::vector<uint32_t>> stores_after(n_ord);
+    auto store_pos = [&](uint32_t root) -> uint32_t {
+      const uint32_t e = emitted[root];
+      if (e >= n_bleaf) return e;
+      last_use[root] = std::max(last_use[root], n_bleaf);
+      return n_bleaf - 1;
+    };
     for (uint32_t k = d.psink_off[p]; k < d.psink_off[p + 1]; ++k) {
       uint32_t s = d.psinks[k];
-      if (s < d.R) stores_after[emitted[d.reg_next[s]]].push_back(s);
+      if (s < d.R) stores_after[store_pos(d.reg_next[s])].push_back(s);
       else if (s < d.R + d.W) {
         uint32_t q = s - d.R;
         last_use[d.wp_en[q]] = last_use[d.wp_addr[q]] = last_use[d.wp_data[q]] = n_ord;
       } else {
-        stores_after[emitted[d.out_node[s - d.R - d.W]]].push_back(s);
+        stores_after[store_pos(d.out_node[s - d.R - d.W])].push_back(s);
       }
     }
     // ---- slot allocation and emission.  1-bit masks get 8-byte slots of
@@ -1538,7 +1547,7 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
       }
       for (uint32_t s : stores_after[i]) {
         uint8_t ca;
-        uint16_t sa = operand(x, ca);
+        uint16_t sa = operand(s < d.R ? d.reg_next[s] : d.out_node[s - d.R - d.W], ca);
         if (s < d.R) {
           Instr st = make(I_STREG, d.reg_width[s], 0, sa, (uint16_t)(s & 0xFFFF), (uint16_t)(s >> 16),
                           d.reg_cls_idx[s] & 0x3FFFFFFF);

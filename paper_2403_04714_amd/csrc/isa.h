@@ -108,10 +108,9 @@ inline uint64_t plain_index(uint32_t w, uint64_t f0, uint64_t index, bool one0 =
 
 // A chunk word: start (16 bits, relative to the first level instruction) |
 // (count - 1) << 16 | kind << 24 | the set of opcodes in an operator chunk
-// (bit k for opcode k) << 32 | flags << 48: kAllNarrowIn (every source field
-// of every instruction is narrow), kAllNarrowOut (every result is narrow),
-// kAllWideOut (every result is wide).
-constexpr uint32_t kAllNarrowIn = 1, kAllNarrowOut = 2, kAllWideOut = 4;
+// (bit k for opcode k) << 32 | flags << 48: kAllNarrowOut (every result
+// takes one unit), kAllWideOut (every result takes two).
+constexpr uint32_t kAllNarrowOut = 2, kAllWideOut = 4;
 inline uint64_t make_chunk(uint32_t start, uint32_t count, uint32_t kind, uint32_t present = 0, uint32_t flags = 0) {
   return start | ((uint64_t)(count - 1) << 16) | ((uint64_t)kind << 24) | ((uint64_t)present << 32) |
          ((uint64_t)flags << 48);

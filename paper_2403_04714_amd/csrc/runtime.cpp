@@ -56,7 +56,12 @@ extern "C" int fsim_ctx_create(int hip_device, void* hip_stream, fsim_ctx** out)
   return FSIM_OK;
 }
 
-extern "C" void fsim_ctx_destroy(fsim_ctx* ctx) { delete ctx; }
+void fsim::ctx_retain(fsim_ctx* c) { if (c) c->refs++; }
+void fsim::ctx_release(fsim_ctx* c) {
+  if (c && --c->refs == 0) delete c;
+}
+
+extern "C" void fsim_ctx_destroy(fsim_ctx* ctx) { fsim::ctx_release(ctx); }
 
 extern "C" int fsim_ctx_device(fsim_ctx* ctx, uint32_t* n_cus, uint32_t* lds_bytes,
                                uint32_t* max_coresident_wgs) {
@@ -176,6 +181,7 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
     if ((rc = upload(dz->in_width, d.in_width, st))) return rc;
     HIP_TRY(hipStreamSynchronize(st));
   }
+  fsim::ctx_retain(dz->ctx);        // held until the design is freed
   *out = dz.release();
   return FSIM_OK;
 }
@@ -202,7 +208,11 @@ extern "C" int fsim_design_partition(const fsim_design* dd, uint32_t* sink_to_pr
 
 void fsim::design_retain(fsim_design* d) { if (d) d->refs++; }
 void fsim::design_release(fsim_design* d) {
-  if (d && --d->refs == 0) delete d;
+  if (d && --d->refs == 0) {
+    fsim_ctx* c = d->ctx;
+    delete d;                       // frees the design's device buffers first
+    fsim::ctx_release(c);
+  }
 }
 
 extern "C" void fsim_design_free(fsim_design* d) { fsim::design_release(d); }

@@ -45,7 +45,11 @@ struct DevBuf {
 
 }  // namespace fsim
 
+// A context is reference-counted: the caller's handle and every design and
+// server made on it each hold one reference, so whatever order the caller
+// releases them in, a design or server never outlives its context.
 struct fsim_ctx {
+  std::atomic<int> refs{1};
   int device = 0;
   hipStream_t stream = nullptr;
   uint32_t n_cus = 0, lds_bytes = 0;
@@ -119,4 +123,6 @@ size_t batched_wave_bytes(const Design& D);
 int ensure_batched(fsim_design* d);
 void design_retain(fsim_design* d);
 void design_release(fsim_design* d);
+void ctx_retain(fsim_ctx* c);
+void ctx_release(fsim_ctx* c);
 }  // namespace fsim

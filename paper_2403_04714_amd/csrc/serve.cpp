@@ -256,6 +256,7 @@ extern "C" int fsim_server_create(fsim_ctx* ctx, size_t hbm_budget, const fsim_s
   if (hbm_budget == 0) return fail(FSIM_E_ARG, "hbm_budget must be > 0");
   auto S = std::make_unique<fsim_server>();
   S->ctx = ctx;
+  fsim::ctx_retain(ctx);
   S->budget = hbm_budget;
   if (opts) {
     if (opts->quantum_cycles) S->K = opts->quantum_cycles;
@@ -420,5 +421,7 @@ extern "C" void fsim_server_destroy(fsim_server* S) {
     if (j->sim) fsim_sim_destroy(j->sim);
     fsim::design_release(j->d);
   }
+  fsim_ctx* c = S->ctx;
   delete S;
+  fsim::ctx_release(c);
 }

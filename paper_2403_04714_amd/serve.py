@@ -33,9 +33,10 @@ def arrivals(n_jobs, lam, arrival_seed=7):
     return np.cumsum(rng.exponential(1.0 / lam, n_jobs))
 
 
-def run(server: F.Server, designs, jobs, arrival_times, timeout_s=600.0, poll_s=0.001):
+def run(server: F.Server, designs, jobs, arrival_times, timeout_s=600.0, poll_s=0.001, progress=None):
     """Submits jobs at their arrival times (seconds from now), waits for all,
-    returns per-job records and a summary."""
+    returns per-job records and a summary.  With `progress` (a text file), a
+    line per submitted and per finished job is written to it."""
     t0 = time.perf_counter()
     ids = []
     submit_at = []
@@ -45,8 +46,12 @@ def run(server: F.Server, designs, jobs, arrival_times, timeout_s=600.0, poll_s=
             time.sleep(at - now)
         submit_at.append(time.perf_counter() - t0)
         ids.append(server.submit(designs[job["design"]], job["instances"], job["cycles"], job["seed"]))
-    for jid in ids:
+        if progress:
+            print(f"serve: t={submit_at[-1]:.1f}s submitted job {len(ids) - 1}", file=progress, flush=True)
+    for k, jid in enumerate(ids):
         server.wait(jid, timeout_s)
+        if progress:
+            print(f"serve: t={time.perf_counter() - t0:.1f}s job {k} done", file=progress, flush=True)
     wall = time.perf_counter() - t0
     recs = []
     for job, jid in zip(jobs, ids):

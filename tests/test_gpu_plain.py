@@ -256,3 +256,32 @@ def test_checkpoint_resume(F, ctx):
     assert np.array_equal(a.regs(), b.regs())
     for m in range(nl.n_mems):
         assert np.array_equal(a.mem(m), b.mem(m))
+
+
+def test_context_released_before_its_design_and_sim(F):
+    """The caller may release handles in any order: with the context's own
+    handle released first, its sim still steps and reads back, the design and
+    sim are released afterwards, and a fresh context works with no error
+    left behind (a design or sim holds the context until it is released)."""
+    nl = g.gen_tiny(seed=8)
+    print("case release order: context first", flush=True)
+    ctx = F.Context(0)
+    d = F.Design(ctx, nl, pack=F.PACK_SLB, target_processes=4)
+    s = F.Sim(d, 1, seed=SEED)
+    ctx.close()
+    s.enable_digest(50)
+    s.step(50)
+    ref = O.Sim(nl, seed=SEED)
+    assert np.array_equal(s.digests()[:, 0], ref.step(50, digests=True))
+    s.close()
+    d.close()
+    ctx2 = F.Context(0)
+    d2 = F.Design(ctx2, nl, pack=F.PACK_SLB, target_processes=4)
+    s2 = F.Sim(d2, 1, seed=SEED)
+    s2.step(10)
+    ref2 = O.Sim(nl, seed=SEED)
+    ref2.step(10)
+    assert np.array_equal(s2.regs(), ref2.regs())
+    s2.close()
+    d2.close()
+    ctx2.close()
