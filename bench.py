@@ -113,13 +113,14 @@ def cpu_baseline(nl, seed, budget_s=15.0):
     P = max(1, min(CPU_THREADS_CAP, len(os.sched_getaffinity(0))))
     done = [0] * P
     start = threading.Barrier(P + 1)
-    deadline = [0.0]
 
     def run(k):
         s = orc.Sim(nl, seed=seed + k)
         s.step(block)
         start.wait()
-        while time.perf_counter() < deadline[0]:
+        # each thread's own deadline, taken after the common start
+        end = time.perf_counter() + budget_s
+        while time.perf_counter() < end:
             s.step(block)
             done[k] += block
 
@@ -128,7 +129,6 @@ def cpu_baseline(nl, seed, budget_s=15.0):
         t.start()
     start.wait()
     t0 = time.perf_counter()
-    deadline[0] = t0 + budget_s
     for t in ths:
         t.join()
     wall = time.perf_counter() - t0

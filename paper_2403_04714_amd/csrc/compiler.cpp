@@ -1621,6 +1621,7 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
   }
   // ---- final form: handler kinds and LDS byte offsets, laid out per process
   d.batch_wave_bytes = 0;
+  std::vector<uint32_t> wave_bytes_of;
   for (uint32_t p = 0; p < d.P; ++p) {
     BatchProc& bp = d.batch_procs[p];
     const uint32_t kbase = 16 + 8 * bp.mask_slots;
@@ -1631,6 +1632,7 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
                                               "16-bit offsets; use more processes", end));
     bp.kbase = kbase;
     d.batch_wave_bytes = std::max(d.batch_wave_bytes, end);
+    wave_bytes_of.push_back(end);
     for (uint32_t i = bp.instr_off; i < bp.instr_off + bp.n_instr; ++i) {
       Instr& in = d.batch_instr[i];
       const uint8_t cd = in.cls & 3, ca = (in.cls >> 2) & 3, cb = (in.cls >> 4) & 3, cc = (in.cls >> 6) & 3;
@@ -1686,6 +1688,26 @@ Status encode_batched(Design& d, uint32_t max_slots_per_class[3]) {
         }
       }
     }
+  }
+  // processes by LDS need (each process's stream, constants and layout are
+  // its own, so their order is free), and the split point
+  {
+    std::vector<uint32_t> ord(d.P);
+    std::iota(ord.begin(), ord.end(), 0u);
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return wave_bytes_of[a] < wave_bytes_of[b]; });
+    std::vector<BatchProc> sorted(d.P);
+    d.batch_need.assign(d.P, 0);
+    for (uint32_t i = 0; i < d.P; ++i) {
+      sorted[i] = d.batch_procs[ord[i]];
+      d.batch_need[i] = wave_bytes_of[ord[i]];
+    }
+    d.batch_procs.swap(sorted);
+  }
+  if (getenv("FSIM_VERBOSE") && !wave_bytes_of.empty()) {
+    std::sort(wave_bytes_of.begin(), wave_bytes_of.end());
+    const size_t n = wave_bytes_of.size();
+    fprintf(stderr, "fsim compile: batched LDS bytes per wave: p50 %u p90 %u p99 %u max %u\n", wave_bytes_of[n / 2],
+            wave_bytes_of[n * 9 / 10], wave_bytes_of[n * 99 / 100], wave_bytes_of.back());
   }
   if (getenv("FSIM_VERBOSE")) {
     std::map<uint32_t, uint64_t> kinds;

@@ -63,7 +63,11 @@ struct Design {
   std::vector<Instr> batch_instr;
   std::vector<uint64_t> batch_consts;   // per-process constant pools, back to back
   uint32_t batch_slots[3] = {0, 0, 0};  // max live slots per class over procs
-  uint32_t batch_wave_bytes = 0;        // LDS bytes of one wave's region
+  uint32_t batch_wave_bytes = 0;        // LDS bytes of one wave's region (the largest process's need)
+  // processes are ordered by their LDS need, ascending: batch_need[i] bytes
+  // of one wave's region for process i (a sim may run a prefix of them in a
+  // launch of its own, with more waves resident per CU)
+  std::vector<uint32_t> batch_need;
   bool batch_encoded = false;
   // internal register numbering of the batched layout: class + index
   std::vector<uint32_t> reg_cls_idx;    // (class << 30) | index

@@ -61,6 +61,17 @@ __device__ __forceinline__ void st_val(char* base, uint32_t off, uint64_t v, boo
 // the spare unit: the last 4 bytes of the value area
 __device__ __forceinline__ uint32_t trash_off(const PlainArgs& A) { return A.slot_words * 8 - 4; }
 
+// The process a workgroup runs.  The dispatcher deals workgroups to the 8
+// XCDs in turn (workgroup b lands on XCD b mod 8, each XCD with an L2 of its
+// own); processes are numbered in packing order, where neighbours share
+// registers and cone logic, so each XCD takes one contiguous range of
+// processes and its L2 serves their shared leaf reads.  A bijection on
+// [0, G) for any G.
+__device__ __forceinline__ uint32_t process_of(uint32_t b, uint32_t G) {
+  const uint32_t x = b & 7, q = G >> 3, r = G & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Per-cycle state shared by the chunk handlers of both plain kernels.
 struct PlainCycle {
   const uint64_t* cur;     // current register values
@@ -298,7 +309,7 @@ __device__ void plain_body(const PlainArgs& A) {
   __shared__ uint64_t red[16];
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
   const uint32_t lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
-  const PlainProc pp = A.procs[blockIdx.x];
+  const PlainProc pp = A.procs[process_of(blockIdx.x, gridDim.x)];
   char* const base = reinterpret_cast<char*>(lds);
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint64_t* const Ig = A.code + pp.instr_off;
@@ -384,7 +395,7 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   extern __shared__ uint64_t lds[];
   int* const abort_flag = reinterpret_cast<int*>(lds);
   const uint32_t lane = threadIdx.x;
-  const PlainProc pp = A.procs[blockIdx.x];
+  const PlainProc pp = A.procs[process_of(blockIdx.x, gridDim.x)];
   char* const base = reinterpret_cast<char*>(lds);
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint64_t* const Ig = A.code + pp.instr_off;

@@ -82,6 +82,9 @@ struct fsim_sim {
   uint32_t* stW = nullptr;
   uint32_t G = 1, threads = 256, launch = FSIM_LAUNCH_PERSISTENT, graph_cycles = 64;
   size_t lds_bytes = 0;
+  // batched: processes [0, split) run in a launch of their own with
+  // wave_bytes_small bytes per wave region (0: one launch for all)
+  uint32_t split = 0, wave_bytes_small = 0;
   bool stage_instr = false;
   bool single_wave = false;    // plain form: the flat one-wave kernel
   bool poisoned = false;
