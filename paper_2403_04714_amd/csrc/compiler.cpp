@@ -1280,7 +1280,8 @@ Status encode_plain(Design& d, uint32_t max_units) {
     std::sort(ns.begin(), ns.end());
     fprintf(stderr, "fsim compile: plain LDS units per process: p50 %u p90 %u p99 %u max %u\n", ns[ns.size() / 2],
             ns[ns.size() * 9 / 10], ns[ns.size() * 99 / 100], ns.back());
-    uint64_t n_alu = 0, lanes_alu = 0, distinct = 0, all_narrow = 0, narrow_out = 0, n_memrd = 0, n_flush = 0;
+    uint64_t n_alu = 0, lanes_alu = 0, distinct = 0, all_narrow = 0, narrow_out = 0, n_memrd = 0, n_flush = 0,
+             single_op = 0;
     for (const PlainProc& q : d.plain_procs)
       for (uint32_t c = q.c_ops; c < q.c_st; ++c) {
         const uint64_t cw = d.plain_chunks[q.chunk_off + c];
@@ -1289,6 +1290,7 @@ Status encode_plain(Design& d, uint32_t max_units) {
           n_alu++;
           lanes_alu += ((cw >> 16) & 0xFF) + 1;
           distinct += __builtin_popcount((uint32_t)(cw >> 32) & 0xFFFF);
+          if (__builtin_popcount((uint32_t)(cw >> 32) & 0xFFFF) == 1) single_op++;
           if (fl & kAllWideOut) all_narrow++;
           if (fl & kAllNarrowOut) narrow_out++;
         } else if (kind == I_MEMRD) n_memrd++;
@@ -1299,6 +1301,8 @@ Status encode_plain(Design& d, uint32_t max_units) {
             n_alu ? (double)lanes_alu / n_alu : 0.0, n_alu ? (double)distinct / n_alu : 0.0,
             n_alu ? 100.0 * all_narrow / n_alu : 0.0, n_alu ? 100.0 * narrow_out / n_alu : 0.0,
             (unsigned long long)n_memrd, (unsigned long long)n_flush);
+    fprintf(stderr, "fsim compile: plain operator chunks with one opcode: %.1f%%\n",
+            n_alu ? 100.0 * single_op / n_alu : 0.0);
     uint64_t wc = 0, wl = 0, ws = 0, ww = 0, cl = 0, cs = 0;
     for (const PlainProc& q : d.plain_procs) {
       wc += 2 * q.n_consts;
