@@ -1188,6 +1188,8 @@ Status encode_plain(Design& d, uint32_t max_units) {
           if (ins[j].out_narrow) flags &= ~kAllWideOut;
           d.plain_instr.push_back(ins[j].word);
         }
+        if (kk == I_ALU && (present & (present - 1)) && !(flags & (kAllNarrowOut | kAllWideOut))) flags |= kMixedChunk;
+        if (kk != I_ALU) flags |= kOtherKind;
         d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), kk, present, flags));
         k = e;
       }

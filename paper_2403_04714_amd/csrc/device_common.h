@@ -22,40 +22,45 @@ __device__ __forceinline__ uint64_t hmix(uint64_t x) {
 
 __device__ __forceinline__ uint64_t wmask(uint32_t w) { return ~0ull >> (64u - w); }
 
-// One operator per lane, opcodes differing between lanes.  `present` (wave
-// uniform) holds the opcodes that occur in the chunk.  A chunk of a single
-// opcode dispatches once on it with scalar branches and evaluates it alone.
-// Otherwise each opcode present is evaluated for every lane and selected
-// where it is the lane's own: a few vector instructions per opcode present
-// and no divergent branch.  (Running each opcode under an execution mask of
-// its lanes instead saves the selects but adds scalar mask work and a branch
-// per opcode; it measured 1-2% slower on every workload.)
-__device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uint32_t w, uint64_t a, uint64_t b,
-                                              uint64_t c) {
+// One operator per lane, all lanes of one opcode `k` (wave-uniform): one
+// dispatch on k with scalar branches.  The result is cut to the operator's
+// width by `mask`.
+__device__ __forceinline__ uint64_t alu_single(uint32_t k, uint64_t mask, uint64_t a, uint64_t b, uint64_t c) {
   uint64_t r = 0;
-  if ((present & (present - 1)) == 0) {
-    // the empty asm keeps the dispatch a tree of real (scalar) branches
-    switch (__builtin_ctz(present | (1u << 31))) {
-      case I_AND: asm volatile(""); r = a & b; break;
-      case I_OR:  asm volatile(""); r = a | b; break;
-      case I_XOR: asm volatile(""); r = a ^ b; break;
-      case I_NOT: asm volatile(""); r = ~a; break;
-      case I_ADD: asm volatile(""); r = a + b; break;
-      case I_SUB: asm volatile(""); r = a - b; break;
-      case I_MUX: asm volatile(""); r = a ? b : c; break;
-      case I_SHL: asm volatile(""); r = b >= 64 ? 0 : (a << (b & 63)); break;
-      case I_SHR: asm volatile(""); r = b >= 64 ? 0 : (a >> (b & 63)); break;
-      case I_EQ:  asm volatile(""); r = a == b; break;
-      case I_LT:  asm volatile(""); r = a < b; break;
-      case I_MUL: asm volatile(""); r = a * b; break;
-      default: break;
-    }
-    return r & wmask(w);
+  // the empty asm keeps the dispatch a tree of real (scalar) branches
+  switch (k) {
+    case I_AND: asm volatile(""); r = a & b; break;
+    case I_OR:  asm volatile(""); r = a | b; break;
+    case I_XOR: asm volatile(""); r = a ^ b; break;
+    case I_NOT: asm volatile(""); r = ~a; break;
+    case I_ADD: asm volatile(""); r = a + b; break;
+    case I_SUB: asm volatile(""); r = a - b; break;
+    case I_MUX: asm volatile(""); r = a ? b : c; break;
+    case I_SHL: asm volatile(""); r = b >= 64 ? 0 : (a << (b & 63)); break;
+    case I_SHR: asm volatile(""); r = b >= 64 ? 0 : (a >> (b & 63)); break;
+    case I_EQ:  asm volatile(""); r = a == b; break;
+    case I_LT:  asm volatile(""); r = a < b; break;
+    case I_MUL: asm volatile(""); r = a * b; break;
+    default: break;
   }
+  return r & mask;
+}
+
+// One operator per lane, opcodes differing between lanes.  `present` (wave
+// uniform) holds the opcodes that occur in the chunk; each is evaluated for
+// every lane and selected where it is the lane's own: a few vector
+// instructions per opcode present and no divergent branch.  (Running each
+// opcode under an execution mask of its lanes instead saves the selects but
+// adds scalar mask work and a branch per opcode; it measured 1-2% slower on
+// every workload.)  An opcode's block follows its test in the code, so an
+// opcode present costs no taken branch.
+__device__ __forceinline__ uint64_t alu_select(uint32_t present, uint32_t op, uint64_t mask, uint64_t a, uint64_t b,
+                                               uint64_t c) {
+  uint64_t r = 0;
   // the empty asm keeps each test a real (scalar) branch, so opcodes absent
   // from the chunk cost two scalar instructions instead of being computed
 #define FSIM_MIXED(OPC, EXPR) \
-  if (present & (1u << (OPC))) { asm volatile(""); r = op == (OPC) ? (uint64_t)(EXPR) : r; }
+  if (__builtin_expect((present & (1u << (OPC))) != 0, 1)) { asm volatile(""); r = op == (OPC) ? (uint64_t)(EXPR) : r; }
   FSIM_MIXED(I_AND, a & b)
   FSIM_MIXED(I_OR, a | b)
   FSIM_MIXED(I_XOR, a ^ b)
@@ -69,7 +74,7 @@ __device__ __forceinline__ uint64_t alu_mixed(uint32_t present, uint32_t op, uin
   FSIM_MIXED(I_LT, a < b)
   FSIM_MIXED(I_MUL, a * b)
 #undef FSIM_MIXED
-  return r & wmask(w);
+  return r & mask;
 }
 
 static constexpr long kSpinLimit = 1l << 22;
@@ -137,15 +142,16 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* flags, uint32_t* error, u
 // Fields of a plain-form instruction word (isa.h), from its low and high
 // halves.  Fields come out as LDS byte offsets (unit x 4).
 __device__ __forceinline__ uint32_t pw_op(uint32_t lo) { return lo & 15; }
-__device__ __forceinline__ uint32_t pw_w(uint32_t lo) { return (lo >> 4) & 127; }
+// the mask of the value's width (the field holds 64 - width)
+__device__ __forceinline__ uint64_t pw_mask(uint32_t lo) { return ~0ull >> ((lo >> 4) & 63); }
 __device__ __forceinline__ uint32_t pw_f0(uint32_t lo) { return (lo >> 12) & 0x3FFC; }
 __device__ __forceinline__ uint32_t pw_f1(uint32_t lo, uint32_t hi) {
   return (uint32_t)((((uint64_t)hi << 32) | lo) >> 24) & 0x3FFC;
 }
 __device__ __forceinline__ uint32_t pw_f2(uint32_t hi) { return (hi >> 4) & 0x3FFC; }
 __device__ __forceinline__ uint32_t pw_f3(uint32_t hi) { return (hi >> 16) & 0x3FFC; }
-// whether the destination in field 0 takes one unit (bit 30 of the high half)
-__device__ __forceinline__ bool pw_one0(uint32_t hi) { return (hi >> 30) & 1; }
+// whether the destination in field 0 takes one unit (the high half's sign)
+__device__ __forceinline__ bool pw_one0(uint32_t hi) { return (int32_t)hi < 0; }
 // register, port, output or constant index (bits 26..61)
 __device__ __forceinline__ uint64_t pw_index(uint32_t lo, uint32_t hi) {
   return (((uint64_t)(hi & 0x3FFFFFFFu)) << 6) | (lo >> 26);

@@ -73,20 +73,21 @@ struct PlainProc {
 static_assert(sizeof(PlainProc) == 56, "PlainProc must be 56 bytes");
 
 // A plain-form instruction is one 64-bit word.  Values live in LDS in
-// 4-byte units: a value of at most 32 bits takes one unit, a wider one two
-// (an even pair); a field names a unit (12 bits), and the flags mark the
-// source fields whose value is narrow (its upper half is not stored).
+// 4-byte units: a value of at most 32 bits takes one unit (or two, kept
+// zero-extended, where a reader needs its upper half), a wider one two (an
+// even pair); a field names a unit (12 bits).
 //   bits  0..3   opcode & 15 (operators 4..15; other instructions take their
 //                kind from the chunk)
-//   bits  4..10  width 1..64 (STREG: the register's; LDIN: the smaller of
-//                the node's and the port's; WPORT: the memory's)
-//   bits 11..13  narrow flags of fields 1, 2, 3
+//   bits  4..10  64 - width, for width 1..64 (STREG: the register's; LDIN:
+//                the smaller of the node's and the port's; WPORT: the
+//                memory's), so the width's mask is ~0 >> this field
 //   bits 14..25  field 0        bits 26..37  field 1
 //   bits 38..49  field 2        bits 50..61  field 3
-//   bit  62      narrow flag of field 0 (when it is a source)
+//   bit  63      the destination in field 0 takes one unit (the sign bit of
+//                the high half, so a kernel tests it with one compare)
 // Operators: destination, then operands a, b, c in fields 0..3 (an unused
 // operand repeats a).  Leaf loads (LDREG, LDIN) and the prologue (LDCONST):
-// the destination in field 0 (its narrow flag gives the destination's size),
+// the destination in field 0 (bit 63 gives its size),
 // the register or port index in bits 26..61, and bit 0 set for an input port.
 // Stores (STREG, STOUT): the source in field 0, the register or output index
 // in bits 26..61, and bit 0 set for an output.  MEMRD: destination and address, the memory
@@ -100,17 +101,20 @@ constexpr uint32_t kMaxPlainUnits = (1u << kUnitBits) - 1;
 constexpr uint32_t kMaxWportMems = 1u << 12;
 inline uint64_t plain_word(uint32_t op, uint32_t w, uint64_t f0, uint64_t f1, uint64_t f2, uint64_t f3,
                            bool one0 = false) {
-  return (op & 15) | (uint64_t)w << 4 | f0 << 14 | f1 << 26 | f2 << 38 | f3 << 50 | (uint64_t)one0 << 62;
+  return (op & 15) | (uint64_t)(64u - w) << 4 | f0 << 14 | f1 << 26 | f2 << 38 | f3 << 50 | (uint64_t)one0 << 63;
 }
 inline uint64_t plain_index(uint32_t w, uint64_t f0, uint64_t index, bool one0 = false) {
-  return (uint64_t)w << 4 | f0 << 14 | index << 26 | (uint64_t)one0 << 62;
+  return (uint64_t)(64u - w) << 4 | f0 << 14 | index << 26 | (uint64_t)one0 << 63;
 }
 
 // A chunk word: start (16 bits, relative to the first level instruction) |
 // (count - 1) << 16 | kind << 24 | the set of opcodes in an operator chunk
 // (bit k for opcode k) << 32 | flags << 48: kAllNarrowOut (every result
-// takes one unit), kAllWideOut (every result takes two).
-constexpr uint32_t kAllNarrowOut = 2, kAllWideOut = 4;
+// takes one unit), kAllWideOut (every result takes two), kMixedChunk (an
+// operator chunk of several opcodes whose results take one unit in some
+// lanes and two in others), kOtherKind (any chunk but an operator chunk: the
+// chunk word's sign bit).
+constexpr uint32_t kAllNarrowOut = 2, kAllWideOut = 4, kMixedChunk = 8, kOtherKind = 0x8000;
 inline uint64_t make_chunk(uint32_t start, uint32_t count, uint32_t kind, uint32_t present = 0, uint32_t flags = 0) {
   return start | ((uint64_t)(count - 1) << 16) | ((uint64_t)kind << 24) | ((uint64_t)present << 32) |
          ((uint64_t)flags << 48);

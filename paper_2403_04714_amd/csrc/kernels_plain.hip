@@ -42,21 +42,34 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
   return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
 }
 
+// LDS addresses: ds instructions take a 32-bit byte address within the
+// workgroup's allocation, so the value area is named by its LDS address
+// (`base`) and an access builds its pointer from base + offset.  Where the
+// value area starts at address 0 (no static LDS) the addition folds away.
+typedef __attribute__((address_space(3))) uint32_t lds_u32_t;
+typedef __attribute__((address_space(3))) uint64_t lds_u64_t;
+__device__ __forceinline__ lds_u32_t* lds32(uint32_t a) { return (lds_u32_t*)(size_t)a; }
+__device__ __forceinline__ lds_u64_t* lds64(uint32_t a) { return (lds_u64_t*)(size_t)a; }
+// the LDS address of a __shared__ object
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(size_t)(const __attribute__((address_space(3))) char*)p;
+}
+
 // LDS value access by byte offset.  A value is read as 8 bytes.  A value in
 // one 4-byte unit (at most 32 bits, read only where its upper half does not
 // matter) then comes with the next unit, which belongs to another value, as
 // its upper half; a value in two units (wide, or narrow and kept
 // zero-extended) is an 8-byte aligned pair.
-__device__ __forceinline__ uint64_t ld_raw(const char* base, uint32_t off) {
-  const uint32_t* p = reinterpret_cast<const uint32_t*>(base + off);
+__device__ __forceinline__ uint64_t ld_raw(uint32_t base, uint32_t off) {
+  const lds_u32_t* p = lds32(base + off);
   return (uint64_t)p[0] | ((uint64_t)p[1] << 32);
 }
 // A store of either size without a branch: the low half goes to its unit,
 // the high half to the next unit for a two-unit value and to the spare unit
 // at `trash` (never read as a value) for a one-unit one.
-__device__ __forceinline__ void st_val(char* base, uint32_t off, uint64_t v, bool one, uint32_t trash) {
-  *reinterpret_cast<uint32_t*>(base + off) = (uint32_t)v;
-  *reinterpret_cast<uint32_t*>(base + (one ? trash : off + 4)) = (uint32_t)(v >> 32);
+__device__ __forceinline__ void st_val(uint32_t base, uint32_t off, uint64_t v, bool one, uint32_t trash) {
+  *lds32(base + off) = (uint32_t)v;
+  *lds32(base + (one ? trash : off + 4)) = (uint32_t)(v >> 32);
 }
 // the spare unit: the last 4 bytes of the value area
 __device__ __forceinline__ uint32_t trash_off(const PlainArgs& A) { return A.slot_words * 8 - 4; }
@@ -85,7 +98,7 @@ struct PlainCycle {
 // lane's first instruction (already fetched); Is the process's
 // instructions; base the LDS value area.
 __device__ __forceinline__ void plain_wide_chunk(const PlainArgs& A, PlainCycle& C, const uint64_t* Is,
-                                                 uint64_t cw, uint64_t raw, uint32_t lane, char* base) {
+                                                 uint64_t cw, uint64_t raw, uint32_t lane, uint32_t base) {
   const uint32_t start = (uint32_t)cw & 0xFFFF, cnt = ((uint32_t)(cw >> 16) & 0xFF) + 1;
   const uint32_t op = (uint32_t)(cw >> 24) & 0xFF;
   uint64_t rq[4], v[4];
@@ -115,7 +128,7 @@ __device__ __forceinline__ void plain_wide_chunk(const PlainArgs& A, PlainCycle&
     const uint32_t e = lane + 64 * q;
     if (e < cnt) {
       const uint32_t lo = (uint32_t)rq[q], hi = (uint32_t)(rq[q] >> 32);
-      const uint64_t x = v[q] & wmask(pw_w(lo));   // LDIN widths fold in the port width
+      const uint64_t x = v[q] & pw_mask(lo);   // LDIN widths fold in the port width
       if (op == I_LDREG || op == I_LDIN) {
         st_val(base, pw_f0(lo), x, pw_one0(hi), trash_off(A));
       } else if (op == I_STREG) {
@@ -132,20 +145,27 @@ __device__ __forceinline__ void plain_wide_chunk(const PlainArgs& A, PlainCycle&
 // An operator chunk: one instruction per lane, every operand read before any
 // lane computes.  Lanes past the chunk's end hold its last instruction: they
 // read the same operands and store the same value to the same place, so the
-// store needs no guard.  `cw` is the chunk word (wave-uniform).
-__device__ __forceinline__ void plain_alu_chunk(uint64_t cw, uint64_t raw, char* base, uint32_t trash) {
+// store needs no guard.  `cw` is the chunk word (wave-uniform).  The general
+// chunk (several opcodes, results of both sizes: nearly every chunk of a
+// large process) takes one test; the others have cheaper forms.
+__device__ __forceinline__ void plain_alu_chunk(uint64_t cw, uint64_t raw, uint32_t base, uint32_t trash) {
   const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
-  const uint32_t flags = (uint32_t)(cw >> 48);
+  const uint32_t flags = (uint32_t)(cw >> 48), present = (uint32_t)(cw >> 32) & 0xFFFF;
   uint64_t a = ld_raw(base, pw_f1(lo, hi)), b = ld_raw(base, pw_f2(hi)), c = ld_raw(base, pw_f3(hi));
   asm volatile("; operands of an operator chunk ready" : "+v"(a), "+v"(b), "+v"(c));
-  const uint64_t r = alu_mixed((uint32_t)(cw >> 32), pw_op(lo), pw_w(lo), a, b, c);
-  if (flags & kAllNarrowOut) *reinterpret_cast<uint32_t*>(base + pw_f0(lo)) = (uint32_t)r;
-  else if (flags & kAllWideOut) *reinterpret_cast<uint64_t*>(base + pw_f0(lo)) = r;
+  if (__builtin_expect((flags & kMixedChunk) != 0, 1)) {
+    st_val(base, pw_f0(lo), alu_select(present, pw_op(lo), pw_mask(lo), a, b, c), pw_one0(hi), trash);
+    return;
+  }
+  const uint64_t r = (present & (present - 1)) == 0 ? alu_single(__builtin_ctz(present | (1u << 31)), pw_mask(lo), a, b, c)
+                                                    : alu_select(present, pw_op(lo), pw_mask(lo), a, b, c);
+  if (flags & kAllNarrowOut) *lds32(base + pw_f0(lo)) = (uint32_t)r;
+  else if (flags & kAllWideOut) *lds64(base + pw_f0(lo)) = r;
   else st_val(base, pw_f0(lo), r, pw_one0(hi), trash);
 }
 
 // A memory-read chunk.  Lanes past the chunk's end repeat its last read.
-__device__ __forceinline__ void plain_memrd(const PlainArgs& A, uint64_t raw, char* base) {
+__device__ __forceinline__ void plain_memrd(const PlainArgs& A, uint64_t raw, uint32_t base) {
   const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
   const uint64_t addr_v = ld_raw(base, pw_f1(lo, hi));
   const uint32_t m = pw_mem38(hi);
@@ -156,17 +176,16 @@ __device__ __forceinline__ void plain_memrd(const PlainArgs& A, uint64_t raw, ch
   uint64_t addr = addr_v - q * depth;
   addr = addr >= depth ? addr - depth : addr;
   addr = addr >= depth ? addr - depth : addr;
-  const uint32_t w = pw_w(lo);
-  st_val(base, pw_f0(lo), A.mem[A.mem_off[m] + addr] & wmask(w), pw_one0(hi), trash_off(A));
+  st_val(base, pw_f0(lo), A.mem[A.mem_off[m] + addr] & pw_mask(lo), pw_one0(hi), trash_off(A));
 }
 
 // Register or output stores written out among the operator levels: one per
 // lane.  Lanes past the chunk's end repeat its last store (the same value to
 // the same place) and add nothing to the digest.
 __device__ __forceinline__ void plain_store64(const PlainArgs& A, PlainCycle& C, uint64_t cw, uint64_t raw,
-                                              uint32_t lane, const char* base) {
+                                              uint32_t lane, uint32_t base) {
   const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
-  const uint64_t x = ld_raw(base, pw_f0(lo)) & wmask(pw_w(lo));
+  const uint64_t x = ld_raw(base, pw_f0(lo)) & pw_mask(lo);
   const uint64_t ix = pw_index(lo, hi);
   if (((uint32_t)(cw >> 24) & 0xFF) == I_STREG) {
     C.nxt[ix] = x;
@@ -180,16 +199,17 @@ __device__ __forceinline__ void plain_store64(const PlainArgs& A, PlainCycle& C,
 // and output stores written out before the last level; one instruction per
 // lane and no branch that differs between lanes.
 __device__ __forceinline__ void plain_op_level_chunk(const PlainArgs& A, PlainCycle& C, uint64_t cw, uint64_t raw,
-                                                     uint32_t lane, char* base) {
-  const uint32_t kind = (uint32_t)(cw >> 24) & 0xFF;
-  if (kind == I_ALU) plain_alu_chunk(cw, raw, base, trash_off(A));
-  else if (kind == I_MEMRD) plain_memrd(A, raw, base);
+                                                     uint32_t lane, uint32_t base) {
+  // operator chunks carry no kOtherKind flag, so the common case costs one
+  // test of the chunk word's sign
+  if (__builtin_expect((int64_t)cw >= 0, 1)) plain_alu_chunk(cw, raw, base, trash_off(A));
+  else if (((uint32_t)(cw >> 24) & 0xFF) == I_MEMRD) plain_memrd(A, raw, base);
   else plain_store64(A, C, cw, raw, lane, base);
 }
 
 // Any chunk (the multi-wave kernel, which runs every level alike).
 __device__ __forceinline__ void plain_level_chunk(const PlainArgs& A, PlainCycle& C, const uint64_t* Is, uint64_t cw,
-                                                  uint64_t raw, uint32_t lane, char* base) {
+                                                  uint64_t raw, uint32_t lane, uint32_t base) {
   const uint32_t kind = (uint32_t)(cw >> 24) & 0xFF;
   if (kind == I_ALU) plain_alu_chunk(cw, raw, base, trash_off(A));
   else if (kind == I_MEMRD) plain_memrd(A, raw, base);
@@ -198,7 +218,7 @@ __device__ __forceinline__ void plain_level_chunk(const PlainArgs& A, PlainCycle
 
 // The write-port commit: after every read of the cycle, in port order, by
 // one lane.
-__device__ __forceinline__ void plain_commit(const PlainArgs& A, const uint64_t* Is, const PlainProc& pp, char* base) {
+__device__ __forceinline__ void plain_commit(const PlainArgs& A, const uint64_t* Is, const PlainProc& pp, uint32_t base) {
   for (uint32_t k = 0; k < pp.n_wp; ++k) {
     const uint64_t w = Is[pp.n_instr + k];
     const uint32_t lo = (uint32_t)w, hi = (uint32_t)(w >> 32);
@@ -206,7 +226,7 @@ __device__ __forceinline__ void plain_commit(const PlainArgs& A, const uint64_t*
       const uint32_t m = pw_mem50(hi);
       const uint64_t depth = A.mem_depth[m], av = ld_raw(base, pw_f1(lo, hi));
       const uint64_t addr = (depth & (depth - 1)) ? av % depth : (av & (depth - 1));
-      A.mem[A.mem_off[m] + addr] = ld_raw(base, pw_f2(hi)) & wmask(pw_w(lo));
+      A.mem[A.mem_off[m] + addr] = ld_raw(base, pw_f2(hi)) & pw_mask(lo);
     }
   }
 }
@@ -214,7 +234,7 @@ __device__ __forceinline__ void plain_commit(const PlainArgs& A, const uint64_t*
 // The constant prologue: every constant into its LDS place, once per launch.
 // A constant is a destination word followed by its value.
 __device__ __forceinline__ void plain_consts(const PlainArgs& A, const PlainProc& pp, uint32_t tid, uint32_t nthr,
-                                             char* base) {
+                                             uint32_t base) {
   for (uint32_t i = tid; i < pp.n_consts; i += nthr) {
     const uint64_t w = A.code[pp.const_off + 2 * i], v = A.code[pp.const_off + 2 * i + 1];
     st_val(base, pw_f0((uint32_t)w), v, pw_one0((uint32_t)(w >> 32)), trash_off(A));
@@ -235,7 +255,7 @@ __device__ __forceinline__ void leaf_words(const uint64_t* Ig, uint32_t b0, uint
 }
 // `w` holds the first batch's words on entry
 __device__ __forceinline__ void leaf_level(const PlainArgs& A, const PlainCycle& C, const uint64_t* Ig,
-                                           uint64_t (&w)[kLeafQ], uint32_t n, uint32_t lane, char* base) {
+                                           uint64_t (&w)[kLeafQ], uint32_t n, uint32_t lane, uint32_t base) {
   // inputs: the stimulus hash of the port's key (the key is gathered like a
   // register), or a row of caller-supplied values
   const bool expl = A.in_vals != nullptr;
@@ -263,7 +283,7 @@ __device__ __forceinline__ void leaf_level(const PlainArgs& A, const PlainCycle&
     for (uint32_t q = 0; q < kLeafQ; ++q) {
       const uint32_t lo = (uint32_t)w[q], hi = (uint32_t)(w[q] >> 32);
       // LDIN widths fold in the port width
-      if (b0 + lane + 64 * q < n) st_val(base, pw_f0(lo), v[q] & wmask(pw_w(lo)), pw_one0(hi), trash_off(A));
+      if (b0 + lane + 64 * q < n) st_val(base, pw_f0(lo), v[q] & pw_mask(lo), pw_one0(hi), trash_off(A));
     }
 #pragma unroll
     for (uint32_t q = 0; q < kLeafQ; ++q) w[q] = wn[q];
@@ -273,7 +293,7 @@ __device__ __forceinline__ void leaf_level(const PlainArgs& A, const PlainCycle&
 // One-wave final store level: kStQ store words per lane in flight.
 constexpr uint32_t kStQ = 4;
 __device__ __forceinline__ void final_stores(const PlainArgs& A, PlainCycle& C, const uint64_t* Is, uint32_t first,
-                                             uint32_t n, uint32_t lane, const char* base) {
+                                             uint32_t n, uint32_t lane, uint32_t base) {
   for (uint32_t b0 = first; b0 < n; b0 += 64 * kStQ) {
     uint64_t w[kStQ];
 #pragma unroll
@@ -285,7 +305,7 @@ __device__ __forceinline__ void final_stores(const PlainArgs& A, PlainCycle& C, 
     for (uint32_t q = 0; q < kStQ; ++q) {
       if (b0 + lane + 64 * q < n) {
         const uint32_t lo = (uint32_t)w[q], hi = (uint32_t)(w[q] >> 32);
-        const uint64_t x = ld_raw(base, pw_f0(lo)) & wmask(pw_w(lo));
+        const uint64_t x = ld_raw(base, pw_f0(lo)) & pw_mask(lo);
         const uint64_t ix = pw_index(lo, hi);
         if (lo & 1) {
           A.outputs[ix] = x;
@@ -310,7 +330,7 @@ __device__ void plain_body(const PlainArgs& A) {
   const uint32_t tid = threadIdx.x, nthr = blockDim.x;
   const uint32_t lane = tid & 63, wave = tid >> 6, nwaves = (nthr + 63) >> 6;
   const PlainProc pp = A.procs[process_of(blockIdx.x, gridDim.x)];
-  char* const base = reinterpret_cast<char*>(lds);
+  const uint32_t base = lds_addr(lds);
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint64_t* const Ig = A.code + pp.instr_off;
   uint64_t* const Ist = lds + A.slot_words;
@@ -396,7 +416,7 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   int* const abort_flag = reinterpret_cast<int*>(lds);
   const uint32_t lane = threadIdx.x;
   const PlainProc pp = A.procs[process_of(blockIdx.x, gridDim.x)];
-  char* const base = reinterpret_cast<char*>(lds);
+  const uint32_t base = 0;   // the value area's LDS address
   const uint32_t n_all = pp.n_instr + pp.n_wp;
   const uint64_t* const Ig = A.code + pp.instr_off;
   uint64_t* const ctab = lds + A.slot_words;
@@ -409,7 +429,15 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   uint64_t lw[kLeafQ];
   leaf_words(Ig, 0, n_leaf, lane, lw);
   const uint64_t* const K = A.code + pp.const_off;
-  const uint64_t cw0 = lane < n_ch ? A.chunks[pp.chunk_off + lane] : 0;
+  // the chunk table: entries from the store phase on repeat the last
+  // operator chunk, so the operator loop reads ahead without a bound
+  const uint32_t c_ops = pp.c_ops, c_st = pp.c_st;
+  const uint32_t c_rep = c_st > c_ops ? c_st - 1 : n_ch;
+  auto ctab_entry = [&](uint32_t i) -> uint64_t {
+    const uint32_t j = i < c_rep ? i : c_rep;
+    return j < n_ch ? A.chunks[pp.chunk_off + j] : 0;
+  };
+  const uint64_t cw0 = ctab_entry(lane);
   const uint64_t kw0 = lane < n_k ? K[2 * lane] : 0, kv0 = lane < n_k ? K[2 * lane + 1] : 0;
   // staging, eight loads in flight per lane
   for (uint32_t b0 = 0; STAGED && b0 < n_all; b0 += 512) {
@@ -427,7 +455,7 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   }
   const uint64_t* const Is = STAGED ? Ist : Ig;
   if (lane < A.ctab_words) ctab[lane] = cw0;
-  for (uint32_t i = lane + 64; i < A.ctab_words; i += 64) ctab[i] = i < n_ch ? A.chunks[pp.chunk_off + i] : 0;
+  for (uint32_t i = lane + 64; i < A.ctab_words; i += 64) ctab[i] = ctab_entry(i);
   if (lane < n_k) st_val(base, pw_f0((uint32_t)kw0), kv0, pw_one0((uint32_t)(kw0 >> 32)), trash_off(A));
   for (uint32_t i = lane + 64; i < n_k; i += 64)
     st_val(base, pw_f0((uint32_t)K[2 * i]), K[2 * i + 1], pw_one0((uint32_t)(K[2 * i] >> 32)), trash_off(A));
@@ -437,15 +465,15 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   // one wave: its LDS operations complete in order, so the set-up's stores
   // need no barrier before the reads below
   if (lane == 0) *abort_flag = 0;
-  // the lane's instruction of a chunk; lanes past the end take the last one
-  // (a zero word, past the last chunk, reads instruction 0)
-  auto first_instr = [&](uint64_t cw) -> uint64_t {
+  // a chunk word (wave-uniform, kept in scalar registers) and the lane's
+  // instruction of that chunk; lanes past the chunk's end take its last one
+  auto op_chunk = [&](uint32_t c) -> uint64_t { return rfl64(ctab[c]); };
+  auto op_instr = [&](uint64_t cw) -> uint64_t {
     const uint32_t m = (uint32_t)(cw >> 16) & 0xFF;
     return Is[((uint32_t)cw & 0xFFFF) + (lane < m ? lane : m)];
   };
   const uint64_t cyc0 = A.cycle_ptr ? *A.cycle_ptr + A.cycle0 : A.cycle0;
   uint64_t* trace_row = nullptr;
-  const uint32_t c_ops = pp.c_ops, c_st = pp.c_st;
   for (uint32_t t = 0; t < A.n_cycles; ++t) {
     PlainCycle C;
     C.cyc = cyc0 + t;
@@ -468,47 +496,45 @@ __device__ void plain_wave_body(const PlainArgs& A) {
       }
     };
     // global instructions: the first group of operator chunks is fetched
-    // before the leaf level.  The chunk words of a group stay in vector
-    // registers (every lane holds the same value); a scalar copy is taken
-    // where it is used.
+    // before the leaf level
     uint64_t cw[kGroup], ins[kGroup];
-    if (!STAGED) {
+    if (!STAGED && c_ops < c_st) {
 #pragma unroll
       for (uint32_t k = 0; k < kGroup; ++k) {
-        cw[k] = ctab[c_ops + k];
-        ins[k] = first_instr(cw[k]);
+        cw[k] = op_chunk(c_ops + k);
+        ins[k] = op_instr(cw[k]);
       }
     }
     // the leaf level
     if (t > 0) leaf_words(Ig, 0, n_leaf, lane, lw);
     leaf_level(A, C, Ig, lw, n_leaf, lane, base);
     if (TRACE && trace_row) stamp(c_ops);
-    if (STAGED) {
+    if (STAGED && c_ops < c_st) {
       // the next chunk's instruction and the chunk word after it are read
       // while a chunk runs
-      uint64_t sw = rfl64(ctab[c_ops]), swn = ctab[c_ops + 1];
-      uint64_t sins = first_instr(sw);
+      uint64_t sw = op_chunk(c_ops), swn = op_chunk(c_ops + 1);
+      uint64_t sins = op_instr(sw);
       for (uint32_t c = c_ops; c < c_st; ++c) {
-        const uint64_t nins = first_instr(swn);
-        const uint64_t swnn = ctab[c + 2];
+        const uint64_t nins = op_instr(swn);
+        const uint64_t swnn = op_chunk(c + 2);
         plain_op_level_chunk(A, C, sw, sins, lane, base);
-        sw = rfl64(swn);
+        sw = swn;
         swn = swnn;
         sins = nins;
         if (TRACE && trace_row) stamp(c + 1);
       }
-    } else {
+    } else if (!STAGED) {
       for (uint32_t c = c_ops; c < c_st; c += kGroup) {
         uint64_t nw[kGroup], nins[kGroup];
 #pragma unroll
         for (uint32_t k = 0; k < kGroup; ++k) {
-          nw[k] = ctab[c + kGroup + k];
-          nins[k] = first_instr(nw[k]);
+          nw[k] = op_chunk(c + kGroup + k);
+          nins[k] = op_instr(nw[k]);
         }
 #pragma unroll
         for (uint32_t k = 0; k < kGroup; ++k) {
           if (c + k < c_st) {
-            plain_op_level_chunk(A, C, rfl64(cw[k]), ins[k], lane, base);
+            plain_op_level_chunk(A, C, cw[k], ins[k], lane, base);
             if (TRACE && trace_row) stamp(c + k + 1);
           }
         }
