@@ -1188,7 +1188,11 @@ Status encode_plain(Design& d, uint32_t max_units) {
           if (ins[j].out_narrow) flags &= ~kAllWideOut;
           d.plain_instr.push_back(ins[j].word);
         }
-        if (kk == I_ALU && (present & (present - 1)) && !(flags & (kAllNarrowOut | kAllWideOut))) flags |= kMixedChunk;
+        if (kk == I_ALU && (present & (present - 1)) && !(flags & (kAllNarrowOut | kAllWideOut))) {
+          flags |= kMixedChunk;
+          const uint32_t and_to_lt = ((1u << (I_LT + 1)) - 1) & ~((1u << I_AND) - 1);
+          if ((uint32_t)__builtin_popcount(present & and_to_lt) >= kDenseOps) flags |= kDenseChunk;
+        }
         if (kk != I_ALU) flags |= kOtherKind;
         d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), kk, present, flags));
         k = e;
@@ -1283,7 +1287,7 @@ Status encode_plain(Design& d, uint32_t max_units) {
     fprintf(stderr, "fsim compile: plain LDS units per process: p50 %u p90 %u p99 %u max %u\n", ns[ns.size() / 2],
             ns[ns.size() * 9 / 10], ns[ns.size() * 99 / 100], ns.back());
     uint64_t n_alu = 0, lanes_alu = 0, distinct = 0, all_narrow = 0, narrow_out = 0, n_memrd = 0, n_flush = 0,
-             single_op = 0;
+             single_op = 0, op_chunks[16] = {0};
     for (const PlainProc& q : d.plain_procs)
       for (uint32_t c = q.c_ops; c < q.c_st; ++c) {
         const uint64_t cw = d.plain_chunks[q.chunk_off + c];
@@ -1293,6 +1297,7 @@ Status encode_plain(Design& d, uint32_t max_units) {
           lanes_alu += ((cw >> 16) & 0xFF) + 1;
           distinct += __builtin_popcount((uint32_t)(cw >> 32) & 0xFFFF);
           if (__builtin_popcount((uint32_t)(cw >> 32) & 0xFFFF) == 1) single_op++;
+          for (int k = 0; k < 16; ++k) op_chunks[k] += (cw >> (32 + k)) & 1;
           if (fl & kAllWideOut) all_narrow++;
           if (fl & kAllNarrowOut) narrow_out++;
         } else if (kind == I_MEMRD) n_memrd++;
@@ -1305,6 +1310,9 @@ Status encode_plain(Design& d, uint32_t max_units) {
             (unsigned long long)n_memrd, (unsigned long long)n_flush);
     fprintf(stderr, "fsim compile: plain operator chunks with one opcode: %.1f%%\n",
             n_alu ? 100.0 * single_op / n_alu : 0.0);
+    fprintf(stderr, "fsim compile: plain operator chunks holding opcode k (%%):");
+    for (int k = I_AND; k <= I_MUL; ++k) fprintf(stderr, " %d:%.0f", k, n_alu ? 100.0 * op_chunks[k] / n_alu : 0.0);
+    fprintf(stderr, "\n");
     uint64_t wc = 0, wl = 0, ws = 0, ww = 0, cl = 0, cs = 0;
     for (const PlainProc& q : d.plain_procs) {
       wc += 2 * q.n_consts;

@@ -77,6 +77,31 @@ __device__ __forceinline__ uint64_t alu_select(uint32_t present, uint32_t op, ui
   return r & mask;
 }
 
+// The same for a chunk holding most opcodes: every opcode from AND to LT is
+// evaluated for every lane without a test (a test costs two scalar
+// instructions, more than evaluating the few opcodes such a chunk lacks), and
+// AND, evaluated first, needs no select.
+__device__ __forceinline__ uint64_t alu_dense(uint32_t present, uint32_t op, uint64_t mask, uint64_t a, uint64_t b,
+                                              uint64_t c) {
+  uint64_t r = a & b;
+  asm volatile("" : "+v"(r));
+  // (the empty asm keeps each select a select: no lane-divergent branch)
+#define FSIM_DENSE(OPC, EXPR) r = op == (OPC) ? (uint64_t)(EXPR) : r; asm volatile("" : "+v"(r));
+  FSIM_DENSE(I_OR, a | b)
+  FSIM_DENSE(I_XOR, a ^ b)
+  FSIM_DENSE(I_NOT, ~a)
+  FSIM_DENSE(I_ADD, a + b)
+  FSIM_DENSE(I_SUB, a - b)
+  FSIM_DENSE(I_MUX, a ? b : c)
+  FSIM_DENSE(I_SHL, b >= 64 ? 0 : (a << (b & 63)))
+  FSIM_DENSE(I_SHR, b >= 64 ? 0 : (a >> (b & 63)))
+  FSIM_DENSE(I_EQ, a == b)
+  FSIM_DENSE(I_LT, a < b)
+#undef FSIM_DENSE
+  if (present & (1u << I_MUL)) { asm volatile(""); r = op == I_MUL ? a * b : r; }
+  return r & mask;
+}
+
 static constexpr long kSpinLimit = 1l << 22;
 
 // Polls n epoch flags (one per lane, strided by 64) until every one has

@@ -146,13 +146,18 @@ __device__ __forceinline__ void plain_wide_chunk(const PlainArgs& A, PlainCycle&
 // lane computes.  Lanes past the chunk's end hold its last instruction: they
 // read the same operands and store the same value to the same place, so the
 // store needs no guard.  `cw` is the chunk word (wave-uniform).  The general
-// chunk (several opcodes, results of both sizes: nearly every chunk of a
-// large process) takes one test; the others have cheaper forms.
+// chunks (several opcodes, results of both sizes: nearly every chunk of a
+// large process) are tested for first, those holding most opcodes before
+// the rest; the others have cheaper forms.
 __device__ __forceinline__ void plain_alu_chunk(uint64_t cw, uint64_t raw, uint32_t base, uint32_t trash) {
   const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
   const uint32_t flags = (uint32_t)(cw >> 48), present = (uint32_t)(cw >> 32) & 0xFFFF;
   uint64_t a = ld_raw(base, pw_f1(lo, hi)), b = ld_raw(base, pw_f2(hi)), c = ld_raw(base, pw_f3(hi));
   asm volatile("; operands of an operator chunk ready" : "+v"(a), "+v"(b), "+v"(c));
+  if (__builtin_expect((flags & kDenseChunk) != 0, 1)) {
+    st_val(base, pw_f0(lo), alu_dense(present, pw_op(lo), pw_mask(lo), a, b, c), pw_one0(hi), trash);
+    return;
+  }
   if (__builtin_expect((flags & kMixedChunk) != 0, 1)) {
     st_val(base, pw_f0(lo), alu_select(present, pw_op(lo), pw_mask(lo), a, b, c), pw_one0(hi), trash);
     return;
