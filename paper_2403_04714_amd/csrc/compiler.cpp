@@ -1191,7 +1191,8 @@ Status encode_plain(Design& d, uint32_t max_units) {
         if (kk == I_ALU && (present & (present - 1)) && !(flags & (kAllNarrowOut | kAllWideOut))) {
           flags |= kMixedChunk;
           const uint32_t and_to_lt = ((1u << (I_LT + 1)) - 1) & ~((1u << I_AND) - 1);
-          if ((uint32_t)__builtin_popcount(present & and_to_lt) >= kDenseOps) flags |= kDenseChunk;
+          if ((uint32_t)__builtin_popcount(present & and_to_lt) >= kDenseOps && !(present & (1u << I_MUL)))
+            flags |= kDenseChunk;
         }
         if (kk != I_ALU) flags |= kOtherKind;
         d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), kk, present, flags));

@@ -77,28 +77,28 @@ __device__ __forceinline__ uint64_t alu_select(uint32_t present, uint32_t op, ui
   return r & mask;
 }
 
-// The same for a chunk holding most opcodes: every opcode from AND to LT is
+// The same for a chunk holding most opcodes and no MUL: every opcode is
 // evaluated for every lane without a test (a test costs two scalar
-// instructions, more than evaluating the few opcodes such a chunk lacks), and
-// AND, evaluated first, needs no select.
-__device__ __forceinline__ uint64_t alu_dense(uint32_t present, uint32_t op, uint64_t mask, uint64_t a, uint64_t b,
-                                              uint64_t c) {
-  uint64_t r = a & b;
-  asm volatile("" : "+v"(r));
-  // (the empty asm keeps each select a select: no lane-divergent branch)
-#define FSIM_DENSE(OPC, EXPR) r = op == (OPC) ? (uint64_t)(EXPR) : r; asm volatile("" : "+v"(r));
-  FSIM_DENSE(I_OR, a | b)
-  FSIM_DENSE(I_XOR, a ^ b)
-  FSIM_DENSE(I_NOT, ~a)
-  FSIM_DENSE(I_ADD, a + b)
-  FSIM_DENSE(I_SUB, a - b)
-  FSIM_DENSE(I_MUX, a ? b : c)
-  FSIM_DENSE(I_SHL, b >= 64 ? 0 : (a << (b & 63)))
-  FSIM_DENSE(I_SHR, b >= 64 ? 0 : (a >> (b & 63)))
-  FSIM_DENSE(I_EQ, a == b)
-  FSIM_DENSE(I_LT, a < b)
-#undef FSIM_DENSE
-  if (present & (1u << I_MUL)) { asm volatile(""); r = op == I_MUL ? a * b : r; }
+// instructions, more than evaluating the few opcodes such a chunk lacks),
+// and the lane's own result
+// is picked by a selection tree on the bits of its opcode (AND = 4 .. LT =
+// 14): ten 64-bit selects under four lane masks computed up front.
+__device__ __forceinline__ uint64_t alu_dense(uint32_t op, uint64_t mask, uint64_t a, uint64_t b, uint64_t c) {
+  const bool o0 = op & 1, o1 = op & 2, ge8 = op >= 8, ge12 = op >= 12;
+  const bool big = b >= 64;
+  const uint64_t x_and = a & b, x_or = a | b, x_xor = a ^ b, x_not = ~a;
+  const uint64_t x_add = a + b, x_sub = a - b, x_mux = a ? b : c;
+  const uint64_t x_shl = big ? 0 : a << (b & 63), x_shr = big ? 0 : a >> (b & 63);
+  const uint64_t x_eq = a == b, x_lt = a < b;
+  // (such a chunk holds no MUL: leaf 15 is never picked)
+  const uint64_t p4 = o0 ? x_or : x_and, p6 = o0 ? x_not : x_xor;
+  const uint64_t p8 = o0 ? x_sub : x_add, p10 = o0 ? x_shl : x_mux;
+  const uint64_t p12 = o0 ? x_eq : x_shr, p14 = x_lt;
+  uint64_t q4 = o1 ? p6 : p4, q8 = o1 ? p10 : p8, q12 = o1 ? p14 : p12;
+  // the empty asm has every lane compute all three before the last two
+  // selects, which would otherwise become a lane-divergent branch
+  asm volatile("" : "+v"(q4), "+v"(q8), "+v"(q12));
+  const uint64_t r = ge12 ? q12 : (ge8 ? q8 : q4);
   return r & mask;
 }
 

@@ -113,7 +113,7 @@ inline uint64_t plain_index(uint32_t w, uint64_t f0, uint64_t index, bool one0 =
 // takes one unit), kAllWideOut (every result takes two), kMixedChunk (an
 // operator chunk of several opcodes whose results take one unit in some
 // lanes and two in others), kDenseChunk (such a chunk holding at least
-// kDenseOps of the opcodes AND .. LT), kOtherKind (any chunk but an operator
+// kDenseOps of the opcodes AND .. LT and no MUL), kOtherKind (any chunk but an operator
 // chunk: the chunk word's sign bit).
 constexpr uint32_t kAllNarrowOut = 2, kAllWideOut = 4, kMixedChunk = 8, kDenseChunk = 16, kOtherKind = 0x8000;
 constexpr uint32_t kDenseOps = 7;

@@ -155,7 +155,7 @@ __device__ __forceinline__ void plain_alu_chunk(uint64_t cw, uint64_t raw, uint3
   uint64_t a = ld_raw(base, pw_f1(lo, hi)), b = ld_raw(base, pw_f2(hi)), c = ld_raw(base, pw_f3(hi));
   asm volatile("; operands of an operator chunk ready" : "+v"(a), "+v"(b), "+v"(c));
   if (__builtin_expect((flags & kDenseChunk) != 0, 1)) {
-    st_val(base, pw_f0(lo), alu_dense(present, pw_op(lo), pw_mask(lo), a, b, c), pw_one0(hi), trash);
+    st_val(base, pw_f0(lo), alu_dense(pw_op(lo), pw_mask(lo), a, b, c), pw_one0(hi), trash);
     return;
   }
   if (__builtin_expect((flags & kMixedChunk) != 0, 1)) {
@@ -206,8 +206,10 @@ __device__ __forceinline__ void plain_store64(const PlainArgs& A, PlainCycle& C,
 __device__ __forceinline__ void plain_op_level_chunk(const PlainArgs& A, PlainCycle& C, uint64_t cw, uint64_t raw,
                                                      uint32_t lane, uint32_t base) {
   // operator chunks carry no kOtherKind flag, so the common case costs one
-  // test of the chunk word's sign
-  if (__builtin_expect((int64_t)cw >= 0, 1)) plain_alu_chunk(cw, raw, base, trash_off(A));
+  // test of the chunk word's sign (taken on its high half, a scalar test)
+  uint32_t cw_hi = (uint32_t)(cw >> 32);
+  asm("" : "+s"(cw_hi));
+  if (__builtin_expect((int32_t)cw_hi >= 0, 1)) plain_alu_chunk(cw, raw, base, trash_off(A));
   else if (((uint32_t)(cw >> 24) & 0xFF) == I_MEMRD) plain_memrd(A, raw, base);
   else plain_store64(A, C, cw, raw, lane, base);
 }
