@@ -814,42 +814,55 @@ namespace {
 // bits) takes one unit, a wide one an even pair.  Released units are reused;
 // a released unit whose partner is free makes a free pair again.  Free lists
 // may hold stale entries; the unit states decide.
+//
+// An operator's result is always stored as 8 bytes: a result in one unit u
+// also writes the unit above it, u + 1, with its upper half, which is
+// garbage.  So such a result goes where u + 1 is free, and u + 1 is given to
+// no value of the same step (whose store could come before or after the
+// garbage).  Every allocation names its step; units that take garbage in a
+// step are marked with it.
 class UnitAlloc {
  public:
   // units below `base` are reserved (never handed out)
   void reset(uint32_t base) {
     st_.assign(base, kUsed);
+    g_.assign(base, 0);
     one_.clear();
     two_.clear();
   }
   uint32_t top() const { return (uint32_t)st_.size(); }
-  uint32_t take(bool wide) {
-    uint32_t u;
+  // a unit (or an even pair) for a value defined in step s; `garbage`: a
+  // one-unit value whose store also writes the unit above it
+  uint32_t take(bool wide, uint32_t s, bool garbage = false) {
+    const uint32_t m = s + 1;   // marks: 0 = none
+    uint32_t u = UINT32_MAX;
     if (!wide) {
       while (!one_.empty()) {
-        u = one_.back();
+        const uint32_t v = one_.back();
         one_.pop_back();
-        if (st_[u] == kFree) { st_[u] = kUsed; return u; }
+        if (st_[v] != kFree) continue;
+        if (g_[v] != m && (!garbage || v + 1 >= top() || st_[v + 1] == kFree)) { u = v; break; }
+        stash_.push_back(v);
       }
-      if (pop_pair(u)) {
-        st_[u] = kUsed;
-        one_.push_back(u + 1);
-        return u;
+      if (u == UINT32_MAX && pop_pair(m, u)) one_.push_back(u + 1);
+      if (u == UINT32_MAX) { grow(); u = top() - 1; }
+      st_[u] = kUsed;
+    } else {
+      if (!pop_pair(m, u)) {
+        if (top() & 1) { grow(); one_.push_back(top() - 1); }
+        grow();
+        grow();
+        u = top() - 2;
       }
-      st_.push_back(kUsed);
-      return top() - 1;
-    }
-    if (pop_pair(u)) {
       st_[u] = st_[u + 1] = kUsed;
-      return u;
     }
-    if (top() & 1) {
-      st_.push_back(kFree);
-      one_.push_back(top() - 1);
+    if (garbage) {
+      if (u + 1 >= top()) { grow(); one_.push_back(u + 1); }
+      g_[u + 1] = m;
     }
-    st_.push_back(kUsed);
-    st_.push_back(kUsed);
-    return top() - 2;
+    for (uint32_t v : stash_) one_.push_back(v);
+    stash_.clear();
+    return u;
   }
   void give(uint32_t u, bool wide) {
     st_[u] = kFree;
@@ -865,16 +878,28 @@ class UnitAlloc {
 
  private:
   enum : uint8_t { kUsed = 0, kFree = 1 };
-  bool pop_pair(uint32_t& u) {
+  void grow() {
+    st_.push_back(kFree);
+    g_.push_back(0);
+  }
+  // a free even pair neither of whose units took garbage in the step marked m
+  bool pop_pair(uint32_t m, uint32_t& u) {
     while (!two_.empty()) {
-      u = two_.back();
+      const uint32_t v = two_.back();
       two_.pop_back();
-      if (st_[u] == kFree && st_[u + 1] == kFree) return true;
+      if (st_[v] != kFree || st_[v + 1] != kFree) continue;
+      if (g_[v] != m && g_[v + 1] != m) { u = v; flush_pairs(); return true; }
+      pstash_.push_back(v);
     }
+    flush_pairs();
     return false;
   }
+  void flush_pairs() {
+    for (uint32_t v : pstash_) two_.push_back(v);
+    pstash_.clear();
+  }
   std::vector<uint8_t> st_;
-  std::vector<uint32_t> one_, two_;
+  std::vector<uint32_t> g_, one_, two_, stash_, pstash_;
 };
 
 // pending register and output stores are written out early, in a store level
@@ -1124,7 +1149,7 @@ Status encode_plain(Design& d, uint32_t max_units) {
     // whose last read comes before it
     alloc.reset(kPlainUnitBase);
     for (uint32_t x : ord)
-      if (d.op[x] == FSIM_OP_CONST) unit[x] = alloc.take(!one(x));
+      if (d.op[x] == FSIM_OP_CONST) unit[x] = alloc.take(!one(x), 0);
     by_last.clear();
     for (uint32_t x : ord)
       if (d.op[x] != FSIM_OP_CONST) by_last.push_back({lpos[x], x});
@@ -1136,7 +1161,10 @@ Status encode_plain(Design& d, uint32_t max_units) {
         const uint32_t y = by_last[rel++].second;
         alloc.give(unit[y], !one(y));
       }
-      unit[x] = alloc.take(!one(x));
+      // operators store 8 bytes (the upper half of a one-unit result is
+      // garbage); leaves and memory reads store a one-unit value's upper
+      // half to the spare unit
+      unit[x] = alloc.take(!one(x), loc[x], d.op[x] > FSIM_OP_MEMRD && one(x));
     }
     const uint32_t n = alloc.top();
     if (n > max_units || n > kMaxPlainUnits)
@@ -1181,19 +1209,14 @@ Status encode_plain(Design& d, uint32_t max_units) {
         size_t e = k;
         while (e < ins.size() && e - k < cap && ins[e].kind == kk) ++e;
         const uint32_t start = (uint32_t)d.plain_instr.size() - pp.instr_off;
-        uint32_t present = 0, flags = kAllNarrowOut | kAllWideOut;
+        uint32_t present = 0, flags = 0;
         for (size_t j = k; j < e; ++j) {
           if (kk == I_ALU) present |= 1u << (ins[j].word & 15);
-          if (!ins[j].out_narrow) flags &= ~kAllNarrowOut;
-          if (ins[j].out_narrow) flags &= ~kAllWideOut;
           d.plain_instr.push_back(ins[j].word);
         }
-        if (kk == I_ALU && (present & (present - 1)) && !(flags & (kAllNarrowOut | kAllWideOut))) {
-          flags |= kMixedChunk;
-          const uint32_t and_to_lt = ((1u << (I_LT + 1)) - 1) & ~((1u << I_AND) - 1);
-          if ((uint32_t)__builtin_popcount(present & and_to_lt) >= kDenseOps && !(present & (1u << I_MUL)))
-            flags |= kDenseChunk;
-        }
+        const uint32_t and_to_lt = ((1u << (I_LT + 1)) - 1) & ~((1u << I_AND) - 1);
+        if (kk == I_ALU && (uint32_t)__builtin_popcount(present & and_to_lt) >= kDenseOps && !(present & (1u << I_MUL)))
+          flags |= kDenseChunk;
         if (kk != I_ALU) flags |= kOtherKind;
         d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), kk, present, flags));
         k = e;
@@ -1287,8 +1310,8 @@ Status encode_plain(Design& d, uint32_t max_units) {
     std::sort(ns.begin(), ns.end());
     fprintf(stderr, "fsim compile: plain LDS units per process: p50 %u p90 %u p99 %u max %u\n", ns[ns.size() / 2],
             ns[ns.size() * 9 / 10], ns[ns.size() * 99 / 100], ns.back());
-    uint64_t n_alu = 0, lanes_alu = 0, distinct = 0, all_narrow = 0, narrow_out = 0, n_memrd = 0, n_flush = 0,
-             single_op = 0, op_chunks[16] = {0};
+    uint64_t n_alu = 0, lanes_alu = 0, distinct = 0, dense = 0, n_memrd = 0, n_flush = 0, single_op = 0,
+             op_chunks[16] = {0};
     for (const PlainProc& q : d.plain_procs)
       for (uint32_t c = q.c_ops; c < q.c_st; ++c) {
         const uint64_t cw = d.plain_chunks[q.chunk_off + c];
@@ -1299,18 +1322,15 @@ Status encode_plain(Design& d, uint32_t max_units) {
           distinct += __builtin_popcount((uint32_t)(cw >> 32) & 0xFFFF);
           if (__builtin_popcount((uint32_t)(cw >> 32) & 0xFFFF) == 1) single_op++;
           for (int k = 0; k < 16; ++k) op_chunks[k] += (cw >> (32 + k)) & 1;
-          if (fl & kAllWideOut) all_narrow++;
-          if (fl & kAllNarrowOut) narrow_out++;
+          if (fl & kDenseChunk) dense++;
         } else if (kind == I_MEMRD) n_memrd++;
         else n_flush++;
       }
-    fprintf(stderr, "fsim compile: plain operator chunks %llu: lanes/chunk %.1f, opcodes/chunk %.2f, all results in two units %.1f%%, "
-            "in one unit %.1f%%; memory-read chunks %llu, early store chunks %llu\n", (unsigned long long)n_alu,
-            n_alu ? (double)lanes_alu / n_alu : 0.0, n_alu ? (double)distinct / n_alu : 0.0,
-            n_alu ? 100.0 * all_narrow / n_alu : 0.0, n_alu ? 100.0 * narrow_out / n_alu : 0.0,
-            (unsigned long long)n_memrd, (unsigned long long)n_flush);
-    fprintf(stderr, "fsim compile: plain operator chunks with one opcode: %.1f%%\n",
-            n_alu ? 100.0 * single_op / n_alu : 0.0);
+    fprintf(stderr, "fsim compile: plain operator chunks %llu: lanes/chunk %.1f, opcodes/chunk %.2f; memory-read chunks "
+            "%llu, early store chunks %llu\n", (unsigned long long)n_alu, n_alu ? (double)lanes_alu / n_alu : 0.0,
+            n_alu ? (double)distinct / n_alu : 0.0, (unsigned long long)n_memrd, (unsigned long long)n_flush);
+    fprintf(stderr, "fsim compile: plain operator chunks with one opcode: %.1f%%, with most opcodes (dense): %.1f%%\n",
+            n_alu ? 100.0 * single_op / n_alu : 0.0, n_alu ? 100.0 * dense / n_alu : 0.0);
     fprintf(stderr, "fsim compile: plain operator chunks holding opcode k (%%):");
     for (int k = I_AND; k <= I_MUL; ++k) fprintf(stderr, " %d:%.0f", k, n_alu ? 100.0 * op_chunks[k] / n_alu : 0.0);
     fprintf(stderr, "\n");
