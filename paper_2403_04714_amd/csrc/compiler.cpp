@@ -1331,6 +1331,15 @@ Status encode_plain(Design& d, uint32_t max_units) {
             n_alu ? (double)distinct / n_alu : 0.0, (unsigned long long)n_memrd, (unsigned long long)n_flush);
     fprintf(stderr, "fsim compile: plain operator chunks with one opcode: %.1f%%, with most opcodes (dense): %.1f%%\n",
             n_alu ? 100.0 * single_op / n_alu : 0.0, n_alu ? 100.0 * dense / n_alu : 0.0);
+    {
+      std::vector<uint32_t> steps;
+      for (const PlainProc& q : d.plain_procs) steps.push_back(q.c_st - q.c_ops);
+      std::sort(steps.begin(), steps.end());
+      if (!steps.empty())
+        fprintf(stderr, "fsim compile: operator-phase chunks per process: p10 %u p50 %u p90 %u p99 %u max %u\n",
+                steps[steps.size() / 10], steps[steps.size() / 2], steps[steps.size() * 9 / 10],
+                steps[steps.size() * 99 / 100], steps.back());
+    }
     fprintf(stderr, "fsim compile: plain operator chunks holding opcode k (%%):");
     for (int k = I_AND; k <= I_MUL; ++k) fprintf(stderr, " %d:%.0f", k, n_alu ? 100.0 * op_chunks[k] / n_alu : 0.0);
     fprintf(stderr, "\n");

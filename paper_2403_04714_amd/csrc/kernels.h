@@ -12,7 +12,8 @@ namespace fsim {
 // One-wave plain kernel: the operator levels run in groups of this many
 // chunks, and the instructions of the next group are fetched when a group
 // starts, so a fetch has a whole group's time to land.  The LDS chunk table
-// holds 2 kGroup zero words past a process's last chunk.
+// has room for 2 kGroup entries past a process's last chunk (the read-ahead),
+// which repeat its last operator chunk.
 constexpr uint32_t kGroup = 2;
 
 // Words of the grid barrier's flag array for G workgroups: one epoch flag per
@@ -45,7 +46,7 @@ struct PlainArgs {
   uint32_t stage_instr;       // instructions staged in LDS
   uint32_t slot_words;        // u64 words of LDS reserved for slots
   uint32_t ctab_words;        // one-wave kernel: u64 entries of the LDS chunk table after the slots
-                              // (the most chunks of any process + 2 kGroup zero entries)
+                              // (the most chunks of any process + 2 kGroup read-ahead entries)
   uint32_t instr_words;       // instruction words staged in LDS (after the chunk table)
   uint64_t cycle0;            // absolute cycle at the first cycle of this launch
   uint32_t n_cycles;

@@ -569,18 +569,18 @@ __device__ void plain_wave_body(const PlainArgs& A) {
   }
 }
 
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_persistent(PlainArgs A) { plain_wave_body<true, true, false>(A); }
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_cycle(PlainArgs A) { plain_wave_body<false, true, false>(A); }
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_persistent_g(PlainArgs A) { plain_wave_body<true, false, false>(A); }
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_cycle_g(PlainArgs A) { plain_wave_body<false, false, false>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) plain_wave_persistent(PlainArgs A) { plain_wave_body<true, true, false>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) plain_wave_cycle(PlainArgs A) { plain_wave_body<false, true, false>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) plain_wave_persistent_g(PlainArgs A) { plain_wave_body<true, false, false>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) plain_wave_cycle_g(PlainArgs A) { plain_wave_body<false, false, false>(A); }
 // the same with phase timestamps (a sim with tracing enabled): the untraced
 // kernels carry no per-chunk test for it
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_persistent_trace(PlainArgs A) { plain_wave_body<true, true, true>(A); }
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_cycle_trace(PlainArgs A) { plain_wave_body<false, true, true>(A); }
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_persistent_g_trace(PlainArgs A) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) plain_wave_persistent_trace(PlainArgs A) { plain_wave_body<true, true, true>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) plain_wave_cycle_trace(PlainArgs A) { plain_wave_body<false, true, true>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) plain_wave_persistent_g_trace(PlainArgs A) {
   plain_wave_body<true, false, true>(A);
 }
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) plain_wave_cycle_g_trace(PlainArgs A) { plain_wave_body<false, false, true>(A); }
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) plain_wave_cycle_g_trace(PlainArgs A) { plain_wave_body<false, false, true>(A); }
 
 __global__ void __launch_bounds__(1024) plain_persistent(PlainArgs A) { plain_body<true, true>(A); }
 __global__ void __launch_bounds__(1024) plain_cycle(PlainArgs A) { plain_body<false, true>(A); }
