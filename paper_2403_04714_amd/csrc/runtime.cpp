@@ -82,6 +82,9 @@ static constexpr uint32_t kDefaultLds = 160 * 1024;
 static constexpr uint32_t kStaticLds = 1024;     // abort flag, reduction scratch
 // u64 entries of the one-wave kernel's LDS chunk table: every chunk of the
 // largest process and the zero entries of the two groups it reads ahead
+// order each XCD's range of the plain process table longest first
+constexpr bool kLongestFirst = true;
+
 static uint32_t wave_ctab_words(const fsim_design* d) { return d->max_chunks + 2 * fsim::kGroup; }
 
 template <class T>
@@ -168,7 +171,23 @@ extern "C" int fsim_design_load(fsim_ctx* ctx, const fsim_netlist* nl, const fsi
     if ((rc = upload(dz->instr, d.plain_instr, st))) return rc;
     if ((rc = upload(dz->levels, d.plain_levels, st))) return rc;
     if ((rc = upload(dz->chunks, d.plain_chunks, st))) return rc;
-    if ((rc = upload(dz->procs, d.plain_procs, st))) return rc;
+    {
+      // dispatch order: workgroup b runs table entry process_of(b, P), so
+      // XCD x runs one contiguous range of the table, in order of
+      // dispatch; each range lists its longest processes (most operator
+      // chunks) first, so the workgroups that start last have the least to
+      // do.  Processes are independent within a cycle: any order is valid.
+      std::vector<fsim::PlainProc> tab(d.plain_procs);
+      const uint32_t P = (uint32_t)tab.size(), q = P / 8, r = P % 8;
+      for (uint32_t x = 0, lo = 0; kLongestFirst && x < 8; ++x) {
+        const uint32_t hi = lo + q + (x < r ? 1 : 0);
+        std::stable_sort(tab.begin() + lo, tab.begin() + hi, [](const fsim::PlainProc& a, const fsim::PlainProc& b) {
+          return a.c_st - a.c_ops > b.c_st - b.c_ops;
+        });
+        lo = hi;
+      }
+      if ((rc = upload(dz->procs, tab, st))) return rc;
+    }
     std::vector<uint64_t> moff(d.mem_off.begin(), d.mem_off.end() - (d.M ? 1 : 0));
     if (d.M == 0) moff.clear();
     if ((rc = upload(dz->mem_off, moff, st))) return rc;
