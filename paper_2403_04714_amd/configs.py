@@ -70,13 +70,13 @@ SOC48_PLAIN = Plain("soc48", F.PACK_HYPER, 4096, stage=F.STAGE_GLOBAL)
 # the 48-tile SoC, 64 instances
 SOC48_BATCHED = Batched("soc48", 64, F.PACK_HYPER, 32768)
 # the single core, one instance
-CORE_PLAIN = Plain("core", F.PACK_HYPER, 2048, stage=F.STAGE_LDS)
+CORE_PLAIN = Plain("core", F.PACK_HYPER, 2048, stage=F.STAGE_GLOBAL)
 # the single core, 1024 instances
 CORE_BATCHED = Batched("core", 1024, F.PACK_HYPER, 4096)
 # the 8-tile SoC, one instance and 256 instances
 SOC8_PLAIN = Plain("soc8", F.PACK_HYPER, 4096, stage=F.STAGE_GLOBAL)
 SOC8_BATCHED = Batched("soc8", 256, F.PACK_HYPER, 16384)
 # the single core with clock domains, one instance
-CORE_CLOCKS_PLAIN = Plain("core_clocks", F.PACK_HYPER, 2048, stage=F.STAGE_LDS)
+CORE_CLOCKS_PLAIN = Plain("core_clocks", F.PACK_HYPER, 2048, stage=F.STAGE_GLOBAL)
 # served designs (batched form inside the server)
 SERVED = (("core", F.PACK_HYPER, 2048), ("soc8", F.PACK_HYPER, 16384))

@@ -1215,8 +1215,11 @@ Status encode_plain(Design& d, uint32_t max_units) {
           d.plain_instr.push_back(ins[j].word);
         }
         const uint32_t and_to_lt = ((1u << (I_LT + 1)) - 1) & ~((1u << I_AND) - 1);
-        if (kk == I_ALU && (uint32_t)__builtin_popcount(present & and_to_lt) >= kDenseOps && !(present & (1u << I_MUL)))
-          flags |= kDenseChunk;
+        const uint32_t n_tree = (uint32_t)__builtin_popcount(present & and_to_lt);
+        if (kk == I_ALU && !(present & (1u << I_MUL))) {
+          if (n_tree >= kDenseOps) flags |= kDenseChunk;
+          if (n_tree >= kDenseOpsLow) flags |= kDenseLow;
+        }
         if (kk != I_ALU) flags |= kOtherKind;
         d.plain_chunks.push_back(make_chunk(start, (uint32_t)(e - k), kk, present, flags));
         k = e;

@@ -53,6 +53,7 @@ struct PlainArgs {
   uint32_t epoch0;            // barrier epoch before this launch
   const uint64_t* cycle_ptr;  // graph mode: absolute base cycle in device memory
   uint32_t single_wave;       // 64-thread workgroups: the one-wave kernel
+  uint32_t dense_flag;        // the chunk flag that selects the opcode-bit tree (kDenseChunk or kDenseLow)
 };
 
 // Batched form: one wave per (process, tile of 64 instances).  State is kept

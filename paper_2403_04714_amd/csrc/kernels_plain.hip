@@ -145,17 +145,18 @@ __device__ __forceinline__ void plain_wide_chunk(const PlainArgs& A, PlainCycle&
 // An operator chunk: one instruction per lane, every operand read before any
 // lane computes.  Lanes past the chunk's end hold its last instruction: they
 // read the same operands and store the same value to the same place, so the
-// store needs no guard.  `cw` is the chunk word (wave-uniform).  Every
+// store needs no guard.  `cw` is the chunk word (wave-uniform); `dense_flag`
+// the chunk flag that selects the opcode-bit tree for this launch.  Every
 // result is stored as 8 bytes: a one-unit result's upper half lands on the
 // unit above it, which the encoder keeps free at that step.  Chunks holding
 // most opcodes are tested for first (nearly every chunk of a large process).
-__device__ __forceinline__ void plain_alu_chunk(uint64_t cw, uint64_t raw, uint32_t base) {
+__device__ __forceinline__ void plain_alu_chunk(uint64_t cw, uint64_t raw, uint32_t base, uint32_t dense_flag) {
   const uint32_t lo = (uint32_t)raw, hi = (uint32_t)(raw >> 32);
   const uint32_t flags = (uint32_t)(cw >> 48), present = (uint32_t)(cw >> 32) & 0xFFFF;
   uint64_t a = ld_raw(base, pw_f1(lo, hi)), b = ld_raw(base, pw_f2(hi)), c = ld_raw(base, pw_f3(hi));
   asm volatile("; operands of an operator chunk ready" : "+v"(a), "+v"(b), "+v"(c));
   uint64_t r;
-  if (__builtin_expect((flags & kDenseChunk) != 0, 1)) r = alu_dense(pw_op(lo), pw_mask(lo), a, b, c);
+  if (__builtin_expect((flags & dense_flag) != 0, 1)) r = alu_dense(pw_op(lo), pw_mask(lo), a, b, c);
   else if ((present & (present - 1)) == 0) r = alu_single(__builtin_ctz(present | (1u << 31)), pw_mask(lo), a, b, c);
   else r = alu_select(present, pw_op(lo), pw_mask(lo), a, b, c);
   lds_u32_t* const d = lds32(base + pw_f0(lo));
@@ -203,7 +204,7 @@ __device__ __forceinline__ void plain_op_level_chunk(const PlainArgs& A, PlainCy
   // test of the chunk word's sign (taken on its high half, a scalar test)
   uint32_t cw_hi = (uint32_t)(cw >> 32);
   asm("" : "+s"(cw_hi));
-  if (__builtin_expect((int32_t)cw_hi >= 0, 1)) plain_alu_chunk(cw, raw, base);
+  if (__builtin_expect((int32_t)cw_hi >= 0, 1)) plain_alu_chunk(cw, raw, base, A.dense_flag);
   else if (((uint32_t)(cw >> 24) & 0xFF) == I_MEMRD) plain_memrd(A, raw, base);
   else plain_store64(A, C, cw, raw, lane, base);
 }
@@ -212,7 +213,7 @@ __device__ __forceinline__ void plain_op_level_chunk(const PlainArgs& A, PlainCy
 __device__ __forceinline__ void plain_level_chunk(const PlainArgs& A, PlainCycle& C, const uint64_t* Is, uint64_t cw,
                                                   uint64_t raw, uint32_t lane, uint32_t base) {
   const uint32_t kind = (uint32_t)(cw >> 24) & 0xFF;
-  if (kind == I_ALU) plain_alu_chunk(cw, raw, base);
+  if (kind == I_ALU) plain_alu_chunk(cw, raw, base, A.dense_flag);
   else if (kind == I_MEMRD) plain_memrd(A, raw, base);
   else plain_wide_chunk(A, C, Is, cw, raw, lane, base);
 }
