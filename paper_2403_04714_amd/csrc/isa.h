@@ -115,7 +115,7 @@ inline uint64_t plain_index(uint32_t w, uint64_t f0, uint64_t index, bool one0 =
 // the branch-free tree's shorter latency wins earlier), kOtherKind (any
 // chunk but an operator chunk: the chunk word's sign bit).
 constexpr uint32_t kDenseChunk = 16, kDenseLow = 32, kOtherKind = 0x8000;
-constexpr uint32_t kDenseOps = 7, kDenseOpsLow = 4;
+constexpr uint32_t kDenseOps = 7, kDenseOpsLow = 2;
 inline uint64_t make_chunk(uint32_t start, uint32_t count, uint32_t kind, uint32_t present = 0, uint32_t flags = 0) {
   return start | ((uint64_t)(count - 1) << 16) | ((uint64_t)kind << 24) | ((uint64_t)present << 32) |
          ((uint64_t)flags << 48);

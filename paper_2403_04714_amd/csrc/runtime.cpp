@@ -573,7 +573,7 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   a.cycle_ptr = nullptr;
   // with at most two waves per SIMD (one-wave workgroups over 4 SIMDs per
   // CU) each wave's latency sets the pace, and the branch-free tree pays
-  // from four opcodes on; with more waves, vector issue is shared and the
+  // from two opcodes on; with more waves, vector issue is shared and the
   // tree pays from seven
   const uint64_t waves = (uint64_t)s->G * ((s->threads + 63) / 64);
   a.dense_flag = waves <= 8ull * dd->ctx->n_cus ? fsim::kDenseLow : fsim::kDenseChunk;
