@@ -51,6 +51,8 @@ extern "C" {
 #define FSIM_E_DEVICE       -6   /* HIP runtime or kernel error               */
 #define FSIM_E_STATE        -7   /* poisoned sim, or object in the wrong state*/
 #define FSIM_E_BUSY         -8   /* server queue full                         */
+#define FSIM_E_INTERNAL     -9   /* a self-check of the compiler failed       */
+                                 /* (environment FSIM_CHECK_UNITS=1)          */
 
 /* Text of the calling thread's last failure; valid until its next call. */
 const char* fsim_last_error(void);

@@ -50,9 +50,10 @@ static inline int arity(uint8_t op) {
   }
 }
 
-static std::string fmt(const char* f, unsigned long long a = 0, unsigned long long b = 0) {
+static std::string fmt(const char* f, unsigned long long a = 0, unsigned long long b = 0, unsigned long long c = 0,
+                       unsigned long long e = 0) {
   char buf[256];
-  snprintf(buf, sizeof buf, f, a, b);
+  snprintf(buf, sizeof buf, f, a, b, c, e);
   return buf;
 }
 
@@ -1058,6 +1059,7 @@ Status encode_plain(Design& d, uint32_t max_units) {
   std::vector<std::pair<uint32_t, uint32_t>> by_last;
   UnitAlloc alloc;
   auto narrow = [&](uint32_t x) { return d.width[x] <= 32; };
+  const bool check_units = getenv("FSIM_CHECK_UNITS") && atoi(getenv("FSIM_CHECK_UNITS")) != 0;
   for (uint32_t p = 0; p < d.P; ++p) {
     const uint32_t lo = d.proc_off[p], hi = d.proc_off[p + 1];
     // ---- local levels: 0 holds the leaves and constants, 1..K the steps of
@@ -1167,6 +1169,37 @@ Status encode_plain(Design& d, uint32_t max_units) {
       unit[x] = alloc.take(!one(x), loc[x], d.op[x] > FSIM_OP_MEMRD && one(x));
     }
     const uint32_t n = alloc.top();
+    if (check_units) {
+      // the allocation's invariants, checked from the definition: units are
+      // held from a value's definition (position 2 loc; constants from the
+      // start) to its last read; (1) no two values hold a unit at a common
+      // position; (2) the unit above a one-unit operator result, which its
+      // 8-byte store overwrites at its step, is held by no other value then
+      struct Iv { uint32_t from, to, x; };
+      std::vector<std::vector<Iv>> held(n + 2);
+      for (uint32_t x : ord) {
+        const uint32_t u = unit[x];
+        const bool c = d.op[x] == FSIM_OP_CONST;
+        const uint32_t from = c ? 0 : 2 * loc[x], to = c ? UINT32_MAX : std::max(lpos[x], from);
+        for (uint32_t k = 0; k < (one(x) ? 1u : 2u); ++k) held[u + k].push_back({from, to, x});
+      }
+      for (uint32_t u = 0; u < n; ++u)
+        for (size_t i = 0; i < held[u].size(); ++i)
+          for (size_t j = i + 1; j < held[u].size(); ++j) {
+            const Iv &a = held[u][i], &b = held[u][j];
+            if (a.from <= b.to && b.from <= a.to)
+              return Status::err(FSIM_E_INTERNAL, fmt("process %llu: nodes %llu and %llu share LDS unit %llu while "
+                                                      "both are live", p, a.x, b.x, u));
+          }
+      for (uint32_t x : ord) {
+        if (d.op[x] <= FSIM_OP_MEMRD || !one(x)) continue;
+        const uint32_t at = 2 * loc[x];
+        for (const Iv& b : held[unit[x] + 1])
+          if (b.x != x && b.from <= at && at <= b.to)
+            return Status::err(FSIM_E_INTERNAL, fmt("process %llu: the 8-byte store of node %llu overwrites node "
+                                                    "%llu, live in unit %llu", p, x, b.x, unit[x] + 1));
+      }
+    }
     if (n > max_units || n > kMaxPlainUnits)
       return Status::err(FSIM_E_CAPACITY,
                          fmt("process %llu needs %llu LDS units of live values; use more processes", p, n));

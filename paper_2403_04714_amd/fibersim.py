@@ -19,8 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfibersim.so")
 
 OK = 0
-E_ARG, E_NETLIST, E_COMB_LOOP, E_UNSUPPORTED, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY = \
-    -1, -2, -3, -4, -5, -6, -7, -8
+E_ARG, E_NETLIST, E_COMB_LOOP, E_UNSUPPORTED, E_CAPACITY, E_DEVICE, E_STATE, E_BUSY, E_INTERNAL = \
+    -1, -2, -3, -4, -5, -6, -7, -8, -9
 PACK_SLB, PACK_FIBERS, PACK_SINGLE, PACK_HYPER = 0, 1, 2, 3
 LAUNCH_AUTO, LAUNCH_PERSISTENT, LAUNCH_PER_CYCLE, LAUNCH_GRAPH = 0, 1, 2, 3
 FORM_AUTO, FORM_BATCHED, FORM_PLAIN = 0, 1, 2

@@ -387,3 +387,22 @@ def test_plain_slots_follow_liveness():
     stp, off, nodes = d.partition()
     regs_per_proc = np.bincount(stp[: nl.n_regs], minlength=info["n_processes"])
     assert regs_per_proc.max() <= info["plain_max_slots"] < info["max_process_nodes"]
+
+
+@pytest.mark.parametrize("make,pack,target", [
+    (lambda: g.gen_tiny(3), F.PACK_SLB, 4),
+    (lambda: g.gen_tiny(11), F.PACK_HYPER, 9),
+    (lambda: g.workload("core"), F.PACK_HYPER, 2048),
+    (lambda: g.workload("core"), F.PACK_SLB, 512),
+    (lambda: g.workload("core_clocks"), F.PACK_HYPER, 2048),
+    (lambda: g.workload("soc8"), F.PACK_HYPER, 4096),
+])
+def test_plain_unit_allocation_self_check(monkeypatch, make, pack, target):
+    """The plain encoder's LDS units, checked against its own liveness: no
+    two values hold a unit at a common position, and the unit above a
+    one-unit operator result (which the result's 8-byte store overwrites at
+    its step) holds no live value then.  The library checks this itself
+    when FSIM_CHECK_UNITS is set and fails the compile with E_INTERNAL."""
+    monkeypatch.setenv("FSIM_CHECK_UNITS", "1")
+    d = host_design(make(), pack=pack, target_processes=target)
+    assert d.info()["plain_max_slots"] > 0
