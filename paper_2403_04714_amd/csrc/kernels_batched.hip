@@ -48,8 +48,7 @@ __device__ __forceinline__ uint64_t lread(const char* base, uint32_t cls, uint32
 // Store a per-lane value into a slot of class cls (never a constant).
 __device__ __forceinline__ void lwrite(char* base, uint32_t cls, uint32_t off, uint32_t lane, uint64_t v) {
   if (cls == C_B) {
-    const uint64_t m = __ballot(v & 1);
-    if (lane == 0) *reinterpret_cast<uint64_t*>(base + off) = m;
+    *reinterpret_cast<uint64_t*>(base + off) = __ballot(v & 1);   // the same mask from every lane
   } else if (cls == C_W) {
     reinterpret_cast<uint32_t*>(base + off)[lane] = (uint32_t)v;
   } else {
@@ -138,8 +137,8 @@ __device__ __forceinline__ void vstore(char* base, uint32_t cls, uint32_t off, u
   } else if (cls == C_W) {
     *reinterpret_cast<uint32_t*>(base + off + lane4) = (uint32_t)v;
   } else {
-    const uint64_t m = __ballot(v & 1);
-    if (lane == 0) *reinterpret_cast<uint64_t*>(base + off) = m;
+    // every lane stores the same mask: no change of the execution mask
+    *reinterpret_cast<uint64_t*>(base + off) = __ballot(v & 1);
   }
 }
 
@@ -242,10 +241,9 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
 #pragma unroll
           for (uint32_t t = 0; t < TW; ++t) r[t] = (ma[t] & mb[t]) | (~ma[t] & mread(base[t], z >> 16));   // MUX
         }
-        if (lane == 0) {
+        // every lane stores the same mask: no change of the execution mask
 #pragma unroll
-          for (uint32_t t = 0; t < TW; ++t) *reinterpret_cast<uint64_t*>(base[t] + (y & 0xFFFF)) = r[t];
-        }
+        for (uint32_t t = 0; t < TW; ++t) *reinterpret_cast<uint64_t*>(base[t] + (y & 0xFFFF)) = r[t];
       } else if (op >= I_AND && op <= I_MUL) {
         // one value per lane: every operand load is issued before the first
         // is used, then 1-bit operands are taken out of their masks
@@ -319,7 +317,7 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
             for (uint32_t t = 0; t < TW; ++t) {
               if (op == K_LDREG_D) *reinterpret_cast<uint64_t*>(base[t] + o + lane8) = v[k][t];
               else if (op == K_LDREG_W) *reinterpret_cast<uint32_t*>(base[t] + o + lane4) = (uint32_t)v[k][t];
-              else if (lane == 0) *reinterpret_cast<uint64_t*>(base[t] + o) = v[k][t];
+              else *reinterpret_cast<uint64_t*>(base[t] + o) = v[k][t];   // the same mask from every lane
             }
           }
         }
@@ -369,11 +367,11 @@ __device__ __forceinline__ void batched_body(const BatchArgs& A, uint32_t block,
               if ((xk & 0xFF) == I_LDREG) {
                 if (cak == C_B) {
                   if (cdk == C_B) {
-                    // the mask is wave-uniform: taken into scalar registers here,
-                    // outside the one-lane store
+                    // the mask is wave-uniform: taken into scalar registers,
+                    // and every lane stores the same mask
                     const uint64_t m = ((uint64_t)rlane((uint32_t)(val[k][t] >> 32), 0) << 32) |
                                        rlane((uint32_t)val[k][t], 0);
-                    if (lane == 0) *reinterpret_cast<uint64_t*>(base[t] + dk) = m;
+                    *reinterpret_cast<uint64_t*>(base[t] + dk) = m;
                   } else {
                     lwrite(base[t], cdk, dk, lane, (val[k][t] >> lane) & 1);
                   }
