@@ -577,6 +577,8 @@ static fsim::PlainArgs plain_args(fsim_sim* s) {
   // tree pays from seven
   const uint64_t waves = (uint64_t)s->G * ((s->threads + 63) / 64);
   a.dense_flag = waves <= 8ull * dd->ctx->n_cus ? fsim::kDenseLow : fsim::kDenseChunk;
+  // tests run either threshold on any design: FSIM_TREE=low or high
+  if (const char* e = getenv("FSIM_TREE")) a.dense_flag = e[0] == 'l' ? fsim::kDenseLow : fsim::kDenseChunk;
   return a;
 }
 

@@ -114,10 +114,15 @@ def reference(nl, seed, cycles):
     return ref, ref.step(cycles, digests=True)
 
 
+@pytest.mark.parametrize("tree", ["low", "high"])
 @pytest.mark.parametrize("pack", [0, 1, 2, 3])
-def test_plain_operand_forms(F, ctx, pack):
+def test_plain_operand_forms(F, ctx, pack, tree, monkeypatch):
+    """Both opcode-tree thresholds (the one for few waves per SIMD and the
+    one for many), whatever the design's size, so every operator chunk runs
+    the tree, the per-opcode tests and the single-opcode form."""
+    monkeypatch.setenv("FSIM_TREE", tree)
     nl = operand_forms()
-    print(f"case operand_forms: plain pack={pack}", flush=True)
+    print(f"case operand_forms: plain pack={pack} tree={tree}", flush=True)
     d = F.Design(ctx, nl, pack=pack)
     s = F.Sim(d, 1, seed=SEED, wg_threads=64)
     s.enable_digest(CYCLES)
