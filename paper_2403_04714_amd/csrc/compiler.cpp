@@ -1273,7 +1273,7 @@ Status encode_plain(Design& d, uint32_t max_units) {
     // level 0: register and input loads (always present, possibly empty)
     for (uint32_t i = lv_start[0]; i < lv_start[1]; ++i) {
       const uint32_t x = ord[i];
-      // field 0's narrow flag gives the destination's size (an input's width
+      // the sign bit gives the destination's size (an input's width
       // also folds in the port's own width)
       if (d.op[x] == FSIM_OP_REG)
         ins.push_back({plain_index(d.width[x], unit[x], d.imm[x], one(x)), I_LDREG, one(x)});

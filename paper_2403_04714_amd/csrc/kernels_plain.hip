@@ -1,9 +1,10 @@
 // kernels_plain.hip -- gfx950 device code of libfibersim: the plain form.
 //
 // Plain form (one instance): a workgroup runs one process (a set of fibers,
-// Parendi Sec. 3.2).  Per simulated cycle it evaluates the process level by
-// level -- lanes take the independent operators of a level in parallel,
-// values live in LDS slots -- stores the next values of the registers it owns
+// Parendi Sec. 3.2).  Per simulated cycle it evaluates the process step by
+// step -- a step's operators are independent, one per lane (the compiler's
+// list schedule), and values live in 4-byte LDS units -- stores the next
+// values of the registers it owns
 // into the "next" half of a double-buffered state array, commits memory
 // writes after every read, and then crosses a grid-wide barrier.  The
 // barrier plus the buffer swap is the exchange of Sec. 3.2: the current and
