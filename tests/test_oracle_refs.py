@@ -28,7 +28,7 @@ def nets():
 
 def test_every_record_matches_the_generator(refs, nets):
     assert set(refs) >= {"core_x1_100k", "core_x1024_100", "soc8_x1_2000", "soc8_x256_100",
-                         "soc8_sample_1000", "soc48_x1_500", "soc48_x64_64", "soc48_sample_300"}
+                         "soc8_sample_1000", "soc48_x1_500", "soc48_x64_1000"}
     for name, rec in refs.items():
         R.check_netlist(rec, nets[rec["workload"]])
         assert rec["seed_base"] == g.STIM_SEED_BASE
@@ -46,7 +46,7 @@ def test_clear_digests_are_the_oracles(refs, nets):
             d = sim.step(len(r["head"]), digests=True)
             assert [f"{int(x):016x}" for x in d] == r["head"], (name, i)
             checked += 1
-    assert checked >= 8
+    assert checked >= 7       # every record of at most 4 instances keeps its first digests
 
 
 def test_first_block_of_the_long_run_recomputed(refs, nets):
