@@ -38,7 +38,7 @@ RECORDS = {
     "core_x1024_100": ("core", list(range(1024)), 100, 100, False),
     # the 8-tile SoC: one instance, every instance of x256, a longer sample
     "soc8_x1_2000": ("soc8", [0], 2000, 100, True),
-    "soc8_x256_100": ("soc8", list(range(256)), 100, 100, False),
+    "soc8_x256_500": ("soc8", list(range(256)), 500, 100, False),
     "soc8_sample_1000": ("soc8", [0, 1, 127, 255], 1000, 100, True),
     # the 48-tile SoC: one instance; every instance of x64, memories included
     "soc48_x1_500": ("soc48", [0], 500, 100, True),

@@ -7,7 +7,7 @@ by tests/golden/make_oracle_refs.py:
 - plain, one instance: every cycle's digest over 2,000 cycles, then the
   registers, outputs and every memory;
 - batched, 256 instances: every instance's per-cycle digests, registers and
-  outputs over the first 100 cycles, then instances {0, 1, 127, 255} over
+  outputs over the first 500 cycles, then instances {0, 1, 127, 255} over
   1,000 cycles with every memory;
 - and, against the oracle run live, the plain form under bottom-up SLB
   packing at 4096 processes (the other packing policy) for 300 cycles."""
@@ -82,7 +82,7 @@ def test_soc8_plain_slb_live_oracle(F, soc8):
 def test_soc8_batched_256_config(F, soc8):
     from paper_2403_04714_amd import configs
     nl, ctx = soc8
-    first, sample = R.load("soc8_x256_100"), R.load("soc8_sample_1000")
+    first, sample = R.load("soc8_x256_500"), R.load("soc8_sample_1000")
     R.check_netlist(first, nl)
     cfg = configs.SOC8_BATCHED
     d = cfg.design(ctx, nl)
