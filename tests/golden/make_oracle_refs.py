@@ -35,7 +35,7 @@ RECORDS = {
     # the single core's full 100,000-cycle run
     "core_x1_100k": ("core", [0], 100_000, 1000, True),
     # every instance of the single core batched x1024
-    "core_x1024_100": ("core", list(range(1024)), 100, 100, False),
+    "core_x1024_1000": ("core", list(range(1024)), 1000, 100, False),
     # the 8-tile SoC: one instance, every instance of x256, a longer sample
     "soc8_x1_2000": ("soc8", [0], 2000, 100, True),
     "soc8_x256_500": ("soc8", list(range(256)), 500, 100, False),

@@ -6,7 +6,7 @@ by tests/golden/make_oracle_refs.py:
 - plain, one instance: every cycle's digest over all 100,000 cycles of the
   configuration, then the registers, outputs and both memories;
 - batched, 1024 instances: every instance's per-cycle digests, registers and
-  outputs over 100 cycles."""
+  outputs over 1,000 cycles."""
 import pytest
 
 import oracle_refs as R
@@ -55,7 +55,7 @@ def test_core_plain_config_100k_cycles(F, core):
 def test_core_batched_1024_config(F, core):
     from paper_2403_04714_amd import configs
     nl, ctx = core
-    rec = R.load("core_x1024_100")
+    rec = R.load("core_x1024_1000")
     R.check_netlist(rec, nl)
     cfg = configs.CORE_BATCHED
     d = cfg.design(ctx, nl)

@@ -27,7 +27,7 @@ def nets():
 
 
 def test_every_record_matches_the_generator(refs, nets):
-    assert set(refs) >= {"core_x1_100k", "core_x1024_100", "soc8_x1_2000", "soc8_x256_500",
+    assert set(refs) >= {"core_x1_100k", "core_x1024_1000", "soc8_x1_2000", "soc8_x256_500",
                          "soc8_sample_1000", "soc48_x1_500", "soc48_x64_1000"}
     for name, rec in refs.items():
         R.check_netlist(rec, nets[rec["workload"]])
